@@ -1,0 +1,78 @@
+"""Seeded input generators: determinism and the statistics they must have."""
+import math
+
+import numpy as np
+
+from paper_0909_0879_amd import ics
+
+
+def test_plummer_deterministic_and_com():
+    m1, x1, v1 = ics.plummer(1024, 1)
+    m2, x2, v2 = ics.plummer(1024, 1)
+    assert np.array_equal(x1, x2) and np.array_equal(v1, v2)
+    assert m1.sum() == 1.0 or abs(m1.sum() - 1.0) < 1e-15
+    np.testing.assert_allclose((m1[:, None] * x1).sum(0), 0.0, atol=1e-15)
+    np.testing.assert_allclose((m1[:, None] * v1).sum(0), 0.0, atol=1e-15)
+    _, x3, _ = ics.plummer(1024, 2)
+    assert not np.array_equal(x1, x3)
+
+
+def test_plummer_mass_profile():
+    # Henon-scaled Plummer: M(<r) = r^3 / (r^2 + b^2)^{3/2}
+    m, x, v = ics.plummer(50000, 3)
+    r = np.sort(np.linalg.norm(x, axis=1))
+    b = ics.PLUMMER_HENON_B
+    for q in (0.1, 0.25, 0.5, 0.75, 0.9):
+        rq = r[int(q * len(r))]
+        assert abs(rq ** 3 / (rq * rq + b * b) ** 1.5 - q) < 0.01
+
+
+def test_plummer_kinetic_energy():
+    m, x, v = ics.plummer(50000, 4)
+    K = 0.5 * (m * (v * v).sum(1)).sum()
+    assert abs(K - 0.25) < 0.005
+
+
+def test_salpeter_mean_and_range():
+    n = 200000
+    u = ics.salpeter_masses(n, 3)
+    assert abs(u.sum() - 1.0) < 1e-12
+    raw = u * n * ics.salpeter_mean()    # undo the normalisation approximately
+    assert abs(raw.mean() / ics.salpeter_mean() - 1.0) < 1e-12
+    # ratio of extremes bounded by the spectrum range 0.1 .. 100
+    assert u.max() / u.min() <= 1000.0 * (1 + 1e-12)
+    # sample mean before normalisation ~ closed form <m> ~ 0.351
+    rng = np.random.Generator(np.random.PCG64(3))
+    w = rng.uniform(0.0, 1.0, n)
+    p = 1.0 - ics.SALPETER_ALPHA
+    mm = (0.1 ** p + w * (100.0 ** p - 0.1 ** p)) ** (1.0 / p)
+    assert abs(mm.mean() / ics.salpeter_mean() - 1.0) < 0.02
+    assert abs(ics.salpeter_mean() - 0.3514) < 1e-3
+
+
+def test_king_profile_self_consistent():
+    p = ics.king_profile(7.0)
+    # concentration of a W0 = 7 King model: log10(r_t / r_0) ~ 1.53
+    assert abs(math.log10(p["r_t"]) - 1.53) < 0.02
+    assert np.all(np.diff(p["M"]) >= 0)
+    assert p["W"][0] == 7.0 and p["W"][-1] == 0.0
+
+
+def test_king_sample_henon_units():
+    m, x, v = ics.king(20000, 7.0, 4)
+    K = 0.5 * (m * (v * v).sum(1)).sum()
+    assert abs(K - 0.25) < 0.01
+    np.testing.assert_allclose((m[:, None] * x).sum(0), 0.0, atol=1e-14)
+
+
+def test_ensemble_sizes_and_layout():
+    sizes = ics.ensemble_sizes(256, 256, 16384, 5000)
+    assert sizes.min() >= 256 and sizes.max() <= 16384
+    assert 0.8e6 < sizes.sum() < 1.2e6
+    m, x, v, off = ics.ensemble(4, sizes=[300, 512, 1000, 257], seed=5000)
+    assert list(off) == [0, 300, 812, 1812, 2069]
+    for c in range(4):
+        sl = slice(off[c], off[c + 1])
+        assert abs(m[sl].sum() - 1.0) < 1e-12
+        mc, xc, vc = ics.plummer(int(off[c + 1] - off[c]), 5000 + c)
+        assert np.array_equal(xc, x[sl])
