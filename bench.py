@@ -1,0 +1,153 @@
+"""Benchmark of the direct N-body hot path on one MI355X.
+
+Workload: King model W0 = 7, N = 1,048,576 equal-mass particles in Henon
+units, eps = 1e-4 (seeded synthetic input).  One benchmark step is one
+Hermite-4 block step of the whole hot path with every particle active:
+scheduler and compaction, prediction of all particles while they are
+staged through LDS, the O(N^2) acceleration + jerk evaluation, corrector,
+Aarseth step choice and level bookkeeping (all particles held on one level
+so that every step is a full N x N evaluation).  Interactions per step are
+N^2 kernel slots.  The mixed-precision path is the headline value; the
+plain FP64 path is timed the same way beside it.
+
+Prints ONE JSON line.  Extra keys: "fp64" (the FP64 path's throughput),
+"mixed_over_fp64", "roofline" (force kernel, HIP-event timed), "cpu_baseline"
+(the CPU oracle on a bounded sample of the same evaluation).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pairwise interactions/s (acc+jerk), mixed vs FP64 path at ≤1e-6 rel force err"
+FLOPS_PER_INTERACTION = 41          # algorithmic count, rsqrt counted as one
+FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published dense FP32 vector peak
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+N_DEFAULT = 1 << 20
+LEVEL = 10                          # every particle on step 2^-10
+EPS = 1e-4
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=N_DEFAULT, help="particles (default 2^20)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def time_path(binding, torch, m, x, v, precision, steps, warmup):
+    """Run warmup + timed block steps; return wall ms/step and force-kernel
+    event ms per launch."""
+    g = binding.NBody(m, x, v, eps=EPS, precision=precision, eta=0.01, eta_start=0.01,
+                      level_min=LEVEL, level_max=LEVEL)
+    dt = 2.0 ** -LEVEL
+    t = 0.0
+    for _ in range(warmup):
+        t += dt
+        g.step(t)
+    g.profile(True)
+    g.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    inter = 0
+    for _ in range(steps):
+        t += dt
+        _, ni = g.step(t)
+        inter += ni
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, launches = g.profile_read()
+    g.profile(False)
+    g.close()
+    return {"ms_per_step": 1e3 * wall / steps, "interactions": inter,
+            "rate": inter / wall, "kernel_ms": kms / max(launches, 1), "launches": launches}
+
+
+def cpu_baseline(m, x, v, seconds):
+    """The CPU oracle (as it stands) on a bounded i-sample of the same
+    N x N evaluation; interactions/s = sample size * N / time."""
+    import numpy as np
+    import oracle
+    n = m.shape[0]
+    rng = np.random.default_rng(44)
+    k = 64
+    while True:
+        idx = np.sort(rng.choice(n, k, replace=False)).astype(np.int64)
+        t0 = time.perf_counter()
+        oracle.forces(x, v, m, EPS, idx=idx)
+        dt = time.perf_counter() - t0
+        if dt >= seconds or k >= n:
+            break
+        k = min(n, max(2 * k, int(k * seconds / max(dt, 1e-3))))
+    return {"value": k * n / dt, "unit": "interactions/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{k} random i x {n} j of the same King W0=7 evaluation (FP64, "
+                      f"compensated sums), {dt:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU split is a "
+              "design note, not a measured path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_0909_0879_amd import binding, ics
+
+    m, x, v = ics.king(a.n, 7.0, 4)
+    mixed = time_path(binding, torch, m, x, v, binding.MIXED, a.steps, a.warmup)
+    fp64 = None
+    if not a.no_fp64:
+        fp64 = time_path(binding, torch, m, x, v, binding.FP64, max(1, a.steps // 2 + 1),
+                         a.warmup)
+    n = a.n
+    per_launch_flops = FLOPS_PER_INTERACTION * float(n) * n
+    achieved = per_launch_flops / (mixed["kernel_ms"] * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": mixed["rate"],
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": mixed["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "mixed f64/f32",
+        "data": "synthetic",
+        "config": {"workload": f"King W0=7 N={n} equal-mass Henon units eps=1e-4, Hermite-4 "
+                               f"block step with all particles active (level {LEVEL}), "
+                               "mixed-precision force path",
+                   "n": n, "interactions_per_step": n * n},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": None, "kernel": "k_force<mixed,state,K>",
+                     "kernel_ms": mixed["kernel_ms"],
+                     "flops_per_launch": per_launch_flops},
+    }
+    if fp64:
+        f_ach = per_launch_flops / (fp64["kernel_ms"] * 1e-3) / 1e12
+        out["fp64"] = {"value": fp64["rate"], "ms_per_step": fp64["ms_per_step"],
+                       "kernel_ms": fp64["kernel_ms"], "achieved_tflops": f_ach,
+                       "frac_fp64_peak": f_ach / FP64_VECTOR_PEAK_TFLOPS}
+        out["mixed_over_fp64"] = mixed["rate"] / fp64["rate"]
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(m, x, v, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * nbody.h - C ABI of the MI355X direct N-body library (libnbody.so).
+ *
+ * The library evaluates the O(N^2) pairwise gravitational acceleration of
+ * eq. (1) of the paper (Capuzzo-Dolcetta, "Supercomputing and stellar
+ * dynamics", Sect. 2), with G = 1 and total mass as the mass unit (Sect. 4),
+ * softened in the pair potential by eps (Sect. 4; Plummer form
+ * phi = -m / sqrt(r^2 + eps^2)), together with its time derivative (the
+ * jerk).  It advances systems with a fourth-order Hermite predictor-corrector
+ * on individual power-of-two block time steps chosen by Aarseth's criterion
+ * (the paper's individual per-particle time steps, Sect. 3).  Many
+ * independent systems ("clusters") can share one context; each cluster only
+ * feels its own particles.
+ *
+ * Conventions
+ *  - Arrays of vectors are (n, 3) row-major FP64: x[3*i + c].
+ *  - All data pointers are DEVICE pointers unless marked "host".
+ *  - Time is counted in integer ticks of 2^-20 time units.  A particle on
+ *    level l has step 2^-l; levels run from level_min (largest step) to
+ *    level_max (smallest step), 0 <= level_min <= level_max <= 20.
+ *  - Calls are asynchronous on params.stream unless marked "syncs".
+ *  - Return values are NBODY_OK (0) or a negative nbody_status.  Arguments
+ *    that can be checked on the host are checked before any device work.
+ *    Errors found by kernels are sticky: they are returned by the next call
+ *    that syncs (nbody_step, nbody_energy, nbody_get_state, nbody_sync).
+ *  - No exceptions cross this interface.  nbody_last_error() gives a
+ *    human-readable message for the calling thread's last failure.
+ *
+ * Ownership
+ *  - The caller owns every buffer passed in, including the device workspace
+ *    and the stream.  The library never allocates or frees device memory; it
+ *    carves its state out of the workspace.  A context must be destroyed
+ *    before its workspace is freed or reused.
+ *  - nbody_init copies the initial state into the workspace; the caller's
+ *    m, x, v may be freed afterwards.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nbody_ctx nbody_ctx;
+
+typedef enum nbody_status {
+  NBODY_OK = 0,
+  NBODY_EINVAL = -1,     /* invalid argument (host-checked, nothing enqueued) */
+  NBODY_ENODEV = -2,     /* no usable HIP device */
+  NBODY_ENOMEM = -3,     /* workspace smaller than nbody_workspace_bytes() */
+  NBODY_EHIP = -4,       /* a HIP runtime call failed */
+  NBODY_EINDEX = -5,     /* device-detected: an i index out of range or
+                            i_active not grouped by cluster */
+  NBODY_ENONFINITE = -6, /* device-detected: NaN/Inf in forces or state */
+  NBODY_EDOMAIN = -7     /* device-detected: eps == 0 and two distinct
+                            particles at the same position */
+} nbody_status;
+
+typedef enum nbody_precision {
+  /* plain FP64 arithmetic throughout */
+  NBODY_FP64 = 0,
+  /* FP64 state, predictor/corrector and coordinate differences
+     x_j - x_i, v_j - v_i; FP32 rsqrt, r^-3 and jerk products, FP32 sums
+     over each j-tile folded into a compensated (TwoSum) FP32 hi/lo pair */
+  NBODY_MIXED = 1
+} nbody_precision;
+
+typedef struct nbody_params {
+  int32_t n_clusters;              /* >= 1, <= 4096 */
+  int32_t precision;               /* nbody_precision */
+  const int64_t *cluster_offsets;  /* host, n_clusters + 1 entries, [0] = 0,
+                                      strictly increasing, last = n; NULL
+                                      means one cluster [0, n) */
+  const double *eps;               /* host, n_clusters softening lengths >= 0 */
+  double eta;                      /* Aarseth accuracy parameter, > 0 */
+  double eta_start;                /* initial step: eta_start |a| / |jerk|, > 0 */
+  double dt_shared;                /* > 0: every particle uses this step
+                                      (a power of two in [2^-level_max,
+                                      2^-level_min]); 0: block steps */
+  int32_t level_min, level_max;    /* step range [2^-level_max, 2^-level_min] */
+  void *stream;                    /* hipStream_t for all work; NULL = null stream */
+  void *workspace;                 /* device buffer, 256-byte aligned */
+  size_t workspace_bytes;          /* >= nbody_workspace_bytes(params, n) */
+} nbody_params;
+
+/* Bytes of device workspace a context for n particles needs (0 if the
+ * parameters are invalid).  Host only; no device call. */
+size_t nbody_workspace_bytes(const nbody_params *p, int64_t n);
+
+/* Create a context for n particles, copy masses m (n), positions x and
+ * velocities v ((n, 3), device) into the workspace, evaluate the initial
+ * acceleration and jerk of every particle and choose initial levels
+ * (dt_shared, or the largest power-of-two step <= eta_start |a| / |jerk|,
+ * clamped to the level range).  All particles start at t = 0.  Syncs.
+ * *out is set to NULL on failure. */
+int nbody_init(nbody_ctx **out, const nbody_params *p, int64_t n,
+               const double *m, const double *x, const double *v);
+
+/* Pure evaluation (eq. (1) with Plummer softening, plus jerk): for k in
+ * [0, n_active), acc[k] and jerk[k] ((n_active, 3), device) receive the sum
+ * over the j-particles xj, vj ((n_j, 3)) and mj (n_j) of the pair terms on
+ * particle i = i_active[k] (an index into the j arrays), skipping j == i.
+ * With one cluster n_j may be any size >= 1; with several clusters n_j must
+ * equal the context's n, i's partners are the particles of its own cluster,
+ * and i_active must be grouped by cluster (non-decreasing cluster id).
+ * Indices may repeat.  The context's state is not touched; its precision,
+ * softening and stream are used.  Asynchronous; an index out of range or a
+ * grouping violation is reported as NBODY_EINDEX at the next syncing call
+ * and the affected outputs are zero. */
+int nbody_forces(nbody_ctx *c, const int32_t *i_active, int64_t n_active,
+                 const double *xj, const double *vj, const double *mj,
+                 int64_t n_j, double *acc, double *jerk);
+
+/* Advance every cluster with Hermite-4 block steps to the absolute time
+ * t_end, which must be a multiple of 2^-level_min and not earlier than the
+ * current time.  Each block step: per cluster, the next time
+ * T_next = min_i (t_i + dt_i) and the active set {i : t_i + dt_i = T_next};
+ * every particle of the cluster predicted to T_next; acceleration and jerk
+ * of the active particles; correction; new levels.  Steps run as captured
+ * HIP graphs unless tuning says otherwise.  If n_block_steps is non-NULL it
+ * receives the number of device block-step iterations taken by this call;
+ * n_interactions the sum of n_active * n_cluster over them.  Syncs. */
+int nbody_step(nbody_ctx *c, double t_end, int64_t *n_block_steps,
+               int64_t *n_interactions);
+
+/* Diagnostics per cluster, computed in FP64 at each cluster's current time
+ * (every particle predicted to it): out (host) receives 9 doubles per
+ * cluster: K, W, E, Lx, Ly, Lz, Px, Py, Pz, with K = 1/2 sum m v^2,
+ * W = -sum_{i<j} m_i m_j / sqrt(r^2 + eps^2), E = K + W, L = sum m x cross
+ * v, P = sum m v (virial ratio Q = 2K/|W|, Sect. 4).  Syncs. */
+int nbody_energy(nbody_ctx *c, double *out);
+
+/* Copy the state out: x, v, a, jerk ((n, 3), device, FP64), tick (n, int64,
+ * device: time of each particle's last correction in ticks), level (n,
+ * int8, device).  Any pointer may be NULL to skip it.  Syncs. */
+int nbody_get_state(nbody_ctx *c, double *x, double *v, double *a,
+                    double *jerk, int64_t *tick, int8_t *level);
+
+/* Replace the state (same layouts as nbody_get_state, none may be NULL).
+ * Each cluster's current time becomes the largest tick among its
+ * particles.  Every particle must satisfy: level in the level range, tick a
+ * multiple of its step 2^(20 - level), tick <= cluster time < tick + step
+ * (otherwise NBODY_EINVAL).  Syncs. */
+int nbody_set_state(nbody_ctx *c, const double *x, const double *v,
+                    const double *a, const double *jerk, const int64_t *tick,
+                    const int8_t *level);
+
+/* Wait for the context's stream and return the sticky device error, if any
+ * (the error is cleared once returned). */
+int nbody_sync(nbody_ctx *c);
+
+/* Per-context counters since nbody_init (host, 8 int64): block steps,
+ * interactions (n_active * n_cluster summed over steps), clamps at the
+ * smallest step, current time of cluster 0 in ticks, and 4 reserved.
+ * Syncs. */
+int nbody_stats(nbody_ctx *c, int64_t *out8);
+
+/* Kernel timing for measurement.  While enabled, block steps launch their
+ * kernels eagerly (no graph; results are identical) and the library records
+ * a pair of HIP events on the context's stream around every launch of the
+ * force kernel (steps, nbody_forces, nbody_energy).  nbody_profile_read
+ * syncs and returns the summed event time of those launches in ms and
+ * their number since the previous read (either pointer may be NULL). */
+int nbody_profile(nbody_ctx *c, int enable);
+int nbody_profile_read(nbody_ctx *c, double *force_ms, int64_t *force_launches);
+
+/* Free the host-side context (the workspace stays with the caller).  Waits
+ * for outstanding work.  NULL is ignored. */
+void nbody_destroy(nbody_ctx *c);
+
+const char *nbody_strerror(int code);
+const char *nbody_last_error(void);
+
+/* ---- launch tuning (written by the autotuner, optional) ----------------
+ * The force kernel runs over work items (cluster, i-tile, j-split).  For a
+ * cluster with n_active particles in bucket b = floor(log2(n_active))
+ * (0..24), i_slots[b] threads of a 256-thread workgroup hold i-particles
+ * (a power of two, 1..256; the other 256 / i_slots lanes split j inside the
+ * workgroup) and the j range is split until the cluster has about
+ * target_items[b] items.  variant selects the compiled kernel shape:
+ * NBODY_VARIANT_K1 (one i per thread slot) or NBODY_VARIANT_K2 (two).
+ * Zero fields keep the defaults. */
+#define NBODY_TUNE_BUCKETS 25
+enum { NBODY_VARIANT_DEFAULT = 0, NBODY_VARIANT_K1 = 1, NBODY_VARIANT_K2 = 2 };
+enum { NBODY_GRAPH_ON = 1, NBODY_GRAPH_OFF = 2 };
+
+typedef struct nbody_tuning {
+  int32_t variant;
+  int32_t use_graph;        /* NBODY_GRAPH_ON: block steps replay a captured
+                               HIP graph (default); NBODY_GRAPH_OFF: eager
+                               launches (results are identical) */
+  int32_t steps_per_launch; /* block steps per graph launch / host check */
+  int32_t min_split_j;      /* smallest j range of one split (>= 64) */
+  int32_t i_slots[NBODY_TUNE_BUCKETS];
+  int32_t target_items[NBODY_TUNE_BUCKETS];
+} nbody_tuning;
+
+/* Read or replace the tuning of a context (host only, no device work). */
+int nbody_get_tuning(const nbody_ctx *c, nbody_tuning *t);
+int nbody_set_tuning(nbody_ctx *c, const nbody_tuning *t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBODY_H */

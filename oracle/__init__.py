@@ -50,6 +50,8 @@ def lib():
         L.oracle_energy.argtypes = [C.c_int64, P, P, P, C.c_double, P]
         L.oracle_predict_one.argtypes = [P, P, P, P, C.c_double, P, P]
         L.oracle_predict_one.restype = None
+        L.oracle_predict.argtypes = [C.c_int64, P, P, P, P, P, P, P]
+        L.oracle_predict.restype = None
         L.oracle_correct_one.argtypes = [P, P, P, P, P, P, C.c_double, P, P, P, P]
         L.oracle_correct_one.restype = None
         L.oracle_aarseth_dt.argtypes = [P, P, P, P, C.c_double]
@@ -111,6 +113,17 @@ def predict_one(x, v, a, j, dt):
     xs = [_f64(q, (3,)) for q in (x, v, a, j)]
     xp, vp = np.empty(3), np.empty(3)
     lib().oracle_predict_one(*[_p(q) for q in xs], float(dt), _p(xp), _p(vp))
+    return xp, vp
+
+
+def predict(x, v, a, j, dt):
+    """Predict every particle over its own interval dt (scalar or (n,))."""
+    x = _f64(x)
+    n = x.shape[0]
+    v, a, j = (_f64(q, (n, 3)) for q in (v, a, j))
+    dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, np.float64), (n,)))
+    xp, vp = np.empty((n, 3)), np.empty((n, 3))
+    lib().oracle_predict(n, _p(x), _p(v), _p(a), _p(j), _p(dt), _p(xp), _p(vp))
     return xp, vp
 
 

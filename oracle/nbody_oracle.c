@@ -200,6 +200,14 @@ void oracle_predict_one(const double x[3], const double v[3],
   }
 }
 
+/* Predict n particles over per-particle intervals dt[i] ((n, 3) arrays). */
+void oracle_predict(int64_t n, const double *x, const double *v, const double *a,
+                    const double *j, const double *dt, double *xp, double *vp) {
+  for (int64_t i = 0; i < n; ++i)
+    oracle_predict_one(&x[3 * i], &v[3 * i], &a[3 * i], &j[3 * i], dt[i], &xp[3 * i],
+                       &vp[3 * i]);
+}
+
 /* Corrector of the fourth-order Hermite scheme over a step h, given the
  * predicted xp, vp and the acceleration and jerk at both ends (a0, j0 at
  * the start, a1, j1 at the end):

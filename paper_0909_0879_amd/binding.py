@@ -1,0 +1,272 @@
+"""Thin ctypes binding of libnbody.so (argument marshalling only).
+
+Every step of the hot path runs in the HIP library; this module only turns
+torch device tensors into pointers, holds the workspace tensor and maps
+error codes to exceptions.  PyTorch is used for device memory and streams.
+If the compiled library is missing the import fails: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnbody.so")
+
+OK, EINVAL, ENODEV, ENOMEM, EHIP, EINDEX, ENONFINITE, EDOMAIN = 0, -1, -2, -3, -4, -5, -6, -7
+FP64, MIXED = 0, 1
+VARIANT_DEFAULT, VARIANT_K1, VARIANT_K2 = 0, 1, 2
+GRAPH_ON, GRAPH_OFF = 1, 2
+TUNE_BUCKETS = 25
+TICK_BITS = 20
+
+EXPORTED = [
+    "nbody_workspace_bytes", "nbody_init", "nbody_forces", "nbody_step", "nbody_energy",
+    "nbody_get_state", "nbody_set_state", "nbody_sync", "nbody_stats", "nbody_destroy",
+    "nbody_strerror", "nbody_last_error", "nbody_get_tuning", "nbody_set_tuning",
+    "nbody_profile", "nbody_profile_read",
+]
+
+
+class NBodyError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {msg} (code {code})")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("n_clusters", C.c_int32), ("precision", C.c_int32),
+        ("cluster_offsets", C.c_void_p), ("eps", C.c_void_p),
+        ("eta", C.c_double), ("eta_start", C.c_double), ("dt_shared", C.c_double),
+        ("level_min", C.c_int32), ("level_max", C.c_int32),
+        ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+    ]
+
+
+class Tuning(C.Structure):
+    _fields_ = [
+        ("variant", C.c_int32), ("use_graph", C.c_int32), ("steps_per_launch", C.c_int32),
+        ("min_split_j", C.c_int32),
+        ("i_slots", C.c_int32 * TUNE_BUCKETS), ("target_items", C.c_int32 * TUNE_BUCKETS),
+    ]
+
+    def as_dict(self):
+        return {"variant": self.variant, "use_graph": self.use_graph,
+                "steps_per_launch": self.steps_per_launch, "min_split_j": self.min_split_j,
+                "i_slots": list(self.i_slots), "target_items": list(self.target_items)}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        t.variant = int(d.get("variant", 0))
+        t.use_graph = int(d.get("use_graph", 0))
+        t.steps_per_launch = int(d.get("steps_per_launch", 0))
+        t.min_split_j = int(d.get("min_split_j", 0))
+        for b, v in enumerate(d.get("i_slots", [0] * TUNE_BUCKETS)):
+            t.i_slots[b] = int(v)
+        for b, v in enumerate(d.get("target_items", [0] * TUNE_BUCKETS)):
+            t.target_items[b] = int(v)
+        return t
+
+
+_lib = None
+
+
+def lib():
+    """Load libnbody.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "or python paper_0909_0879_amd/build_lib.py")
+        L = C.CDLL(LIB_PATH)
+        P, I64 = C.c_void_p, C.c_int64
+        L.nbody_workspace_bytes.argtypes = [P, I64]
+        L.nbody_workspace_bytes.restype = C.c_size_t
+        L.nbody_init.argtypes = [P, P, I64, P, P, P]
+        L.nbody_forces.argtypes = [P, P, I64, P, P, P, I64, P, P]
+        L.nbody_step.argtypes = [P, C.c_double, P, P]
+        L.nbody_energy.argtypes = [P, P]
+        L.nbody_get_state.argtypes = [P, P, P, P, P, P, P]
+        L.nbody_set_state.argtypes = [P, P, P, P, P, P, P]
+        L.nbody_sync.argtypes = [P]
+        L.nbody_stats.argtypes = [P, P]
+        L.nbody_destroy.argtypes = [P]
+        L.nbody_destroy.restype = None
+        L.nbody_strerror.argtypes = [C.c_int]
+        L.nbody_strerror.restype = C.c_char_p
+        L.nbody_last_error.argtypes = []
+        L.nbody_last_error.restype = C.c_char_p
+        L.nbody_get_tuning.argtypes = [P, P]
+        L.nbody_set_tuning.argtypes = [P, P]
+        L.nbody_profile.argtypes = [P, C.c_int]
+        L.nbody_profile_read.argtypes = [P, P, P]
+        _lib = L
+    return _lib
+
+
+def check(rc: int, where: str):
+    if rc != OK:
+        msg = lib().nbody_last_error().decode() or lib().nbody_strerror(rc).decode()
+        raise NBodyError(rc, where, msg)
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream), stream
+
+
+def make_params(n, n_clusters=1, cluster_offsets=None, eps=1e-3, precision=FP64, eta=0.01,
+                eta_start=0.01, dt_shared=0.0, level_min=3, level_max=20):
+    """Host-side parameter block (keeps the numpy arrays it points to alive)."""
+    eps_arr = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, np.float64), (n_clusters,)))
+    p = Params()
+    p.n_clusters = n_clusters
+    p.precision = precision
+    keep = [eps_arr]
+    if cluster_offsets is not None:
+        off = np.ascontiguousarray(cluster_offsets, np.int64)
+        keep.append(off)
+        p.cluster_offsets = off.ctypes.data
+    else:
+        p.cluster_offsets = None
+    p.eps = eps_arr.ctypes.data
+    p.eta, p.eta_start, p.dt_shared = float(eta), float(eta_start), float(dt_shared)
+    p.level_min, p.level_max = int(level_min), int(level_max)
+    p._keep = keep
+    return p
+
+
+def workspace_bytes(n, **kw) -> int:
+    p = make_params(n, **kw)
+    return int(lib().nbody_workspace_bytes(C.byref(p), int(n)))
+
+
+class NBody:
+    """One library context: state in a caller-owned torch workspace tensor."""
+
+    def __init__(self, m, x, v, *, cluster_offsets=None, eps=1e-3, precision=FP64, eta=0.01,
+                 eta_start=0.01, dt_shared=0.0, level_min=3, level_max=20, stream=None,
+                 device="cuda"):
+        import torch
+        self._torch = torch
+        m = torch.as_tensor(m, dtype=torch.float64, device=device).contiguous()
+        x = torch.as_tensor(x, dtype=torch.float64, device=device).contiguous()
+        v = torch.as_tensor(v, dtype=torch.float64, device=device).contiguous()
+        n = m.shape[0]
+        if x.shape != (n, 3) or v.shape != (n, 3):
+            raise ValueError("x and v must have shape (n, 3)")
+        n_clusters = 1 if cluster_offsets is None else len(cluster_offsets) - 1
+        self.params = make_params(n, n_clusters, cluster_offsets, eps, precision, eta, eta_start,
+                                  dt_shared, level_min, level_max)
+        self.n = n
+        self.n_clusters = n_clusters
+        self.precision = precision
+        self.level_min, self.level_max = level_min, level_max
+        nbytes = lib().nbody_workspace_bytes(C.byref(self.params), n)
+        if nbytes == 0:
+            check(EINVAL, "nbody_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        h, self.stream = _stream_handle(stream)
+        self.params.stream = h
+        self.params.workspace = self.workspace.data_ptr()
+        self.params.workspace_bytes = nbytes
+        self.ctx = C.c_void_p()
+        check(lib().nbody_init(C.byref(self.ctx), C.byref(self.params), n, _ptr(m), _ptr(x),
+                               _ptr(v)), "nbody_init")
+
+    # -- evaluation -------------------------------------------------------
+    def forces(self, xj, vj, mj, i_active=None):
+        """Acceleration and jerk on i_active from (xj, vj, mj); device tensors."""
+        torch = self._torch
+        dev = self.workspace.device
+        xj = torch.as_tensor(xj, dtype=torch.float64, device=dev).contiguous()
+        vj = torch.as_tensor(vj, dtype=torch.float64, device=dev).contiguous()
+        mj = torch.as_tensor(mj, dtype=torch.float64, device=dev).contiguous()
+        nj = mj.shape[0]
+        if i_active is None:
+            i_active = torch.arange(nj, dtype=torch.int32, device=dev)
+        ia = torch.as_tensor(i_active, dtype=torch.int32, device=dev).contiguous()
+        na = ia.shape[0]
+        acc = torch.empty((na, 3), dtype=torch.float64, device=dev)
+        jerk = torch.empty((na, 3), dtype=torch.float64, device=dev)
+        check(lib().nbody_forces(self.ctx, _ptr(ia), na, _ptr(xj), _ptr(vj), _ptr(mj), nj,
+                                 _ptr(acc), _ptr(jerk)), "nbody_forces")
+        return acc, jerk
+
+    def step(self, t_end):
+        ns, ni = C.c_int64(0), C.c_int64(0)
+        check(lib().nbody_step(self.ctx, float(t_end), C.byref(ns), C.byref(ni)), "nbody_step")
+        return ns.value, ni.value
+
+    def energy(self):
+        out = np.empty((self.n_clusters, 9))
+        check(lib().nbody_energy(self.ctx, out.ctypes.data_as(C.c_void_p)), "nbody_energy")
+        return out
+
+    def get_state(self):
+        torch = self._torch
+        dev = self.workspace.device
+        x, v, a, j = (torch.empty((self.n, 3), dtype=torch.float64, device=dev) for _ in range(4))
+        tick = torch.empty(self.n, dtype=torch.int64, device=dev)
+        level = torch.empty(self.n, dtype=torch.int8, device=dev)
+        check(lib().nbody_get_state(self.ctx, _ptr(x), _ptr(v), _ptr(a), _ptr(j), _ptr(tick),
+                                    _ptr(level)), "nbody_get_state")
+        return {"x": x, "v": v, "a": a, "j": j, "tick": tick, "level": level}
+
+    def set_state(self, st):
+        torch = self._torch
+        dev = self.workspace.device
+        f = lambda k: torch.as_tensor(st[k], dtype=torch.float64, device=dev).contiguous()
+        x, v, a, j = f("x"), f("v"), f("a"), f("j")
+        tick = torch.as_tensor(st["tick"], dtype=torch.int64, device=dev).contiguous()
+        level = torch.as_tensor(st["level"], dtype=torch.int8, device=dev).contiguous()
+        check(lib().nbody_set_state(self.ctx, _ptr(x), _ptr(v), _ptr(a), _ptr(j), _ptr(tick),
+                                    _ptr(level)), "nbody_set_state")
+
+    def sync(self):
+        check(lib().nbody_sync(self.ctx), "nbody_sync")
+
+    def stats(self):
+        out = np.zeros(8, np.int64)
+        check(lib().nbody_stats(self.ctx, out.ctypes.data_as(C.c_void_p)), "nbody_stats")
+        return {"block_steps": int(out[0]), "interactions": int(out[1]),
+                "floor_clamps": int(out[2]), "t_tick": int(out[3])}
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        check(lib().nbody_get_tuning(self.ctx, C.byref(t)), "nbody_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, d: dict):
+        t = Tuning.from_dict(d)
+        check(lib().nbody_set_tuning(self.ctx, C.byref(t)), "nbody_set_tuning")
+
+    def profile(self, enable: bool):
+        check(lib().nbody_profile(self.ctx, 1 if enable else 0), "nbody_profile")
+
+    def profile_read(self):
+        """(total ms, launches) of force-kernel launches since the last read."""
+        ms, nl = C.c_double(0.0), C.c_int64(0)
+        check(lib().nbody_profile_read(self.ctx, C.byref(ms), C.byref(nl)), "nbody_profile_read")
+        return ms.value, nl.value
+
+    def close(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            lib().nbody_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

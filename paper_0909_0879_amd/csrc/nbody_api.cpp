@@ -1,0 +1,627 @@
+// Host runtime of libnbody.so: argument validation, workspace carving,
+// launch sequencing and HIP-graph capture of block steps.  See nbody.h for
+// the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "nbody.h"
+#include "nbody_internal.h"
+
+using nbk::Dev;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define NB_HIP(call)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return fail(NBODY_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kEvPairs = 1024;
+constexpr int64_t kMaxN = (int64_t)1 << 30;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Carve the workspace.  With base == nullptr only the size is computed.
+size_t carve(int64_t n, int32_t C, char *base, Dev *d) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char * {
+    char *p = base ? base + off : nullptr;
+    off = align_up(off + bytes);
+    return p;
+  };
+  Dev t{};
+  t.n = n;
+  t.C = C;
+  t.nblk = (int32_t)((n + nbk::kScanBlock - 1) / nbk::kScanBlock);
+  t.cap_active = n;
+  t.rows_cap = 5 * n + 4096;
+  t.x = (double *)take(sizeof(double) * 3 * n);
+  t.v = (double *)take(sizeof(double) * 3 * n);
+  t.a = (double *)take(sizeof(double) * 3 * n);
+  t.j = (double *)take(sizeof(double) * 3 * n);
+  t.m = (double *)take(sizeof(double) * n);
+  t.tick = (int64_t *)take(sizeof(int64_t) * n);
+  t.level = (int32_t *)take(sizeof(int32_t) * n);
+  t.cid = (int32_t *)take(sizeof(int32_t) * n);
+  t.coff = (int64_t *)take(sizeof(int64_t) * (C + 1));
+  t.eps2 = (double *)take(sizeof(double) * C);
+  t.T = (int64_t *)take(sizeof(int64_t) * C);
+  t.Tnext = (int64_t *)take(sizeof(int64_t) * C);
+  t.Lthr = (int32_t *)take(sizeof(int32_t) * C);
+  t.hist = (int32_t *)take(sizeof(int32_t) * C * nbk::kLevels);
+  t.active = (int32_t *)take(sizeof(int32_t) * t.cap_active);
+  t.act_off = (int32_t *)take(sizeof(int32_t) * (C + 1));
+  t.blk_cnt = (int32_t *)take(sizeof(int32_t) * t.nblk);
+  t.blk_off = (int32_t *)take(sizeof(int32_t) * (t.nblk + 1));
+  t.plan_c = (nbk::ClusterPlan *)take(sizeof(nbk::ClusterPlan) * C);
+  t.plan_lpt = (nbk::ClusterPlan *)take(sizeof(nbk::ClusterPlan) * C);
+  t.item_prefix = (int32_t *)take(sizeof(int32_t) * (C + 1));
+  t.partial = (double *)take(sizeof(double) * nbk::kRowStride * t.rows_cap);
+  t.work = (int32_t *)take(sizeof(int32_t) * 4);
+  t.err = (int32_t *)take(sizeof(int32_t) * 4);
+  t.ctr = (int64_t *)take(sizeof(int64_t) * nbk::kCtrCount);
+  t.eout = (double *)take(sizeof(double) * 9 * C);
+  if (d) *d = t;
+  return off;
+}
+
+bool is_pow2_step(double dt, int lmin, int lmax, int *level) {
+  if (!(dt > 0.0) || !std::isfinite(dt)) return false;
+  int e;
+  const double f = std::frexp(dt, &e);
+  if (f != 0.5) return false;
+  const int l = 1 - e;
+  if (l < lmin || l > lmax) return false;
+  if (level) *level = l;
+  return true;
+}
+
+int validate_params(const nbody_params *p, int64_t n) {
+  if (!p) return fail(NBODY_EINVAL, "params is NULL");
+  if (n < 1 || n > kMaxN) return fail(NBODY_EINVAL, "n must be in [1, 2^30]");
+  if (p->n_clusters < 1 || p->n_clusters > nbk::kMaxClusters)
+    return fail(NBODY_EINVAL, "n_clusters must be in [1, 4096]");
+  if (p->precision != NBODY_FP64 && p->precision != NBODY_MIXED)
+    return fail(NBODY_EINVAL, "unknown precision");
+  const int C = p->n_clusters;
+  if (p->cluster_offsets) {
+    if (p->cluster_offsets[0] != 0 || p->cluster_offsets[C] != n)
+      return fail(NBODY_EINVAL, "cluster_offsets must start at 0 and end at n");
+    for (int c = 0; c < C; ++c)
+      if (p->cluster_offsets[c + 1] <= p->cluster_offsets[c])
+        return fail(NBODY_EINVAL, "cluster_offsets must be strictly increasing");
+  } else if (C != 1) {
+    return fail(NBODY_EINVAL, "cluster_offsets is NULL with n_clusters > 1");
+  }
+  if (!p->eps) return fail(NBODY_EINVAL, "eps is NULL");
+  for (int c = 0; c < C; ++c)
+    if (!(p->eps[c] >= 0.0) || !std::isfinite(p->eps[c]))
+      return fail(NBODY_EINVAL, "eps must be finite and >= 0");
+  if (!(p->eta > 0.0) || !std::isfinite(p->eta))
+    return fail(NBODY_EINVAL, "eta must be > 0");
+  if (!(p->eta_start > 0.0) || !std::isfinite(p->eta_start))
+    return fail(NBODY_EINVAL, "eta_start must be > 0");
+  if (p->level_min < 0 || p->level_max > nbk::kTickBits || p->level_min > p->level_max)
+    return fail(NBODY_EINVAL, "need 0 <= level_min <= level_max <= 20");
+  if (p->dt_shared != 0.0 && !is_pow2_step(p->dt_shared, p->level_min, p->level_max, nullptr))
+    return fail(NBODY_EINVAL, "dt_shared must be 0 or a power of two within the level range");
+  return NBODY_OK;
+}
+
+int device_present(int *dev) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+    return fail(NBODY_ENODEV, "no HIP device");
+  if (hipGetDevice(dev) != hipSuccess) return fail(NBODY_ENODEV, "hipGetDevice failed");
+  return NBODY_OK;
+}
+
+nbody_tuning default_tuning(int precision) {
+  nbody_tuning t;
+  std::memset(&t, 0, sizeof t);
+  t.variant = (precision == NBODY_MIXED) ? NBODY_VARIANT_K2 : NBODY_VARIANT_K1;
+  t.use_graph = NBODY_GRAPH_ON;
+  t.steps_per_launch = 16;
+  t.min_split_j = 256;
+  const int K = (t.variant == NBODY_VARIANT_K2) ? 2 : 1;
+  for (int b = 0; b < NBODY_TUNE_BUCKETS; ++b) {
+    // one i-tile covers the bucket [2^b, 2^(b+1)) when possible
+    int64_t cover = ((int64_t)2 << b) / K;
+    if (b == 0) cover = 1;
+    if (cover < 1) cover = 1;
+    int P = 1;
+    while (P < cover && P < 256) P <<= 1;
+    t.i_slots[b] = P;
+    t.target_items[b] = 2048;
+  }
+  return t;
+}
+
+int map_err_bits(int bits) {
+  if (bits & nbk::kErrDomain)
+    return fail(NBODY_EDOMAIN, "eps == 0 and two distinct particles coincide");
+  if (bits & nbk::kErrNonFinite)
+    return fail(NBODY_ENONFINITE, "non-finite acceleration, jerk or state");
+  if (bits & nbk::kErrIndex)
+    return fail(NBODY_EINDEX, "i index out of range or i_active not grouped by cluster");
+  if (bits) return fail(NBODY_EINVAL, "invalid state");
+  return NBODY_OK;
+}
+
+}  // namespace
+
+struct nbody_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;   // caller's stream
+  hipStream_t cap = nullptr;      // private stream used only for capture
+  int64_t n = 0;
+  int32_t C = 1;
+  int prec = NBODY_FP64;
+  double eta = 0, eta_start = 0, dt_shared = 0;
+  int lmin = 0, lmax = 0;
+  std::vector<int64_t> coff;
+  std::vector<int64_t> T_host;    // cluster times known to the host
+  Dev d{};
+  nbody_tuning tune{};
+  int K = 1;
+  int grid_state = 0, grid_raw = 0, grid_pot = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_steps = 0;
+  int64_t *pinned = nullptr;      // host pinned readback words (32 x int64)
+  // profiling: event pairs around force-kernel launches
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;     // 2 * kEvPairs events
+  int ev_used = 0;                // pairs recorded since the last harvest
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
+};
+
+namespace {
+
+nbk::Tuning device_tuning(const nbody_ctx *c, int K) {
+  nbk::Tuning t{};
+  for (int b = 0; b < nbk::kBuckets; ++b) {
+    t.i_slots[b] = c->tune.i_slots[b];
+    t.target_items[b] = c->tune.target_items[b];
+  }
+  t.min_split_j = c->tune.min_split_j;
+  t.K = K;
+  return t;
+}
+
+int mode_of(const nbody_ctx *c) {
+  return c->prec == NBODY_MIXED ? nbk::kModeMixed : nbk::kModeFP64;
+}
+
+void drop_graph(nbody_ctx *c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->graph_steps = 0;
+}
+
+int refresh_grids(nbody_ctx *c) {
+  c->K = (c->tune.variant == NBODY_VARIANT_K2) ? 2 : 1;
+  c->grid_state = nbk::force_grid_size(mode_of(c), nbk::kSrcState, c->K, c->device);
+  c->grid_raw = nbk::force_grid_size(mode_of(c), nbk::kSrcRaw, c->K, c->device);
+  c->grid_pot = nbk::force_grid_size(nbk::kModePot, nbk::kSrcState, 1, c->device);
+  if (c->grid_state < 1 || c->grid_raw < 1 || c->grid_pot < 1)
+    return fail(NBODY_EHIP, "could not size the force kernel grid");
+  return NBODY_OK;
+}
+
+int harvest_events(nbody_ctx *c);
+
+// Launch the force kernel, bracketed by timing events when profiling.
+int force_launch(nbody_ctx *c, int mode, int src, int K, const nbk::RawSrc *raw, int grid,
+                 hipStream_t s) {
+  const bool prof = c->profiling && s == c->stream;
+  if (prof && c->ev_used == kEvPairs) {
+    int rc = harvest_events(c);
+    if (rc) return rc;
+  }
+  if (prof) NB_HIP(hipEventRecord(c->ev[2 * c->ev_used], s));
+  NB_HIP(nbk::launch_force(c->d, mode, src, K, raw, grid, s));
+  if (prof) {
+    NB_HIP(hipEventRecord(c->ev[2 * c->ev_used + 1], s));
+    ++c->ev_used;
+  }
+  return NBODY_OK;
+}
+
+// Wait for the recorded pairs and add their durations.
+int harvest_events(nbody_ctx *c) {
+  if (!c->ev_used) return NBODY_OK;
+  NB_HIP(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < c->ev_used; ++k) {
+    float ms = 0.0f;
+    NB_HIP(hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
+    c->prof_ms += ms;
+  }
+  c->prof_launches += c->ev_used;
+  c->ev_used = 0;
+  return NBODY_OK;
+}
+
+// One Hermite block step for every cluster, enqueued on s.
+int enqueue_block_step(nbody_ctx *c, hipStream_t s) {
+  const nbk::Tuning t = device_tuning(c, c->K);
+  NB_HIP(nbk::launch_sched(c->d, s));
+  NB_HIP(nbk::launch_compact(c->d, s));
+  NB_HIP(nbk::launch_plan(c->d, t, 0, 0, s));
+  int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->grid_state, s);
+  if (rc) return rc;
+  NB_HIP(nbk::launch_correct(c->d, c->eta, c->dt_shared, c->lmin, c->lmax, s));
+  return NBODY_OK;
+}
+
+int ensure_graph(nbody_ctx *c) {
+  const int steps = c->tune.steps_per_launch;
+  if (c->gexec && c->graph_steps == steps) return NBODY_OK;
+  drop_graph(c);
+  NB_HIP(hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+  int rc = NBODY_OK;
+  for (int k = 0; k < steps && rc == NBODY_OK; ++k) rc = enqueue_block_step(c, c->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->cap, &g);
+  if (rc != NBODY_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(NBODY_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  c->graph = g;
+  NB_HIP(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+  c->graph_steps = steps;
+  return NBODY_OK;
+}
+
+// Wait for the stream, then fetch counters and error bits into pinned.
+int readback(nbody_ctx *c) {
+  NB_HIP(hipMemcpyAsync(c->pinned, c->d.ctr, sizeof(int64_t) * nbk::kCtrCount,
+                        hipMemcpyDeviceToHost, c->stream));
+  NB_HIP(hipMemcpyAsync(c->pinned + 16, c->d.err, sizeof(int32_t), hipMemcpyDeviceToHost,
+                        c->stream));
+  NB_HIP(hipStreamSynchronize(c->stream));
+  return NBODY_OK;
+}
+
+int take_error(nbody_ctx *c) {
+  const int bits = *(const int32_t *)(c->pinned + 16);
+  if (!bits) return NBODY_OK;
+  NB_HIP(nbk::launch_fill32(c->d.err, 0, 1, c->stream));
+  NB_HIP(hipStreamSynchronize(c->stream));
+  *(int32_t *)(c->pinned + 16) = 0;
+  return map_err_bits(bits);
+}
+
+int full_evaluation_into_state(nbody_ctx *c) {
+  // initial forces: every particle active, predicted to its own time
+  const nbk::Tuning t = device_tuning(c, c->K);
+  NB_HIP(nbk::launch_all_active(c->d, c->stream));
+  NB_HIP(nbk::launch_plan(c->d, t, 1, 0, c->stream));
+  int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->grid_state, c->stream);
+  if (rc) return rc;
+  NB_HIP(nbk::launch_init_levels(c->d, c->eta_start, c->dt_shared, c->lmin, c->lmax,
+                                 c->stream));
+  return NBODY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t nbody_workspace_bytes(const nbody_params *p, int64_t n) {
+  if (validate_params(p, n) != NBODY_OK) return 0;
+  return carve(n, p->n_clusters, nullptr, nullptr);
+}
+
+int nbody_init(nbody_ctx **out, const nbody_params *p, int64_t n, const double *m,
+               const double *x, const double *v) {
+  if (!out) return fail(NBODY_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_params(p, n);
+  if (rc) return rc;
+  if (!m || !x || !v) return fail(NBODY_EINVAL, "m, x or v is NULL");
+  if (!p->workspace) return fail(NBODY_EINVAL, "workspace is NULL");
+  if ((uintptr_t)p->workspace % kAlign)
+    return fail(NBODY_EINVAL, "workspace must be 256-byte aligned");
+  const size_t need = carve(n, p->n_clusters, nullptr, nullptr);
+  if (p->workspace_bytes < need)
+    return fail(NBODY_ENOMEM, "workspace smaller than nbody_workspace_bytes()");
+  int dev = 0;
+  rc = device_present(&dev);
+  if (rc) return rc;
+
+  nbody_ctx *c = new (std::nothrow) nbody_ctx();
+  if (!c) return fail(NBODY_EINVAL, "out of host memory");
+  c->device = dev;
+  c->stream = (hipStream_t)p->stream;
+  c->n = n;
+  c->C = p->n_clusters;
+  c->prec = p->precision;
+  c->eta = p->eta;
+  c->eta_start = p->eta_start;
+  c->dt_shared = p->dt_shared;
+  c->lmin = p->level_min;
+  c->lmax = p->level_max;
+  c->coff.resize(c->C + 1);
+  if (p->cluster_offsets)
+    std::memcpy(c->coff.data(), p->cluster_offsets, sizeof(int64_t) * (c->C + 1));
+  else {
+    c->coff[0] = 0;
+    c->coff[1] = n;
+  }
+  c->T_host.assign(c->C, 0);
+  carve(n, c->C, (char *)p->workspace, &c->d);
+  c->tune = default_tuning(c->prec);
+  auto bail = [&](int code) {
+    nbody_destroy(c);
+    return code;
+  };
+  if ((rc = refresh_grids(c))) return bail(rc);
+  if (hipHostMalloc((void **)&c->pinned, 32 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
+    return bail(fail(NBODY_EHIP, "hipHostMalloc failed"));
+  std::memset(c->pinned, 0, 32 * sizeof(int64_t));
+  if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(NBODY_EHIP, "hipStreamCreate failed"));
+  std::vector<double> eps2(c->C);
+  for (int k = 0; k < c->C; ++k) eps2[k] = p->eps[k] * p->eps[k];
+  if (hipMemcpyAsync(c->d.coff, c->coff.data(), sizeof(int64_t) * (c->C + 1),
+                     hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->d.eps2, eps2.data(), sizeof(double) * c->C,
+                     hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return bail(fail(NBODY_EHIP, "upload of cluster tables failed"));
+  if (nbk::launch_init_state(c->d, m, x, v, c->stream) != hipSuccess)
+    return bail(fail(NBODY_EHIP, "init kernel launch failed"));
+  if ((rc = full_evaluation_into_state(c))) return bail(rc);
+  if ((rc = readback(c))) return bail(rc);
+  if ((rc = take_error(c))) return bail(rc);
+  *out = c;
+  return NBODY_OK;
+}
+
+int nbody_forces(nbody_ctx *c, const int32_t *i_active, int64_t n_active, const double *xj,
+                 const double *vj, const double *mj, int64_t n_j, double *acc, double *jerk) {
+  if (!c) return fail(NBODY_EINVAL, "context is NULL");
+  if (n_active < 0) return fail(NBODY_EINVAL, "n_active < 0");
+  if (n_active == 0) return NBODY_OK;
+  if (!i_active || !xj || !vj || !mj || !acc || !jerk)
+    return fail(NBODY_EINVAL, "NULL array argument");
+  if (n_j < 1 || n_j > kMaxN) return fail(NBODY_EINVAL, "n_j must be in [1, 2^30]");
+  if (c->C > 1 && n_j != c->n)
+    return fail(NBODY_EINVAL, "with several clusters n_j must equal the context's n");
+  const nbk::Tuning t = device_tuning(c, c->K);
+  const int64_t cap = c->d.cap_active;
+  for (int64_t k0 = 0; k0 < n_active; k0 += cap) {
+    nbk::RawSrc r;
+    r.x = xj;
+    r.v = vj;
+    r.m = mj;
+    r.n_j = (c->C == 1) ? n_j : 0;
+    r.i_active = i_active + k0;
+    r.n_active = (n_active - k0 < cap) ? n_active - k0 : cap;
+    r.acc = acc + 3 * k0;
+    r.jerk = jerk + 3 * k0;
+    NB_HIP(nbk::launch_api_group(c->d, r, c->stream));
+    NB_HIP(nbk::launch_plan(c->d, t, 2, r.n_j, c->stream));
+    int rc = force_launch(c, mode_of(c), nbk::kSrcRaw, c->K, &r, c->grid_raw, c->stream);
+    if (rc) return rc;
+    NB_HIP(nbk::launch_api_finalize(c->d, r, c->stream));
+  }
+  return NBODY_OK;
+}
+
+int nbody_step(nbody_ctx *c, double t_end, int64_t *n_block_steps, int64_t *n_interactions) {
+  if (!c) return fail(NBODY_EINVAL, "context is NULL");
+  if (!std::isfinite(t_end) || t_end < 0.0) return fail(NBODY_EINVAL, "t_end must be finite and >= 0");
+  const double tt = t_end * (double)(1 << nbk::kTickBits);
+  if (tt > 9.0e15 || tt != std::floor(tt))
+    return fail(NBODY_EINVAL, "t_end must be a multiple of 2^-20");
+  const int64_t tend = (int64_t)tt;
+  const int64_t dtmax = (int64_t)1 << (nbk::kTickBits - c->lmin);
+  if (tend % dtmax) return fail(NBODY_EINVAL, "t_end must be a multiple of 2^-level_min");
+  for (int k = 0; k < c->C; ++k)
+    if (tend < c->T_host[k]) return fail(NBODY_EINVAL, "t_end is earlier than the current time");
+  int rc = readback(c);
+  if (rc) return rc;
+  if ((rc = take_error(c))) return rc;
+  const int64_t steps0 = c->pinned[nbk::kCtrSteps], inter0 = c->pinned[nbk::kCtrInter];
+  NB_HIP(nbk::launch_set_word64(c->d.ctr + nbk::kCtrTend, tend, c->stream));
+  // an upper bound on block steps: every step moves some cluster by >= 1 tick
+  int64_t remaining = 0;
+  for (int k = 0; k < c->C; ++k) remaining += tend - c->T_host[k];
+  int64_t launches = 0;
+  const int64_t max_launches = remaining / (c->tune.steps_per_launch > 0 ? c->tune.steps_per_launch : 1) + 2;
+  while (remaining > 0) {
+    if (c->tune.use_graph == NBODY_GRAPH_ON && !c->profiling) {
+      if ((rc = ensure_graph(c))) return rc;
+      NB_HIP(hipGraphLaunch(c->gexec, c->stream));
+    } else {
+      for (int k = 0; k < c->tune.steps_per_launch; ++k)
+        if ((rc = enqueue_block_step(c, c->stream))) return rc;
+    }
+    if ((rc = readback(c))) return rc;
+    if (*(const int32_t *)(c->pinned + 16)) break;
+    if (c->pinned[nbk::kCtrNotDone] == 0) break;
+    if (++launches > max_launches) return fail(NBODY_EHIP, "block steps did not reach t_end");
+  }
+  if ((rc = take_error(c))) return rc;
+  for (int k = 0; k < c->C; ++k) c->T_host[k] = tend;
+  if (n_block_steps) *n_block_steps = c->pinned[nbk::kCtrSteps] - steps0;
+  if (n_interactions) *n_interactions = c->pinned[nbk::kCtrInter] - inter0;
+  return NBODY_OK;
+}
+
+int nbody_energy(nbody_ctx *c, double *out) {
+  if (!c || !out) return fail(NBODY_EINVAL, "NULL argument");
+  const nbk::Tuning t = device_tuning(c, 1);
+  NB_HIP(nbk::launch_all_active(c->d, c->stream));
+  NB_HIP(nbk::launch_plan(c->d, t, 1, 0, c->stream));
+  int rc0 = force_launch(c, nbk::kModePot, nbk::kSrcState, 1, nullptr, c->grid_pot, c->stream);
+  if (rc0) return rc0;
+  NB_HIP(nbk::launch_energy_reduce(c->d, c->stream));
+  NB_HIP(hipMemcpyAsync(out, c->d.eout, sizeof(double) * 9 * c->C, hipMemcpyDeviceToHost,
+                        c->stream));
+  int rc = readback(c);
+  if (rc) return rc;
+  return take_error(c);
+}
+
+int nbody_get_state(nbody_ctx *c, double *x, double *v, double *a, double *jerk,
+                    int64_t *tick, int8_t *level) {
+  if (!c) return fail(NBODY_EINVAL, "context is NULL");
+  NB_HIP(nbk::launch_get_state(c->d, x, v, a, jerk, tick, level, c->stream));
+  int rc = readback(c);
+  if (rc) return rc;
+  return take_error(c);
+}
+
+int nbody_set_state(nbody_ctx *c, const double *x, const double *v, const double *a,
+                    const double *jerk, const int64_t *tick, const int8_t *level) {
+  if (!c) return fail(NBODY_EINVAL, "context is NULL");
+  if (!x || !v || !a || !jerk || !tick || !level) return fail(NBODY_EINVAL, "NULL array argument");
+  int rc = readback(c);
+  if (rc) return rc;
+  if ((rc = take_error(c))) return rc;
+  NB_HIP(nbk::launch_fill32((int32_t *)c->d.T, 0, 2 * (int64_t)c->C, c->stream));
+  NB_HIP(nbk::launch_fill32(c->d.hist, 0, (int64_t)c->C * nbk::kLevels, c->stream));
+  NB_HIP(nbk::launch_set_state(c->d, x, v, a, jerk, tick, level, c->lmin, c->lmax, c->stream));
+  NB_HIP(hipMemcpyAsync(c->T_host.data(), c->d.T, sizeof(int64_t) * c->C, hipMemcpyDeviceToHost,
+                        c->stream));
+  if ((rc = readback(c))) return rc;
+  return take_error(c);
+}
+
+int nbody_sync(nbody_ctx *c) {
+  if (!c) return fail(NBODY_EINVAL, "context is NULL");
+  int rc = readback(c);
+  if (rc) return rc;
+  return take_error(c);
+}
+
+int nbody_stats(nbody_ctx *c, int64_t *out8) {
+  if (!c || !out8) return fail(NBODY_EINVAL, "NULL argument");
+  int rc = readback(c);
+  if (rc) return rc;
+  out8[0] = c->pinned[nbk::kCtrSteps];
+  out8[1] = c->pinned[nbk::kCtrInter];
+  out8[2] = c->pinned[nbk::kCtrFloor];
+  out8[3] = c->T_host[0];
+  out8[4] = out8[5] = out8[6] = out8[7] = 0;
+  return NBODY_OK;
+}
+
+void nbody_destroy(nbody_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int nbody_profile(nbody_ctx *c, int enable) {
+  if (!c) return fail(NBODY_EINVAL, "context is NULL");
+  if (enable && c->ev.empty()) {
+    c->ev.assign(2 * kEvPairs, nullptr);
+    for (auto &e : c->ev) NB_HIP(hipEventCreate(&e));
+  }
+  if (!enable && c->profiling) {
+    int rc = harvest_events(c);
+    if (rc) return rc;
+  }
+  c->profiling = enable != 0;
+  return NBODY_OK;
+}
+
+int nbody_profile_read(nbody_ctx *c, double *force_ms, int64_t *force_launches) {
+  if (!c) return fail(NBODY_EINVAL, "context is NULL");
+  int rc = harvest_events(c);
+  if (rc) return rc;
+  if (force_ms) *force_ms = c->prof_ms;
+  if (force_launches) *force_launches = c->prof_launches;
+  c->prof_ms = 0.0;
+  c->prof_launches = 0;
+  return NBODY_OK;
+}
+
+const char *nbody_strerror(int code) {
+  switch (code) {
+    case NBODY_OK: return "success";
+    case NBODY_EINVAL: return "invalid argument";
+    case NBODY_ENODEV: return "no usable HIP device";
+    case NBODY_ENOMEM: return "workspace too small";
+    case NBODY_EHIP: return "HIP runtime error";
+    case NBODY_EINDEX: return "index out of range or i_active not grouped by cluster";
+    case NBODY_ENONFINITE: return "non-finite value";
+    case NBODY_EDOMAIN: return "coincident particles with zero softening";
+    default: return "unknown error";
+  }
+}
+
+const char *nbody_last_error(void) { return g_last_error.c_str(); }
+
+int nbody_get_tuning(const nbody_ctx *c, nbody_tuning *t) {
+  if (!c || !t) return fail(NBODY_EINVAL, "NULL argument");
+  *t = c->tune;
+  return NBODY_OK;
+}
+
+int nbody_set_tuning(nbody_ctx *c, const nbody_tuning *t) {
+  if (!c || !t) return fail(NBODY_EINVAL, "NULL argument");
+  nbody_tuning n = c->tune;
+  if (t->variant) {
+    if (t->variant != NBODY_VARIANT_K1 && t->variant != NBODY_VARIANT_K2)
+      return fail(NBODY_EINVAL, "unknown variant");
+    n.variant = t->variant;
+  }
+  if (t->use_graph) {
+    if (t->use_graph != NBODY_GRAPH_ON && t->use_graph != NBODY_GRAPH_OFF)
+      return fail(NBODY_EINVAL, "use_graph must be NBODY_GRAPH_ON or NBODY_GRAPH_OFF");
+    n.use_graph = t->use_graph;
+  }
+  if (t->steps_per_launch) {
+    if (t->steps_per_launch < 1 || t->steps_per_launch > 1024)
+      return fail(NBODY_EINVAL, "steps_per_launch must be in [1, 1024]");
+    n.steps_per_launch = t->steps_per_launch;
+  }
+  if (t->min_split_j) {
+    if (t->min_split_j < 64) return fail(NBODY_EINVAL, "min_split_j must be >= 64");
+    n.min_split_j = t->min_split_j;
+  }
+  for (int b = 0; b < NBODY_TUNE_BUCKETS; ++b) {
+    if (t->i_slots[b]) {
+      const int P = t->i_slots[b];
+      if (P < 1 || P > 256 || (P & (P - 1))) return fail(NBODY_EINVAL, "i_slots must be a power of two in [1, 256]");
+      n.i_slots[b] = P;
+    }
+    if (t->target_items[b]) {
+      if (t->target_items[b] < 1 || t->target_items[b] > 65536)
+        return fail(NBODY_EINVAL, "target_items must be in [1, 65536]");
+      n.target_items[b] = t->target_items[b];
+    }
+  }
+  c->tune = n;
+  drop_graph(c);
+  return refresh_grids(c);
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// Internal types shared by the host runtime (nbody_api.cpp) and the device
+// kernels (nbody_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace nbk {
+
+constexpr int kWG = 256;            // threads per workgroup of every kernel
+constexpr int kTJ = 256;            // j records per LDS tile of the force kernel
+constexpr int kTickBits = 20;       // one time unit = 2^20 ticks
+constexpr int kLevels = 21;         // levels 0..20, step 2^-level
+constexpr int kMaxClusters = 4096;
+constexpr int kScanBlock = 1024;    // particles per block of the compaction
+constexpr int kBuckets = 25;        // tuning buckets floor(log2(n_active))
+constexpr int kNoActive = 99;       // threshold level meaning "nothing due"
+constexpr int kRowStride = 6;       // doubles per partial row: a(3), jerk(3)
+
+enum ErrBits : int32_t { kErrNonFinite = 1, kErrDomain = 2, kErrIndex = 4 };
+
+// counters in Dev::ctr
+enum Ctr : int {
+  kCtrSteps = 0,        // block-step iterations with work
+  kCtrInter = 1,        // sum of n_active * n_cluster
+  kCtrFloor = 2,        // steps clamped at 2^-level_max
+  kCtrNotDone = 3,      // clusters still short of t_end after the last step
+  kCtrTend = 4,         // t_end in ticks for nbody_step
+  kCtrCount = 8
+};
+
+// Per-cluster launch plan of one force evaluation.  Built on the device by
+// k_plan so that a captured graph adapts to the active-set sizes.
+struct ClusterPlan {
+  int32_t c;        // cluster id
+  int32_t P;        // i thread-slots per workgroup (power of two, 1..256)
+  int32_t Qlog;     // log2 of j-lanes per i slot (Q = 256 / P)
+  int32_t S;        // j splits
+  int32_t na;       // active particles of the cluster
+  int32_t act_off;  // their offset in the active list
+  int32_t tiles;    // i tiles = ceil(na / (P * K))
+  int32_t items;    // tiles * S
+  int64_t row_off;  // first partial row of the cluster
+  int64_t jb, je;   // j range [jb, je)
+  int64_t chunk;    // j per split (multiple of kTJ)
+  int64_t t_pred;   // tick every particle of the cluster is predicted to
+};
+
+struct Tuning {     // device copy of the launch policy (passed by value)
+  int32_t i_slots[kBuckets];
+  int32_t target_items[kBuckets];
+  int32_t min_split_j;
+  int32_t K;        // i-particles per thread slot (1 or 2)
+};
+
+// Device pointers carved from the caller's workspace.
+struct Dev {
+  int64_t n;
+  int32_t C;
+  int32_t nblk;        // compaction blocks = ceil(n / kScanBlock)
+  int64_t rows_cap;    // partial rows available
+  int64_t cap_active;  // entries of the active list
+  // particle state, component-major SoA: x[c * n + i]
+  double *x, *v, *a, *j;
+  double *m;
+  int64_t *tick;
+  int32_t *level;
+  int32_t *cid;
+  // clusters
+  int64_t *coff;       // C + 1
+  double *eps2;        // C
+  int64_t *T;          // C: current time
+  int64_t *Tnext;      // C: time of the block step being taken
+  int32_t *Lthr;       // C: levels >= Lthr are due at Tnext
+  int32_t *hist;       // C * kLevels: particles per level
+  // active list and compaction
+  int32_t *active;     // cap_active
+  int32_t *act_off;    // C + 1
+  int32_t *blk_cnt;    // nblk
+  int32_t *blk_off;    // nblk + 1
+  // plan
+  ClusterPlan *plan_c;    // C, by cluster id
+  ClusterPlan *plan_lpt;  // C, largest item cost first
+  int32_t *item_prefix;   // C + 1 (LPT order)
+  double *partial;        // rows_cap * kRowStride
+  // words
+  int32_t *work;       // item counter of the persistent force kernel
+  int32_t *err;        // sticky error bits
+  int64_t *ctr;        // kCtrCount counters
+  double *eout;        // C * 9 energy output
+};
+
+// Where the force kernel takes j (and i) particles from.
+enum Source : int { kSrcState = 0, kSrcRaw = 1 };
+// What the force kernel computes.
+enum Mode : int { kModeFP64 = 0, kModeMixed = 1, kModePot = 2 };
+
+// Host-side launchers (defined in nbody_kernels.hip).  Every launcher only
+// enqueues on `s`; none synchronises.  They return the hipError_t of the
+// launch.
+struct RawSrc {                 // caller arrays for nbody_forces
+  const double *x, *v, *m;     // (n_j, 3), (n_j, 3), (n_j)
+  int64_t n_j;                 // j count (single cluster) or 0 (use coff)
+  const int32_t *i_active;     // n_active indices
+  int64_t n_active;
+  double *acc, *jerk;          // (n_active, 3) outputs
+};
+
+hipError_t launch_init_state(const Dev &d, const double *m, const double *x,
+                             const double *v, hipStream_t s);
+hipError_t launch_all_active(const Dev &d, hipStream_t s);
+hipError_t launch_sched(const Dev &d, hipStream_t s);
+hipError_t launch_compact(const Dev &d, hipStream_t s);
+hipError_t launch_plan(const Dev &d, const Tuning &t, int use_T,
+                       int64_t api_nj, hipStream_t s);
+hipError_t launch_force(const Dev &d, int mode, int src, int K,
+                        const RawSrc *raw, int grid, hipStream_t s);
+hipError_t launch_correct(const Dev &d, double eta, double dt_shared,
+                          int level_min, int level_max, hipStream_t s);
+hipError_t launch_init_levels(const Dev &d, double eta_start,
+                              double dt_shared, int level_min, int level_max,
+                              hipStream_t s);
+hipError_t launch_api_group(const Dev &d, const RawSrc &r, hipStream_t s);
+hipError_t launch_api_finalize(const Dev &d, const RawSrc &r, hipStream_t s);
+hipError_t launch_energy_reduce(const Dev &d, hipStream_t s);
+hipError_t launch_set_word64(int64_t *p, int64_t v, hipStream_t s);
+hipError_t launch_fill32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_get_state(const Dev &d, double *x, double *v, double *a,
+                            double *jk, int64_t *tick, int8_t *level,
+                            hipStream_t s);
+hipError_t launch_set_state(const Dev &d, const double *x, const double *v,
+                            const double *a, const double *jk,
+                            const int64_t *tick, const int8_t *level,
+                            int level_min, int level_max, hipStream_t s);
+// persistent grid size of the force kernel (workgroups resident at once)
+int force_grid_size(int mode, int src, int K, int device);
+
+}  // namespace nbk

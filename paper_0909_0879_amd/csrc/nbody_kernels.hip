@@ -1,0 +1,1213 @@
+// HIP kernels of the direct N-body hot path for gfx950 (MI355X).
+//
+// Force law: eq. (1) of the paper (Sect. 2) with G = 1 and the Plummer
+// softened pair potential phi = -m / sqrt(r^2 + eps^2) (softening, Sect. 4),
+// plus the jerk (time derivative of the acceleration):
+//   a_i = sum_j m_j r_ij s^-3/2,
+//   j_i = sum_j m_j [v_ij s^-3/2 - 3 (r_ij . v_ij) r_ij s^-5/2],
+//   r_ij = x_j - x_i, v_ij = v_j - v_i, s = |r_ij|^2 + eps^2.
+// Integration: fourth-order Hermite predictor-corrector on power-of-two
+// block time steps (individual time steps, Sect. 3) with Aarseth's step
+// criterion.
+//
+// Kernel layout on CDNA4:
+//  * the force kernel is persistent: each 256-thread workgroup pulls work
+//    items (cluster, i-tile, j-split) from an atomic counter; items are
+//    ordered largest cost first (k_plan), so uneven clusters balance;
+//  * i-particles sit in registers, K per thread slot; j-particles are
+//    predicted while being copied, coalesced, from the SoA state in HBM into
+//    a 256-record LDS tile and are read back as broadcasts;
+//  * small active sets put several lanes on one i (P i-slots x Q j-lanes,
+//    P * Q = 256) and split j over workgroups; lanes are reduced with
+//    wavefront shuffles in a fixed tree and splits by the corrector in a
+//    fixed order, so every result is deterministic;
+//  * FP64 mode accumulates each tile in FP64 and folds it into a TwoSum
+//    (hi, lo) pair; mixed mode forms x_j - x_i and v_j - v_i in FP64,
+//    converts them to FP32, does rsqrt, r^-3 and the jerk products in FP32
+//    and folds each tile's FP32 sums into an FP32 TwoSum (hi, lo) pair.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "nbody_internal.h"
+
+namespace nbk {
+
+namespace {
+
+constexpr double kTick = 1.0 / (double)(1 << kTickBits);
+
+// ------------------------------------------------------------ helpers
+
+__device__ __forceinline__ double rsq64(double s) {
+  // hardware reciprocal square root refined by one third-order Newton step
+  // y1 = y (1 + e/2 + 3 e^2/8), e = 1 - s y^2 (Newton-Raphson on x^2 = r^2,
+  // the square-root method the paper mentions in Sect. 3)
+  const double y = __builtin_amdgcn_rsq(s);
+  const double e = fma(-s, y * y, 1.0);
+  return fma(y * e, fma(0.375, e, 0.5), y);
+}
+
+template <class T>
+__device__ __forceinline__ void two_sum_into(T &hi, T &lo, T t) {
+  const T s = hi + t;
+  const T bp = s - hi;
+  const T err = (hi - (s - bp)) + (t - bp);
+  hi = s;
+  lo += err;
+}
+
+// Hermite predictor, Taylor series to the jerk term (Horner form).
+__device__ __forceinline__ void predict(double x, double v, double a, double j,
+                                        double dt, double &xp, double &vp) {
+  xp = x + dt * (v + dt * (0.5 * a + dt * (j / 6.0)));
+  vp = v + dt * (a + dt * (0.5 * j));
+}
+
+__device__ __forceinline__ void predict_state(const Dev &d, int64_t i,
+                                              int64_t t_pred, double xp[3],
+                                              double vp[3]) {
+  const int64_t n = d.n;
+  const double dt = (double)(t_pred - d.tick[i]) * kTick;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    predict(d.x[c * n + i], d.v[c * n + i], d.a[c * n + i], d.j[c * n + i], dt,
+            xp[c], vp[c]);
+}
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Deterministic 256-thread block sum of an int (wave sums, then LDS).
+__device__ int block_sum_i(int v, int *sh4) {
+  v = wave_sum_i(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh4[w] = v;
+  __syncthreads();
+  const int tot = sh4[0] + sh4[1] + sh4[2] + sh4[3];
+  __syncthreads();
+  return tot;
+}
+
+__device__ __forceinline__ int find_cluster(const int64_t *coff, int C,
+                                            int64_t i) {
+  int lo = 0, hi = C;   // coff[lo] <= i < coff[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (coff[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+struct JRec {            // one j-particle in LDS, 64 bytes
+  double x, y, z, m;
+  double vx, vy, vz;
+  float mf;
+  int32_t idx;
+};
+
+// ------------------------------------------------------------ pair terms
+
+template <bool MASK>
+__device__ __forceinline__ void pair_fp64(const double *xi, const double *vi,
+                                          int iidx, const JRec &r, double eps2,
+                                          double *t, int &dom) {
+  const double dx = r.x - xi[0], dy = r.y - xi[1], dz = r.z - xi[2];
+  const double wx = r.vx - vi[0], wy = r.vy - vi[1], wz = r.vz - vi[2];
+  const double s = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+  const double rv = fma(dx, wx, fma(dy, wy, dz * wz));
+  double rinv = rsq64(s);
+  if (MASK) {
+    if (s == 0.0) {
+      rinv = 0.0;
+      dom |= (r.idx != iidx);
+    }
+  }
+  const double rinv2 = rinv * rinv;
+  const double mr3 = (r.m * rinv) * rinv2;
+  const double al = (3.0 * rv) * rinv2;
+  t[0] = fma(mr3, dx, t[0]);
+  t[1] = fma(mr3, dy, t[1]);
+  t[2] = fma(mr3, dz, t[2]);
+  t[3] = fma(mr3, fma(-al, dx, wx), t[3]);
+  t[4] = fma(mr3, fma(-al, dy, wy), t[4]);
+  t[5] = fma(mr3, fma(-al, dz, wz), t[5]);
+}
+
+template <bool MASK>
+__device__ __forceinline__ void pair_mixed(const double *xi, const double *vi,
+                                           int iidx, const JRec &r, float eps2,
+                                           float *t, int &dom) {
+  const double dxd = r.x - xi[0], dyd = r.y - xi[1], dzd = r.z - xi[2];
+  const float dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
+  const float wx = (float)(r.vx - vi[0]);
+  const float wy = (float)(r.vy - vi[1]);
+  const float wz = (float)(r.vz - vi[2]);
+  const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+  const float rv = fmaf(dx, wx, fmaf(dy, wy, dz * wz));
+  float rinv = __builtin_amdgcn_rsqf(s);
+  if (MASK) {
+    if (dxd == 0.0 && dyd == 0.0 && dzd == 0.0) {
+      rinv = 0.0f;
+      dom |= (r.idx != iidx);
+    }
+  }
+  const float rinv2 = rinv * rinv;
+  const float mr3 = (r.mf * rinv) * rinv2;
+  const float al = (3.0f * rv) * rinv2;
+  t[0] = fmaf(mr3, dx, t[0]);
+  t[1] = fmaf(mr3, dy, t[1]);
+  t[2] = fmaf(mr3, dz, t[2]);
+  t[3] = fmaf(mr3, fmaf(-al, dx, wx), t[3]);
+  t[4] = fmaf(mr3, fmaf(-al, dy, wy), t[4]);
+  t[5] = fmaf(mr3, fmaf(-al, dz, wz), t[5]);
+}
+
+__device__ __forceinline__ void pair_pot(const double *xi, int iidx,
+                                         const JRec &r, double eps2,
+                                         double *t) {
+  const double dx = r.x - xi[0], dy = r.y - xi[1], dz = r.z - xi[2];
+  const double s = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+  const double rinv = (r.idx == iidx) ? 0.0 : 1.0 / sqrt(s);
+  t[0] = fma(-r.m, rinv, t[0]);
+}
+
+template <int MODE>
+struct AccT { using T = double; static constexpr int NC = 6; };
+template <>
+struct AccT<kModeMixed> { using T = float; static constexpr int NC = 6; };
+template <>
+struct AccT<kModePot> { using T = double; static constexpr int NC = 1; };
+
+// One LDS tile against K i-particles.  WIDE: every lane owns its i (Q = 1);
+// otherwise lane q of a slot takes records q, q + Q, ...
+template <int MODE, int K, bool WIDE, bool MASK>
+__device__ __forceinline__ void tile_loop(
+    const JRec *tile, int cnt, int q, int Q, const double (&xi)[K][3],
+    const double (&vi)[K][3], const int (&iidx)[K], double eps2,
+    typename AccT<MODE>::T (&t)[K][AccT<MODE>::NC], int (&dom)[K]) {
+  const int j0 = WIDE ? 0 : q;
+  const int js = WIDE ? 1 : Q;
+  if (MODE == kModeMixed) {
+    const float e2 = (float)eps2;
+#pragma unroll 2
+    for (int jj = j0; jj < cnt; jj += js) {
+      const JRec r = tile[jj];
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        pair_mixed<MASK>(xi[k], vi[k], iidx[k], r, e2, (float *)t[k], dom[k]);
+    }
+  } else if (MODE == kModeFP64) {
+#pragma unroll 2
+    for (int jj = j0; jj < cnt; jj += js) {
+      const JRec r = tile[jj];
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        pair_fp64<MASK>(xi[k], vi[k], iidx[k], r, eps2, (double *)t[k], dom[k]);
+    }
+  } else {
+    for (int jj = j0; jj < cnt; jj += js) {
+      const JRec r = tile[jj];
+#pragma unroll
+      for (int k = 0; k < K; ++k) pair_pot(xi[k], iidx[k], r, eps2, (double *)t[k]);
+    }
+  }
+}
+
+struct ForceArgs {
+  Dev d;
+  const int32_t *active;        // active list (internal or the caller's)
+  const double *rx, *rv, *rm;   // raw source (nbody_forces)
+};
+
+// ------------------------------------------------------------ force kernel
+
+template <int MODE, int SRC, int K>
+__global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
+  using T = typename AccT<MODE>::T;
+  constexpr int NC = AccT<MODE>::NC;
+  __shared__ JRec tile[kTJ];
+  __shared__ double red[kWG / 64][K][NC];
+  __shared__ int s_g;
+  const Dev &d = A.d;
+  const int tid = threadIdx.x;
+  const int n_items = d.item_prefix[d.C];
+  for (;;) {
+    if (tid == 0) s_g = atomicAdd(d.work, 1);
+    __syncthreads();
+    const int g = s_g;
+    __syncthreads();
+    if (g >= n_items) break;
+    int lo = 0, hi = d.C;   // item_prefix[lo] <= g < item_prefix[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (d.item_prefix[mid] <= g) lo = mid; else hi = mid;
+    }
+    const ClusterPlan cp = d.plan_lpt[lo];
+    const int t_item = g - d.item_prefix[lo];
+    const int tile_i = t_item / cp.S;
+    const int split = t_item - tile_i * cp.S;
+    const int64_t js = cp.jb + (int64_t)split * cp.chunk;
+    const int64_t je = (js + cp.chunk < cp.je) ? js + cp.chunk : cp.je;
+    const int Qlog = cp.Qlog;
+    const int Q = 1 << Qlog;
+    const int p = tid >> Qlog;
+    const int q = tid & (Q - 1);
+    const double eps2 = d.eps2[cp.c];
+
+    double xi[K][3], vi[K][3];
+    int iidx[K], dom[K];
+    bool ok[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int slot = tile_i * cp.P * K + k * cp.P + p;
+      ok[k] = slot < cp.na;
+      iidx[k] = ok[k] ? A.active[cp.act_off + slot] : -1;
+      dom[k] = 0;
+      if (SRC == kSrcRaw && ok[k] && (iidx[k] < cp.jb || iidx[k] >= cp.je)) {
+        ok[k] = false;
+        if (q == 0 && split == 0) atomicOr(d.err, (int)kErrIndex);
+      }
+      if (!ok[k]) {
+        iidx[k] = -1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xi[k][c] = vi[k][c] = 0.0;
+      } else if (SRC == kSrcState) {
+        predict_state(d, iidx[k], cp.t_pred, xi[k], vi[k]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          xi[k][c] = A.rx[3 * (int64_t)iidx[k] + c];
+          vi[k][c] = A.rv[3 * (int64_t)iidx[k] + c];
+        }
+      }
+    }
+    T t[K][NC], shi[K][NC], slo[K][NC];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) t[k][c] = shi[k][c] = slo[k][c] = (T)0;
+
+    const bool mask = (eps2 == 0.0);
+    for (int64_t jt = js; jt < je; jt += kTJ) {
+      const int cnt = (int)((je - jt < kTJ) ? je - jt : kTJ);
+      if (tid < cnt) {
+        const int64_t j = jt + tid;
+        JRec r;
+        double xp[3], vp[3];
+        if (SRC == kSrcState) {
+          predict_state(d, j, cp.t_pred, xp, vp);
+          r.m = d.m[j];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            xp[c] = A.rx[3 * j + c];
+            vp[c] = A.rv[3 * j + c];
+          }
+          r.m = A.rm[j];
+        }
+        r.x = xp[0]; r.y = xp[1]; r.z = xp[2];
+        r.vx = vp[0]; r.vy = vp[1]; r.vz = vp[2];
+        r.mf = (float)r.m;
+        r.idx = (int32_t)j;
+        tile[tid] = r;
+      }
+      __syncthreads();
+      if (Q == 1) {
+        if (mask || MODE == kModePot)
+          tile_loop<MODE, K, true, true>(tile, cnt, q, Q, xi, vi, iidx, eps2, t, dom);
+        else
+          tile_loop<MODE, K, true, false>(tile, cnt, q, Q, xi, vi, iidx, eps2, t, dom);
+      } else {
+        if (mask || MODE == kModePot)
+          tile_loop<MODE, K, false, true>(tile, cnt, q, Q, xi, vi, iidx, eps2, t, dom);
+        else
+          tile_loop<MODE, K, false, false>(tile, cnt, q, Q, xi, vi, iidx, eps2, t, dom);
+      }
+      // fold the tile sums into the compensated running sums
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          two_sum_into(shi[k][c], slo[k][c], t[k][c]);
+          t[k][c] = (T)0;
+        }
+      __syncthreads();
+    }
+
+    // combine hi + lo in FP64, reduce the Q lanes of a slot in a fixed tree
+    double res[K][NC];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) res[k][c] = (double)shi[k][c] + (double)slo[k][c];
+      if (ok[k] && dom[k]) atomicOr(d.err, (int)kErrDomain);
+    }
+    if (Q > 1) {
+      const int qw = Q < 64 ? Q : 64;
+      for (int off = 1; off < qw; off <<= 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) res[k][c] += __shfl_xor(res[k][c], off);
+      }
+      if (Q > 64) {
+        const int w = tid >> 6;
+        if ((tid & 63) == 0) {
+#pragma unroll
+          for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) red[w][k][c] = res[k][c];
+        }
+        __syncthreads();
+        if (q == 0) {
+          const int nw = Q >> 6;   // waves of this slot: w0 .. w0 + nw - 1
+#pragma unroll
+          for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              double s = red[w][k][c];
+              for (int u = 1; u < nw; ++u) s += red[w + u][k][c];
+              res[k][c] = s;
+            }
+        }
+        __syncthreads();
+      }
+    }
+    if (q == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int slot = tile_i * cp.P * K + k * cp.P + p;
+        if (slot < cp.na) {
+          double *row = d.partial + (cp.row_off + (int64_t)split * cp.na + slot) * kRowStride;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) row[c] = ok[k] ? res[k][c] : 0.0;
+        }
+      }
+    }
+  }
+}
+
+// Sum the S partial rows of one active slot in split order (Neumaier).
+__device__ __forceinline__ void sum_rows(const Dev &d, const ClusterPlan &cp,
+                                         int slot, int nc, double *out) {
+  double s[6], cc[6];
+  for (int c = 0; c < nc; ++c) s[c] = cc[c] = 0.0;
+  for (int sp = 0; sp < cp.S; ++sp) {
+    const double *row = d.partial + (cp.row_off + (int64_t)sp * cp.na + slot) * kRowStride;
+    for (int c = 0; c < nc; ++c) {
+      const double x = row[c];
+      const double u = s[c] + x;
+      cc[c] += (fabs(s[c]) >= fabs(x)) ? (s[c] - u) + x : (x - u) + s[c];
+      s[c] = u;
+    }
+  }
+  for (int c = 0; c < nc; ++c) out[c] = s[c] + cc[c];
+}
+
+__device__ __forceinline__ bool finite3(const double *a) {
+  return isfinite(a[0]) && isfinite(a[1]) && isfinite(a[2]);
+}
+
+__device__ __forceinline__ double norm3(const double *a) {
+  return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+}
+
+// Aarseth's criterion sqrt(eta (|a||a2| + |j|^2) / (|j||a3| + |a2|^2)).
+__device__ double aarseth_dt(const double *a, const double *j, const double *a2,
+                             const double *a3, double eta) {
+  const double na = norm3(a), nj = norm3(j), n2 = norm3(a2), n3 = norm3(a3);
+  const double num = na * n2 + nj * nj;
+  const double den = nj * n3 + n2 * n2;
+  if (den == 0.0) return INFINITY;
+  return sqrt(eta * num / den);
+}
+
+// Power-of-two block rule: halve until <= dt_c (floor at level_max,
+// counted); double once when dt_c >= 2 dt and t is a multiple of 2 dt and
+// the doubled step stays within level_min.
+__device__ int next_level(int level, double dt_c, int64_t t_tick, int lmin,
+                          int lmax, int &floor_hit) {
+  double dt = ldexp(1.0, -level);
+  if (dt_c < dt) {
+    while (dt > dt_c && level < lmax) {
+      ++level;
+      dt *= 0.5;
+    }
+    floor_hit = (dt > dt_c);
+    return level;
+  }
+  floor_hit = 0;
+  if (level > lmin && dt_c >= 2.0 * dt) {
+    const int64_t two = (int64_t)1 << (kTickBits - level + 1);
+    if (t_tick % two == 0) --level;
+  }
+  return level;
+}
+
+__device__ int initial_level(const double *a, const double *j, double eta_s,
+                             int lmin, int lmax, int &floor_hit) {
+  const double na = norm3(a), nj = norm3(j);
+  const double dt0 = (nj == 0.0) ? INFINITY : eta_s * na / nj;
+  int level = lmin;
+  double dt = ldexp(1.0, -level);
+  while (dt > dt0 && level < lmax) {
+    ++level;
+    dt *= 0.5;
+  }
+  floor_hit = (dt > dt0);
+  return level;
+}
+
+// ------------------------------------------------------------ O(N) kernels
+
+__global__ void k_init_state(Dev d, const double *m, const double *x,
+                             const double *v) {
+  const int64_t n = d.n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      d.x[c * n + i] = x[3 * i + c];
+      d.v[c * n + i] = v[3 * i + c];
+      d.a[c * n + i] = 0.0;
+      d.j[c * n + i] = 0.0;
+    }
+    d.m[i] = m[i];
+    d.tick[i] = 0;
+    d.level[i] = 0;
+    d.cid[i] = find_cluster(d.coff, d.C, i);
+  }
+  const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gt < d.C) {
+    d.T[gt] = 0;
+    d.Tnext[gt] = 0;
+    d.Lthr[gt] = 0;
+  }
+  if (gt < (int64_t)d.C * kLevels) d.hist[gt] = 0;
+  if (gt < kCtrCount) d.ctr[gt] = 0;
+  if (gt == 0) *d.err = 0;
+}
+
+__global__ void k_all_active(Dev d) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < d.n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d.active[i] = (int32_t)i;
+  const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gt <= d.C) d.act_off[gt] = (int32_t)d.coff[gt];
+}
+
+// Per cluster: T_next = next multiple of the finest present step after T,
+// threshold level L = 20 - ctz(T_next) (particles on levels >= L are due).
+__global__ void k_sched(Dev d) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= d.C) return;
+  const int64_t T = d.T[c];
+  const int64_t tend = d.ctr[kCtrTend];
+  if (T >= tend || *d.err != 0) {
+    d.Tnext[c] = T;
+    d.Lthr[c] = kNoActive;
+    return;
+  }
+  int lmax = -1;
+  for (int l = kLevels - 1; l >= 0; --l)
+    if (d.hist[c * kLevels + l] > 0) { lmax = l; break; }
+  if (lmax < 0) {
+    d.Tnext[c] = T;
+    d.Lthr[c] = kNoActive;
+    return;
+  }
+  const int64_t dtl = (int64_t)1 << (kTickBits - lmax);
+  const int64_t tn = (T / dtl + 1) * dtl;
+  int L = kTickBits - __builtin_ctzll((unsigned long long)tn);
+  if (L < 0) L = 0;
+  d.Tnext[c] = tn;
+  d.Lthr[c] = L;
+}
+
+__global__ __launch_bounds__(kWG) void k_count(Dev d) {
+  __shared__ int sh[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
+  int cnt = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = base + e;
+    if (i < d.n && d.level[i] >= d.Lthr[d.cid[i]]) ++cnt;
+  }
+  cnt = block_sum_i(cnt, sh);
+  if (threadIdx.x == 0) d.blk_cnt[blockIdx.x] = cnt;
+}
+
+// Exclusive scan of nblk block counts by one 1024-thread workgroup.
+__global__ __launch_bounds__(1024) void k_scan(Dev d) {
+  __shared__ int sh[1024];
+  int carry = 0;
+  for (int base = 0; base < d.nblk; base += 1024) {
+    const int i = base + threadIdx.x;
+    const int v = (i < d.nblk) ? d.blk_cnt[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int add = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (i < d.nblk) d.blk_off[i] = carry + sh[threadIdx.x] - v;
+    carry += sh[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) d.blk_off[d.nblk] = carry;
+}
+
+// Ordered compaction: active list ascending in particle index, and each
+// cluster's offset in it.
+__global__ __launch_bounds__(kWG) void k_scatter(Dev d) {
+  __shared__ int wsum[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
+  int flag[4];
+  int cnt = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = base + e;
+    flag[e] = (i < d.n && d.level[i] >= d.Lthr[d.cid[i]]) ? 1 : 0;
+    cnt += flag[e];
+  }
+  // exclusive scan of cnt over the block, in thread order
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int incl = cnt;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int wbase = 0;
+  for (int u = 0; u < w; ++u) wbase += wsum[u];
+  int pos = d.blk_off[blockIdx.x] + wbase + incl - cnt;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = base + e;
+    if (i < d.n) {
+      const int c = d.cid[i];
+      if (d.coff[c] == i) d.act_off[c] = pos;
+      if (flag[e]) d.active[pos++] = (int32_t)i;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) d.act_off[d.C] = d.blk_off[d.nblk];
+}
+
+// Launch plan for every cluster, in one 1024-thread workgroup.
+// kind 0: block step (predict to T_next, commit T = T_next, count);
+// kind 1: init / energy (predict to T); kind 2: nbody_forces (raw source).
+__global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
+                                                int64_t api_nj) {
+  __shared__ int64_t cost[kMaxClusters];
+  __shared__ int64_t scan64[1024];
+  const int C = d.C;
+  const int K = tu.K;
+  int64_t my_inter = 0;
+  int my_active = 0, my_notdone = 0;
+  for (int c = threadIdx.x; c < C; c += 1024) {
+    ClusterPlan cp;
+    cp.c = c;
+    cp.act_off = d.act_off[c];
+    cp.na = d.act_off[c + 1] - cp.act_off;
+    if (kind == 2 && C == 1 && api_nj > 0) {
+      cp.jb = 0;
+      cp.je = api_nj;
+    } else {
+      cp.jb = d.coff[c];
+      cp.je = d.coff[c + 1];
+    }
+    const int64_t nc = cp.je - cp.jb;
+    cp.t_pred = (kind == 0) ? d.Tnext[c] : d.T[c];
+    cp.P = 256;
+    cp.Qlog = 0;
+    cp.S = 0;
+    cp.tiles = 0;
+    cp.items = 0;
+    cp.chunk = kTJ;
+    cp.row_off = 0;
+    if (cp.na > 0 && nc > 0) {
+      int b = 31 - __builtin_clz((unsigned)cp.na);
+      if (b >= kBuckets) b = kBuckets - 1;
+      int P = tu.i_slots[b];
+      if (P < 1) P = 1;
+      if (P > 256) P = 256;
+      P = 1 << (31 - __builtin_clz((unsigned)P));      // power of two
+      cp.P = P;
+      cp.Qlog = 8 - (31 - __builtin_clz((unsigned)P));
+      const int64_t ipt = (int64_t)P * K;
+      const int64_t tiles = (cp.na + ipt - 1) / ipt;
+      int64_t target = tu.target_items[b] > 0 ? tu.target_items[b] : 1;
+      int64_t S = (target + tiles - 1) / tiles;
+      const int64_t mj = tu.min_split_j > 0 ? tu.min_split_j : 64;
+      const int64_t s_j = (nc + mj - 1) / mj;
+      if (S > s_j) S = s_j;
+      // partial rows of a cluster: at most 4 per j-particle (so an ensemble
+      // needs at most 4 n rows, and a cluster splits the same way alone or
+      // in an ensemble), and never more than the workspace holds
+      int64_t rowcap = 4 * nc;
+      if (rowcap > d.rows_cap) rowcap = d.rows_cap;
+      const int64_t s_r = rowcap / cp.na;
+      if (S > s_r) S = s_r;
+      if (S < 1) S = 1;
+      int64_t chunk = (nc + S - 1) / S;
+      chunk = ((chunk + kTJ - 1) / kTJ) * kTJ;
+      S = (nc + chunk - 1) / chunk;
+      cp.S = (int32_t)S;
+      cp.chunk = chunk;
+      cp.tiles = (int32_t)tiles;
+      cp.items = (int32_t)(tiles * S);
+      my_inter += (int64_t)cp.na * nc;
+      my_active += cp.na;
+    }
+    if (kind == 0) {
+      if (d.Tnext[c] < d.ctr[kCtrTend]) ++my_notdone;
+    }
+    d.plan_c[c] = cp;
+    cost[c] = cp.items > 0 ? (int64_t)cp.P * K * cp.chunk : -1;
+  }
+  __syncthreads();
+  // row offsets in cluster order
+  int64_t carry = 0;
+  for (int base = 0; base < C; base += 1024) {
+    const int c = base + threadIdx.x;
+    const int64_t r = (c < C) ? (int64_t)d.plan_c[c].S * d.plan_c[c].na : 0;
+    scan64[threadIdx.x] = r;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int64_t add = (threadIdx.x >= off) ? scan64[threadIdx.x - off] : 0;
+      __syncthreads();
+      scan64[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (c < C) d.plan_c[c].row_off = carry + scan64[threadIdx.x] - r;
+    carry += scan64[1023];
+    __syncthreads();
+  }
+  // largest item cost first; ties by cluster id
+  for (int c = threadIdx.x; c < C; c += 1024) {
+    const int64_t mc = cost[c];
+    int rank = 0;
+    for (int u = 0; u < C; ++u) {
+      const int64_t o = cost[u];
+      rank += (o > mc) || (o == mc && u < c);
+    }
+    d.plan_lpt[rank] = d.plan_c[c];
+  }
+  __syncthreads();
+  carry = 0;
+  for (int base = 0; base < C; base += 1024) {
+    const int r = base + threadIdx.x;
+    const int64_t it = (r < C) ? d.plan_lpt[r].items : 0;
+    scan64[threadIdx.x] = it;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int64_t add = (threadIdx.x >= off) ? scan64[threadIdx.x - off] : 0;
+      __syncthreads();
+      scan64[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (r < C) d.item_prefix[r] = (int32_t)(carry + scan64[threadIdx.x] - it);
+    carry += scan64[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    d.item_prefix[C] = (int32_t)carry;
+    *d.work = 0;
+  }
+  if (kind == 0) {
+    for (int c = threadIdx.x; c < C; c += 1024) d.T[c] = d.Tnext[c];
+    // block totals (deterministic: integer atomics)
+    if (my_inter) atomicAdd((unsigned long long *)&d.ctr[kCtrInter],
+                            (unsigned long long)my_inter);
+    __shared__ int any_active, notdone;
+    if (threadIdx.x == 0) { any_active = 0; notdone = 0; }
+    __syncthreads();
+    if (my_active) atomicAdd(&any_active, my_active);
+    if (my_notdone) atomicAdd(&notdone, my_notdone);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (any_active) d.ctr[kCtrSteps] += 1;
+      d.ctr[kCtrNotDone] = notdone;
+    }
+  }
+}
+
+// Hermite-4 correction of every active particle, new level, bookkeeping.
+__global__ __launch_bounds__(kWG) void k_correct(Dev d, double eta,
+                                                 double dt_shared, int lmin,
+                                                 int lmax) {
+  const int64_t n = d.n;
+  const int total = d.act_off[d.C];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < total;
+       k += gridDim.x * blockDim.x) {
+    const int64_t i = d.active[k];
+    const int c = d.cid[i];
+    const ClusterPlan cp = d.plan_c[c];
+    const int slot = k - cp.act_off;
+    double f[6];
+    sum_rows(d, cp, slot, 6, f);
+    const int64_t tn = cp.t_pred;
+    const double h = (double)(tn - d.tick[i]) * kTick;
+    const double h2 = h * h, h3 = h2 * h;
+    double x1[3], v1[3], a2e[3], a3v[3], a1[3], j1[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double xp, vp;
+      const double a0 = d.a[q * n + i], j0 = d.j[q * n + i];
+      predict(d.x[q * n + i], d.v[q * n + i], a0, j0, h, xp, vp);
+      a1[q] = f[q];
+      j1[q] = f[3 + q];
+      const double da = a0 - a1[q];
+      const double a2 = (-6.0 * da - h * (4.0 * j0 + 2.0 * j1[q])) / h2;
+      const double a3 = (12.0 * da + 6.0 * h * (j0 + j1[q])) / h3;
+      x1[q] = xp + a2 * (h2 * h2 / 24.0) + a3 * (h2 * h3 / 120.0);
+      v1[q] = vp + a2 * (h3 / 6.0) + a3 * (h2 * h2 / 24.0);
+      a2e[q] = a2 + h * a3;
+      a3v[q] = a3;
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      d.x[q * n + i] = x1[q];
+      d.v[q * n + i] = v1[q];
+      d.a[q * n + i] = a1[q];
+      d.j[q * n + i] = j1[q];
+    }
+    d.tick[i] = tn;
+    if (!(finite3(x1) && finite3(v1) && finite3(a1) && finite3(j1))) {
+      atomicOr(d.err, (int)kErrNonFinite);
+      continue;
+    }
+    if (dt_shared <= 0.0) {
+      const int lv = d.level[i];
+      const double dtc = aarseth_dt(a1, j1, a2e, a3v, eta);
+      int fl = 0;
+      const int nl = next_level(lv, dtc, tn, lmin, lmax, fl);
+      if (fl) atomicAdd((unsigned long long *)&d.ctr[kCtrFloor], 1ull);
+      if (nl != lv) {
+        atomicSub(&d.hist[c * kLevels + lv], 1);
+        atomicAdd(&d.hist[c * kLevels + nl], 1);
+        d.level[i] = nl;
+      }
+    }
+  }
+}
+
+// After the initial force evaluation: store a, jerk, choose levels, build
+// the level histograms.
+__global__ __launch_bounds__(kWG) void k_init_levels(Dev d, double eta_s,
+                                                     double dt_shared,
+                                                     int lmin, int lmax) {
+  __shared__ int lh[kLevels];
+  __shared__ int same;
+  const int64_t n = d.n;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
+  if (threadIdx.x < kLevels) lh[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    const int64_t last = (i0 + blockDim.x - 1 < n) ? i0 + blockDim.x - 1 : n - 1;
+    same = (i0 < n) && d.cid[i0] == d.cid[last];
+  }
+  __syncthreads();
+  const int64_t i = i0 + threadIdx.x;
+  if (i < n) {
+    const int c = d.cid[i];
+    const ClusterPlan cp = d.plan_c[c];
+    double f[6];
+    sum_rows(d, cp, (int)(i - cp.act_off), 6, f);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      d.a[q * n + i] = f[q];
+      d.j[q * n + i] = f[3 + q];
+    }
+    int lv;
+    if (!(finite3(f) && finite3(f + 3))) {
+      atomicOr(d.err, (int)kErrNonFinite);
+      lv = lmax;
+    } else if (dt_shared > 0.0) {
+      int e;
+      frexp(dt_shared, &e);
+      lv = 1 - e;
+    } else {
+      int fl = 0;
+      lv = initial_level(f, f + 3, eta_s, lmin, lmax, fl);
+      if (fl) atomicAdd((unsigned long long *)&d.ctr[kCtrFloor], 1ull);
+    }
+    d.level[i] = lv;
+    if (same) atomicAdd(&lh[lv], 1);
+    else atomicAdd(&d.hist[c * kLevels + lv], 1);
+  }
+  __syncthreads();
+  if (same && threadIdx.x < kLevels && lh[threadIdx.x])
+    atomicAdd(&d.hist[d.cid[i0] * kLevels + threadIdx.x], lh[threadIdx.x]);
+}
+
+// nbody_forces with several clusters: offsets of each cluster's group in
+// i_active (which must be grouped by non-decreasing cluster id).
+__global__ void k_api_group(Dev d, const int32_t *ia, int64_t na) {
+  const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int C = d.C;
+  auto key = [&](int64_t k) -> int {
+    const int32_t i = ia[k];
+    if (i < 0 || i >= d.n) return C;     // invalid: sorts last
+    return d.cid[i];
+  };
+  // with one cluster the j set is the caller's (any n_j): the force kernel
+  // checks i against it; with several, i must index the context's clusters
+  if (C > 1) {
+    for (int64_t k = gt; k < na; k += (int64_t)gridDim.x * blockDim.x) {
+      const int32_t i = ia[k];
+      if (i < 0 || i >= d.n) atomicOr(d.err, (int)kErrIndex);
+      if (k > 0 && key(k) < key(k - 1)) atomicOr(d.err, (int)kErrIndex);
+    }
+  }
+  if (gt <= C) {
+    if (C == 1) {
+      d.act_off[gt] = (gt == 0) ? 0 : (int32_t)na;
+    } else {
+      int64_t lo = 0, hi = na;   // first k with key(k) >= gt
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (key(mid) < gt) lo = mid + 1; else hi = mid;
+      }
+      d.act_off[gt] = (int32_t)lo;
+    }
+  }
+}
+
+__global__ void k_api_finalize(Dev d, int64_t na, double *acc, double *jerk) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < na;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    int c = 0;
+    if (d.C > 1) {   // largest c with act_off[c] <= k, among non-empty groups
+      int lo = 0, hi = d.C;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (d.act_off[mid] <= k) lo = mid; else hi = mid;
+      }
+      c = lo;
+    }
+    const ClusterPlan cp = d.plan_c[c];
+    double f[6] = {0, 0, 0, 0, 0, 0};
+    const int slot = (int)(k - cp.act_off);
+    if (slot >= 0 && slot < cp.na && cp.S > 0) sum_rows(d, cp, slot, 6, f);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      acc[3 * k + q] = f[q];
+      jerk[3 * k + q] = f[3 + q];
+    }
+    if (!(finite3(f) && finite3(f + 3))) atomicOr(d.err, (int)kErrNonFinite);
+  }
+}
+
+// Per-cluster diagnostics: one workgroup per cluster, fixed-order sums.
+__global__ __launch_bounds__(kWG) void k_energy_reduce(Dev d) {
+  __shared__ double sh[kWG][2];
+  const int c = blockIdx.x;
+  const ClusterPlan cp = d.plan_c[c];
+  const int64_t b = d.coff[c], e = d.coff[c + 1];
+  const int64_t T = d.T[c];
+  // quantities: K, W, Lx, Ly, Lz, Px, Py, Pz
+  double s[8], cc[8];
+  for (int q = 0; q < 8; ++q) s[q] = cc[q] = 0.0;
+  auto add = [&](int q, double x) {
+    const double u = s[q] + x;
+    cc[q] += (fabs(s[q]) >= fabs(x)) ? (s[q] - u) + x : (x - u) + s[q];
+    s[q] = u;
+  };
+  for (int64_t i = b + threadIdx.x; i < e; i += kWG) {
+    double xp[3], vp[3];
+    predict_state(d, i, T, xp, vp);
+    const double m = d.m[i];
+    double phi;
+    sum_rows(d, cp, (int)(i - cp.act_off), 1, &phi);
+    add(0, 0.5 * m * (vp[0] * vp[0] + vp[1] * vp[1] + vp[2] * vp[2]));
+    add(1, 0.5 * m * phi);
+    add(2, m * (xp[1] * vp[2] - xp[2] * vp[1]));
+    add(3, m * (xp[2] * vp[0] - xp[0] * vp[2]));
+    add(4, m * (xp[0] * vp[1] - xp[1] * vp[0]));
+    add(5, m * vp[0]);
+    add(6, m * vp[1]);
+    add(7, m * vp[2]);
+  }
+  double out[8];
+  for (int q = 0; q < 8; ++q) {
+    sh[threadIdx.x][0] = s[q];
+    sh[threadIdx.x][1] = cc[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double S = 0.0, Cc = 0.0;
+      for (int u = 0; u < kWG; ++u) {
+        for (int h = 0; h < 2; ++h) {
+          const double x = sh[u][h];
+          const double t = S + x;
+          Cc += (fabs(S) >= fabs(x)) ? (S - t) + x : (x - t) + S;
+          S = t;
+        }
+      }
+      out[q] = S + Cc;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double *o = d.eout + 9 * (int64_t)c;
+    o[0] = out[0];
+    o[1] = out[1];
+    o[2] = out[0] + out[1];
+    for (int q = 0; q < 6; ++q) o[3 + q] = out[2 + q];
+  }
+}
+
+__global__ void k_set_word64(int64_t *p, int64_t v) { *p = v; }
+
+__global__ void k_fill32(int32_t *p, int32_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_get_state(Dev d, double *x, double *v, double *a, double *jk,
+                            int64_t *tick, int8_t *level) {
+  const int64_t n = d.n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (x) x[3 * i + c] = d.x[c * n + i];
+      if (v) v[3 * i + c] = d.v[c * n + i];
+      if (a) a[3 * i + c] = d.a[c * n + i];
+      if (jk) jk[3 * i + c] = d.j[c * n + i];
+    }
+    if (tick) tick[i] = d.tick[i];
+    if (level) level[i] = (int8_t)d.level[i];
+  }
+}
+
+constexpr int32_t kErrState = 8;
+
+// set_state pass 1: copy in, validate levels, cluster time = max tick.
+__global__ void k_set_state1(Dev d, const double *x, const double *v,
+                             const double *a, const double *jk,
+                             const int64_t *tick, const int8_t *level,
+                             int lmin, int lmax) {
+  const int64_t n = d.n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      d.x[c * n + i] = x[3 * i + c];
+      d.v[c * n + i] = v[3 * i + c];
+      d.a[c * n + i] = a[3 * i + c];
+      d.j[c * n + i] = jk[3 * i + c];
+    }
+    const int lv = level[i];
+    const int64_t tk = tick[i];
+    d.tick[i] = tk;
+    d.level[i] = lv;
+    if (lv < lmin || lv > lmax || tk < 0) {
+      atomicOr(d.err, kErrState);
+      continue;
+    }
+    const int c = d.cid[i];
+    atomicMax((unsigned long long *)&d.T[c], (unsigned long long)tk);
+    atomicAdd(&d.hist[c * kLevels + lv], 1);
+  }
+}
+
+// set_state pass 2: tick multiple of the step and tick <= T < tick + step.
+__global__ void k_set_state2(Dev d) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < d.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int lv = d.level[i];
+    if (lv < 0 || lv >= kLevels) continue;   // already flagged
+    const int64_t dt = (int64_t)1 << (kTickBits - lv);
+    const int64_t tk = d.tick[i];
+    const int64_t T = d.T[d.cid[i]];
+    if (tk % dt != 0 || tk > T || T >= tk + dt) atomicOr(d.err, kErrState);
+  }
+  const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gt < d.C) d.Tnext[gt] = d.T[gt];
+}
+
+inline int grid_for(int64_t n, int block = kWG, int cap = 4096) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+template <int MODE, int SRC, int K>
+hipError_t launch_force_t(const ForceArgs &A, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_force<MODE, SRC, K>), dim3(grid), dim3(kWG), 0, s, A);
+  return hipGetLastError();
+}
+
+template <int MODE, int SRC, int K>
+int grid_t(int device) {
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, (const void *)k_force<MODE, SRC, K>, kWG, 0) != hipSuccess)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                            device) != hipSuccess)
+    cus = 256;
+  if (per_cu < 1) per_cu = 1;
+  return per_cu * cus;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+
+hipError_t launch_init_state(const Dev &d, const double *m, const double *x,
+                             const double *v, hipStream_t s) {
+  int64_t need = d.n;
+  if (need < (int64_t)d.C * kLevels) need = (int64_t)d.C * kLevels;
+  if (need < kCtrCount) need = kCtrCount;
+  const int64_t blocks = (need + kWG - 1) / kWG;
+  // every cluster/hist/ctr slot needs its own thread: no cap on the grid
+  hipLaunchKernelGGL(k_init_state, dim3((unsigned)blocks), dim3(kWG), 0, s, d,
+                     m, x, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_all_active(const Dev &d, hipStream_t s) {
+  int64_t need = d.n > d.C + 1 ? d.n : d.C + 1;
+  hipLaunchKernelGGL(k_all_active, dim3((unsigned)((need + kWG - 1) / kWG)),
+                     dim3(kWG), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_sched(const Dev &d, hipStream_t s) {
+  hipLaunchKernelGGL(k_sched, dim3((d.C + kWG - 1) / kWG), dim3(kWG), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const Dev &d, hipStream_t s) {
+  hipLaunchKernelGGL(k_count, dim3(d.nblk), dim3(kWG), 0, s, d);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d);
+  hipLaunchKernelGGL(k_scatter, dim3(d.nblk), dim3(kWG), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan(const Dev &d, const Tuning &t, int kind, int64_t api_nj,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, d, t, kind, api_nj);
+  return hipGetLastError();
+}
+
+hipError_t launch_force(const Dev &d, int mode, int src, int K,
+                        const RawSrc *raw, int grid, hipStream_t s) {
+  ForceArgs A;
+  A.d = d;
+  A.active = d.active;
+  A.rx = A.rv = A.rm = nullptr;
+  if (src == kSrcRaw) {
+    if (!raw) return hipErrorInvalidValue;
+    A.active = raw->i_active;
+    A.rx = raw->x;
+    A.rv = raw->v;
+    A.rm = raw->m;
+  }
+#define NB_CASE(M, S_, KK)                                    \
+  if (mode == M && src == S_ && K == KK)                      \
+    return launch_force_t<M, S_, KK>(A, grid, s);
+  NB_CASE(kModeFP64, kSrcState, 1)
+  NB_CASE(kModeFP64, kSrcState, 2)
+  NB_CASE(kModeFP64, kSrcRaw, 1)
+  NB_CASE(kModeFP64, kSrcRaw, 2)
+  NB_CASE(kModeMixed, kSrcState, 1)
+  NB_CASE(kModeMixed, kSrcState, 2)
+  NB_CASE(kModeMixed, kSrcRaw, 1)
+  NB_CASE(kModeMixed, kSrcRaw, 2)
+  NB_CASE(kModePot, kSrcState, 1)
+#undef NB_CASE
+  return hipErrorInvalidValue;
+}
+
+int force_grid_size(int mode, int src, int K, int device) {
+#define NB_CASE(M, S_, KK) \
+  if (mode == M && src == S_ && K == KK) return grid_t<M, S_, KK>(device);
+  NB_CASE(kModeFP64, kSrcState, 1)
+  NB_CASE(kModeFP64, kSrcState, 2)
+  NB_CASE(kModeFP64, kSrcRaw, 1)
+  NB_CASE(kModeFP64, kSrcRaw, 2)
+  NB_CASE(kModeMixed, kSrcState, 1)
+  NB_CASE(kModeMixed, kSrcState, 2)
+  NB_CASE(kModeMixed, kSrcRaw, 1)
+  NB_CASE(kModeMixed, kSrcRaw, 2)
+  NB_CASE(kModePot, kSrcState, 1)
+#undef NB_CASE
+  return 0;
+}
+
+hipError_t launch_correct(const Dev &d, double eta, double dt_shared,
+                          int level_min, int level_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_correct, dim3(grid_for(d.n, kWG, 2048)), dim3(kWG), 0, s,
+                     d, eta, dt_shared, level_min, level_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_levels(const Dev &d, double eta_start, double dt_shared,
+                              int level_min, int level_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_levels, dim3((unsigned)((d.n + kWG - 1) / kWG)),
+                     dim3(kWG), 0, s, d, eta_start, dt_shared, level_min,
+                     level_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_api_group(const Dev &d, const RawSrc &r, hipStream_t s) {
+  int64_t need = r.n_active > d.C + 1 ? r.n_active : d.C + 1;
+  hipLaunchKernelGGL(k_api_group, dim3((unsigned)((need + kWG - 1) / kWG)),
+                     dim3(kWG), 0, s, d, r.i_active, r.n_active);
+  return hipGetLastError();
+}
+
+hipError_t launch_api_finalize(const Dev &d, const RawSrc &r, hipStream_t s) {
+  hipLaunchKernelGGL(k_api_finalize, dim3(grid_for(r.n_active)), dim3(kWG), 0,
+                     s, d, r.n_active, r.acc, r.jerk);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_reduce(const Dev &d, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_reduce, dim3(d.C), dim3(kWG), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_word64(int64_t *p, int64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_word64, dim3(1), dim3(1), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill32, dim3(grid_for(n)), dim3(kWG), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_state(const Dev &d, double *x, double *v, double *a,
+                            double *jk, int64_t *tick, int8_t *level,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_get_state, dim3(grid_for(d.n)), dim3(kWG), 0, s, d, x, v,
+                     a, jk, tick, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_state(const Dev &d, const double *x, const double *v,
+                            const double *a, const double *jk,
+                            const int64_t *tick, const int8_t *level,
+                            int level_min, int level_max, hipStream_t s) {
+  // T and hist are cleared by the caller (fill kernels) beforehand
+  hipLaunchKernelGGL(k_set_state1, dim3(grid_for(d.n)), dim3(kWG), 0, s, d, x,
+                     v, a, jk, tick, level, level_min, level_max);
+  int64_t need = d.n > d.C ? d.n : d.C;
+  hipLaunchKernelGGL(k_set_state2, dim3(grid_for(need)), dim3(kWG), 0, s, d);
+  return hipGetLastError();
+}
+
+}  // namespace nbk

@@ -1,0 +1,183 @@
+"""Parity of nbody_forces (HIP, through the C ABI) against the CPU oracle:
+eq. (1) with Plummer softening plus jerk, FP64 path within 1e-12 and mixed
+path within 1e-6 relative per particle, over ragged sizes, subsets with
+repeats, zero softening, ensembles and the error paths."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0909_0879_amd import binding, ics
+from tests.gpu_util import FP64_TOL, MIXED_TOL, rel_err, require_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 3, 63, 64, 65, 255, 256, 257, 513, 1000, 1024, 4097]
+
+
+def _ctx(m, x, v, eps, prec, **kw):
+    return binding.NBody(m, x, v, eps=eps, precision=prec, **kw)
+
+
+@pytest.mark.parametrize("prec,tol", [(binding.FP64, FP64_TOL), (binding.MIXED, MIXED_TOL)])
+@pytest.mark.parametrize("n", SIZES)
+def test_all_particles_vs_oracle(n, prec, tol):
+    require_gpu()
+    print(f"forces n={n} prec={prec}", flush=True)
+    m, x, v = ics.plummer(n, 100 + n)
+    eps = 1e-3
+    g = _ctx(m, x, v, eps, prec)
+    acc, jerk = g.forces(x, v, m)
+    g.sync()
+    a_ref, j_ref = oracle.forces(x, v, m, eps)
+    if n == 1:
+        assert np.all(to_np(acc) == 0) and np.all(to_np(jerk) == 0)
+        return
+    ea, ej = rel_err(to_np(acc), a_ref), rel_err(to_np(jerk), j_ref)
+    assert ea.max() <= tol, ea.max()
+    assert ej.max() <= tol, ej.max()
+
+
+@pytest.mark.parametrize("prec,tol", [(binding.FP64, FP64_TOL), (binding.MIXED, MIXED_TOL)])
+@pytest.mark.parametrize("na", [1, 2, 5, 17, 100, 700, 3000])
+def test_subsets_with_repeats(na, prec, tol):
+    require_gpu()
+    n = 2500
+    m, x, v = ics.plummer(n, 7)
+    m = ics.salpeter_masses(n, 8)          # uneven masses
+    rng = np.random.default_rng(na)
+    idx = rng.integers(0, n, na).astype(np.int32)
+    idx[: min(3, na)] = idx[0]             # repeats
+    g = _ctx(m, x, v, 1e-4, prec)
+    acc, jerk = g.forces(x, v, m, i_active=idx)
+    g.sync()
+    a_ref, j_ref = oracle.forces(x, v, m, 1e-4, idx=idx.astype(np.int64))
+    assert rel_err(to_np(acc), a_ref).max() <= tol
+    assert rel_err(to_np(jerk), j_ref).max() <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [(binding.FP64, FP64_TOL), (binding.MIXED, MIXED_TOL)])
+def test_j_set_larger_than_context(prec, tol):
+    # one cluster: n_j is free, independent of the context's n
+    require_gpu()
+    m0, x0, v0 = ics.plummer(64, 1)
+    g = _ctx(m0, x0, v0, 1e-3, prec)
+    m, x, v = ics.plummer(20000, 2)
+    idx = np.arange(0, 20000, 37, dtype=np.int32)
+    acc, jerk = g.forces(x, v, m, i_active=idx)
+    g.sync()
+    a_ref, j_ref = oracle.forces(x, v, m, 1e-3, idx=idx.astype(np.int64))
+    assert rel_err(to_np(acc), a_ref).max() <= tol
+    assert rel_err(to_np(jerk), j_ref).max() <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [(binding.FP64, FP64_TOL), (binding.MIXED, MIXED_TOL)])
+def test_zero_softening(prec, tol):
+    require_gpu()
+    rng = np.random.default_rng(3)
+    x = rng.normal(size=(300, 3))
+    v = rng.normal(size=(300, 3))
+    m = rng.uniform(0.1, 1.0, 300)
+    g = _ctx(m, x, v, 0.0, prec)
+    acc, jerk = g.forces(x, v, m)
+    g.sync()
+    a_ref, j_ref = oracle.forces(x, v, m, 0.0)
+    assert rel_err(to_np(acc), a_ref).max() <= tol
+    assert rel_err(to_np(jerk), j_ref).max() <= tol
+
+
+def test_zero_softening_coincident_is_edomain():
+    require_gpu()
+    x = np.array([[0.0, 0, 0], [1.0, 0, 0], [1.0, 0, 0]])
+    v = np.zeros((3, 3))
+    m = np.ones(3)
+    g = _ctx(np.ones(2), x[:2], v[:2], 0.0, binding.FP64)
+    g.forces(x, v, m)
+    with pytest.raises(binding.NBodyError) as e:
+        g.sync()
+    assert e.value.code == binding.EDOMAIN
+    g.sync()      # error is cleared once reported
+
+
+def test_index_out_of_range_is_eindex():
+    require_gpu()
+    m, x, v = ics.plummer(100, 4)
+    g = _ctx(m, x, v, 1e-3, binding.FP64)
+    acc, jerk = g.forces(x, v, m, i_active=np.array([0, 5, 100, -1, 7], np.int32))
+    with pytest.raises(binding.NBodyError) as e:
+        g.sync()
+    assert e.value.code == binding.EINDEX
+    a = to_np(acc)
+    assert np.all(a[2] == 0) and np.all(a[3] == 0)
+    a_ref, _ = oracle.forces(x, v, m, 1e-3, idx=np.array([0, 5, 7]))
+    assert rel_err(a[[0, 1, 4]], a_ref).max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("prec,tol", [(binding.FP64, FP64_TOL), (binding.MIXED, MIXED_TOL)])
+def test_ensemble_forces_per_cluster(prec, tol):
+    require_gpu()
+    m, x, v, off = ics.ensemble(5, sizes=[257, 64, 1000, 3, 511], seed=900)
+    eps = [1e-3, 2e-3, 1e-4, 1e-3, 5e-4]
+    g = _ctx(m, x, v, eps, prec, cluster_offsets=off)
+    acc, jerk = g.forces(x, v, m)
+    g.sync()
+    a, j = to_np(acc), to_np(jerk)
+    for c in range(5):
+        sl = slice(off[c], off[c + 1])
+        a_ref, j_ref = oracle.forces(x[sl], v[sl], m[sl], eps[c])
+        assert rel_err(a[sl], a_ref).max() <= tol, c
+        assert rel_err(j[sl], j_ref).max() <= tol, c
+    # grouped subset with repeats, skipping cluster 1 entirely
+    idx = np.array([0, 0, 5, 400, 400, 1321, 1322, 1400], np.int32)
+    acc, jerk = g.forces(x, v, m, i_active=idx)
+    g.sync()
+    cl = np.searchsorted(off, idx, side="right") - 1
+    for k, i in enumerate(idx):
+        c = cl[k]
+        sl = slice(off[c], off[c + 1])
+        a_ref, _ = oracle.forces(x[sl], v[sl], m[sl], eps[c], idx=[i - off[c]])
+        assert rel_err(to_np(acc)[k:k + 1], a_ref).max() <= tol
+    # not grouped by cluster
+    g.forces(x, v, m, i_active=np.array([400, 0], np.int32))
+    with pytest.raises(binding.NBodyError) as e:
+        g.sync()
+    assert e.value.code == binding.EINDEX
+
+
+@pytest.mark.parametrize("prec,tol", [(binding.FP64, 1e-14), (binding.MIXED, 1e-7)])
+def test_split_and_tile_shape_invariance(prec, tol):
+    require_gpu()
+    m, x, v = ics.plummer(6000, 5)
+    g = _ctx(m, x, v, 1e-3, prec)
+    idx = np.arange(0, 6000, 3, dtype=np.int32)[:150]
+    base_a, base_j = (to_np(t) for t in g.forces(x, v, m, i_active=idx))
+    for variant in (binding.VARIANT_K1, binding.VARIANT_K2):
+        for slots, target in ((1, 1), (4, 64), (64, 4096), (256, 1)):
+            g.set_tuning({"variant": variant, "i_slots": [slots] * 25,
+                          "target_items": [target] * 25, "min_split_j": 64})
+            a, j = (to_np(t) for t in g.forces(x, v, m, i_active=idx))
+            assert rel_err(a, base_a).max() <= tol, (variant, slots, target)
+            assert rel_err(j, base_j).max() <= tol, (variant, slots, target)
+
+
+@pytest.mark.parametrize("prec", [binding.FP64, binding.MIXED])
+def test_bitwise_deterministic(prec):
+    require_gpu()
+    m, x, v = ics.plummer(3000, 6)
+    g = _ctx(m, x, v, 1e-3, prec)
+    idx = np.arange(0, 3000, 7, dtype=np.int32)
+    r1 = [to_np(t) for t in g.forces(x, v, m, i_active=idx)]
+    r2 = [to_np(t) for t in g.forces(x, v, m, i_active=idx)]
+    assert np.array_equal(r1[0], r2[0]) and np.array_equal(r1[1], r2[1])
+
+
+def test_mixed_within_fp64_path():
+    # both GPU paths at identical inputs; the mixed one within 1e-6 of FP64
+    require_gpu()
+    m, x, v = ics.plummer(8192, 9)
+    m = ics.salpeter_masses(8192, 10)
+    g64 = _ctx(m, x, v, 1e-4, binding.FP64)
+    gm = _ctx(m, x, v, 1e-4, binding.MIXED)
+    a64, j64 = (to_np(t) for t in g64.forces(x, v, m))
+    am, jm = (to_np(t) for t in gm.forces(x, v, m))
+    assert rel_err(am, a64).max() <= MIXED_TOL
+    assert rel_err(jm, j64).max() <= MIXED_TOL
