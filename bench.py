@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--n", type=int, default=N_DEFAULT, help="particles (default 2^20)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     return ap.parse_args()
 
 
@@ -49,7 +49,9 @@ def time_path(binding, torch, m, x, v, precision, steps, warmup):
     """Run warmup + timed block steps; return wall ms/step and force-kernel
     event ms per launch."""
     g = binding.NBody(m, x, v, eps=EPS, precision=precision, eta=0.01, eta_start=0.01,
-                      level_min=LEVEL, level_max=LEVEL)
+                      level_min=LEVEL, level_max=LEVEL, tuning="auto")
+    # one block step per launch: each nbody_step call below is exactly one step
+    g.set_tuning({"steps_per_launch": 1})
     dt = 2.0 ** -LEVEL
     t = 0.0
     for _ in range(warmup):

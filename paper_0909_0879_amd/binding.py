@@ -156,7 +156,7 @@ class NBody:
 
     def __init__(self, m, x, v, *, cluster_offsets=None, eps=1e-3, precision=FP64, eta=0.01,
                  eta_start=0.01, dt_shared=0.0, level_min=3, level_max=20, stream=None,
-                 device="cuda"):
+                 device="cuda", tuning=None):
         import torch
         self._torch = torch
         m = torch.as_tensor(m, dtype=torch.float64, device=device).contiguous()
@@ -183,6 +183,11 @@ class NBody:
         self.ctx = C.c_void_p()
         check(lib().nbody_init(C.byref(self.ctx), C.byref(self.params), n, _ptr(m), _ptr(x),
                                _ptr(v)), "nbody_init")
+        if tuning == "auto":
+            from . import autotune
+            tuning = autotune.load(precision, n)
+        if tuning:
+            self.set_tuning(tuning)
 
     # -- evaluation -------------------------------------------------------
     def forces(self, xj, vj, mj, i_active=None):

@@ -17,14 +17,18 @@
 //  * i-particles sit in registers, K per thread slot; j-particles are
 //    predicted while being copied, coalesced, from the SoA state in HBM into
 //    a 256-record LDS tile and are read back as broadcasts;
+//  * FP32 arithmetic dual-issues on gfx950 while FP64 does not, so the mixed
+//    path keeps every per-pair operation in FP32: the FP64 predicted
+//    positions are stored as double-single (hi, lo) FP32 pairs and x_j - x_i
+//    is formed as (hi_j - hi_i) + (lo_j - lo_i);
 //  * small active sets put several lanes on one i (P i-slots x Q j-lanes,
 //    P * Q = 256) and split j over workgroups; lanes are reduced with
 //    wavefront shuffles in a fixed tree and splits by the corrector in a
 //    fixed order, so every result is deterministic;
 //  * FP64 mode accumulates each tile in FP64 and folds it into a TwoSum
-//    (hi, lo) pair; mixed mode forms x_j - x_i and v_j - v_i in FP64,
-//    converts them to FP32, does rsqrt, r^-3 and the jerk products in FP32
-//    and folds each tile's FP32 sums into an FP32 TwoSum (hi, lo) pair.
+//    (hi, lo) pair; mixed mode does rsqrt, r^-3 and the jerk products in
+//    FP32 and folds the FP32 sums of every 64 j into an FP32 TwoSum
+//    (hi, lo) pair.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -40,9 +44,10 @@ constexpr double kTick = 1.0 / (double)(1 << kTickBits);
 // ------------------------------------------------------------ helpers
 
 __device__ __forceinline__ double rsq64(double s) {
-  // hardware reciprocal square root refined by one third-order Newton step
-  // y1 = y (1 + e/2 + 3 e^2/8), e = 1 - s y^2 (Newton-Raphson on x^2 = r^2,
-  // the square-root method the paper mentions in Sect. 3)
+  // hardware reciprocal square root (good to about 2^-24 on gfx950) refined
+  // by one third-order Newton-Raphson step on y^-2 = s (the iteration for
+  // square roots named in Sect. 3): y1 = y (1 + e/2 + 3 e^2/8), e = 1 - s y^2,
+  // which leaves a relative error of order e^3, far below FP64 rounding
   const double y = __builtin_amdgcn_rsq(s);
   const double e = fma(-s, y * y, 1.0);
   return fma(y * e, fma(0.375, e, 0.5), y);
@@ -102,21 +107,76 @@ __device__ __forceinline__ int find_cluster(const int64_t *coff, int C,
   return lo;
 }
 
-struct JRec {            // one j-particle in LDS, 64 bytes
+// ------------------------------------------------------------ LDS records
+
+struct JRec64 {          // one j-particle for FP64 and potential modes, 64 bytes
   double x, y, z, m;
   double vx, vy, vz;
   float mf;
   int32_t idx;
 };
 
+struct JRecDS {          // one j-particle for mixed mode, 48 bytes: position as a
+  float xh, yh, zh, m;   // double-single pair (hi + lo = the FP64 predicted
+  float xl, yl, zl, pad; // position to ~48 bits), velocity and mass in FP32
+  float vx, vy, vz;
+  int32_t idx;
+};
+
+struct I64 {             // an i-particle in registers, FP64 modes
+  double x[3], v[3];
+};
+
+struct IDS {             // an i-particle in registers, mixed mode
+  float xh[3], xl[3], v[3];
+};
+
+__device__ __forceinline__ void make_i(const double *xp, const double *vp, I64 &s) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    s.x[c] = xp[c];
+    s.v[c] = vp[c];
+  }
+}
+
+// hi = x rounded to FP32, lo = (x - hi) rounded to FP32 (x - hi is exact in FP64)
+__device__ __forceinline__ void make_i(const double *xp, const double *vp, IDS &s) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float h = (float)xp[c];
+    s.xh[c] = h;
+    s.xl[c] = (float)(xp[c] - (double)h);
+    s.v[c] = (float)vp[c];
+  }
+}
+
+__device__ __forceinline__ void make_rec(const double *xp, const double *vp, double m,
+                                         int32_t idx, JRec64 &r) {
+  r.x = xp[0]; r.y = xp[1]; r.z = xp[2]; r.m = m;
+  r.vx = vp[0]; r.vy = vp[1]; r.vz = vp[2];
+  r.mf = (float)m;
+  r.idx = idx;
+}
+
+__device__ __forceinline__ void make_rec(const double *xp, const double *vp, double m,
+                                         int32_t idx, JRecDS &r) {
+  IDS s;
+  make_i(xp, vp, s);
+  r.xh = s.xh[0]; r.yh = s.xh[1]; r.zh = s.xh[2];
+  r.xl = s.xl[0]; r.yl = s.xl[1]; r.zl = s.xl[2];
+  r.vx = s.v[0]; r.vy = s.v[1]; r.vz = s.v[2];
+  r.m = (float)m;
+  r.pad = 0.0f;
+  r.idx = idx;
+}
+
 // ------------------------------------------------------------ pair terms
 
 template <bool MASK>
-__device__ __forceinline__ void pair_fp64(const double *xi, const double *vi,
-                                          int iidx, const JRec &r, double eps2,
-                                          double *t, int &dom) {
-  const double dx = r.x - xi[0], dy = r.y - xi[1], dz = r.z - xi[2];
-  const double wx = r.vx - vi[0], wy = r.vy - vi[1], wz = r.vz - vi[2];
+__device__ __forceinline__ void pair_fp64(const I64 &I, int iidx, const JRec64 &r,
+                                          double eps2, double *t, int &dom) {
+  const double dx = r.x - I.x[0], dy = r.y - I.x[1], dz = r.z - I.x[2];
+  const double wx = r.vx - I.v[0], wy = r.vy - I.v[1], wz = r.vz - I.v[2];
   const double s = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
   const double rv = fma(dx, wx, fma(dy, wy, dz * wz));
   double rinv = rsq64(s);
@@ -137,26 +197,27 @@ __device__ __forceinline__ void pair_fp64(const double *xi, const double *vi,
   t[5] = fma(mr3, fma(-al, dz, wz), t[5]);
 }
 
+// Mixed precision: x_j - x_i from the double-single pairs, (hi_j - hi_i) +
+// (lo_j - lo_i), which is the FP64 difference rounded to FP32 within an ulp
+// (the hi difference is exact for close pairs); everything after it in FP32.
 template <bool MASK>
-__device__ __forceinline__ void pair_mixed(const double *xi, const double *vi,
-                                           int iidx, const JRec &r, float eps2,
-                                           float *t, int &dom) {
-  const double dxd = r.x - xi[0], dyd = r.y - xi[1], dzd = r.z - xi[2];
-  const float dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
-  const float wx = (float)(r.vx - vi[0]);
-  const float wy = (float)(r.vy - vi[1]);
-  const float wz = (float)(r.vz - vi[2]);
+__device__ __forceinline__ void pair_mixed(const IDS &I, int iidx, const JRecDS &r,
+                                           float eps2, float *t, int &dom) {
+  const float dx = (r.xh - I.xh[0]) + (r.xl - I.xl[0]);
+  const float dy = (r.yh - I.xh[1]) + (r.yl - I.xl[1]);
+  const float dz = (r.zh - I.xh[2]) + (r.zl - I.xl[2]);
+  const float wx = r.vx - I.v[0], wy = r.vy - I.v[1], wz = r.vz - I.v[2];
   const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
   const float rv = fmaf(dx, wx, fmaf(dy, wy, dz * wz));
   float rinv = __builtin_amdgcn_rsqf(s);
   if (MASK) {
-    if (dxd == 0.0 && dyd == 0.0 && dzd == 0.0) {
+    if (dx == 0.0f && dy == 0.0f && dz == 0.0f) {
       rinv = 0.0f;
       dom |= (r.idx != iidx);
     }
   }
   const float rinv2 = rinv * rinv;
-  const float mr3 = (r.mf * rinv) * rinv2;
+  const float mr3 = (r.m * rinv) * rinv2;
   const float al = (3.0f * rv) * rinv2;
   t[0] = fmaf(mr3, dx, t[0]);
   t[1] = fmaf(mr3, dy, t[1]);
@@ -166,54 +227,89 @@ __device__ __forceinline__ void pair_mixed(const double *xi, const double *vi,
   t[5] = fmaf(mr3, fmaf(-al, dz, wz), t[5]);
 }
 
-__device__ __forceinline__ void pair_pot(const double *xi, int iidx,
-                                         const JRec &r, double eps2,
-                                         double *t) {
-  const double dx = r.x - xi[0], dy = r.y - xi[1], dz = r.z - xi[2];
+__device__ __forceinline__ void pair_pot(const I64 &I, int iidx, const JRec64 &r,
+                                         double eps2, double *t) {
+  const double dx = r.x - I.x[0], dy = r.y - I.x[1], dz = r.z - I.x[2];
   const double s = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
   const double rinv = (r.idx == iidx) ? 0.0 : 1.0 / sqrt(s);
   t[0] = fma(-r.m, rinv, t[0]);
 }
 
-template <int MODE>
-struct AccT { using T = double; static constexpr int NC = 6; };
-template <>
-struct AccT<kModeMixed> { using T = float; static constexpr int NC = 6; };
-template <>
-struct AccT<kModePot> { using T = double; static constexpr int NC = 1; };
+template <int MODE> struct Traits {          // FP64 forces
+  using T = double;
+  using Rec = JRec64;
+  using Ist = I64;
+  static constexpr int NC = 6;
+  static constexpr int FOLD = kTJ;           // j per compensated fold
+};
+template <> struct Traits<kModeMixed> {
+  using T = float;
+  using Rec = JRecDS;
+  using Ist = IDS;
+  static constexpr int NC = 6;
+  static constexpr int FOLD = 64;
+};
+template <> struct Traits<kModePot> {
+  using T = double;
+  using Rec = JRec64;
+  using Ist = I64;
+  static constexpr int NC = 1;
+  static constexpr int FOLD = kTJ;
+};
 
-// One LDS tile against K i-particles.  WIDE: every lane owns its i (Q = 1);
-// otherwise lane q of a slot takes records q, q + Q, ...
+template <int MODE, int K>
+__device__ __forceinline__ void fold(typename Traits<MODE>::T (&t)[K][Traits<MODE>::NC],
+                                     typename Traits<MODE>::T (&hi)[K][Traits<MODE>::NC],
+                                     typename Traits<MODE>::T (&lo)[K][Traits<MODE>::NC]) {
+  using T = typename Traits<MODE>::T;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int c = 0; c < Traits<MODE>::NC; ++c) {
+      two_sum_into(hi[k][c], lo[k][c], t[k][c]);
+      t[k][c] = (T)0;
+    }
+}
+
+template <int MODE, int K, bool MASK>
+__device__ __forceinline__ void pair_k(const typename Traits<MODE>::Rec &r,
+                                       const typename Traits<MODE>::Ist (&I)[K],
+                                       const int (&iidx)[K], double eps2,
+                                       typename Traits<MODE>::T (&t)[K][Traits<MODE>::NC],
+                                       int (&dom)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if constexpr (MODE == kModeMixed)
+      pair_mixed<MASK>(I[k], iidx[k], r, (float)eps2, t[k], dom[k]);
+    else if constexpr (MODE == kModeFP64)
+      pair_fp64<MASK>(I[k], iidx[k], r, eps2, t[k], dom[k]);
+    else
+      pair_pot(I[k], iidx[k], r, eps2, t[k]);
+  }
+}
+
+// One LDS tile against K i-particles, folding the running tile sums into the
+// compensated (hi, lo) pairs every FOLD records.  WIDE: every lane owns its
+// i (Q = 1); otherwise lane q of a slot takes records q, q + Q, ... and
+// folds once per tile.
 template <int MODE, int K, bool WIDE, bool MASK>
 __device__ __forceinline__ void tile_loop(
-    const JRec *tile, int cnt, int q, int Q, const double (&xi)[K][3],
-    const double (&vi)[K][3], const int (&iidx)[K], double eps2,
-    typename AccT<MODE>::T (&t)[K][AccT<MODE>::NC], int (&dom)[K]) {
-  const int j0 = WIDE ? 0 : q;
-  const int js = WIDE ? 1 : Q;
-  if (MODE == kModeMixed) {
-    const float e2 = (float)eps2;
+    const typename Traits<MODE>::Rec *tile, int cnt, int q, int Q,
+    const typename Traits<MODE>::Ist (&I)[K], const int (&iidx)[K], double eps2,
+    typename Traits<MODE>::T (&t)[K][Traits<MODE>::NC],
+    typename Traits<MODE>::T (&hi)[K][Traits<MODE>::NC],
+    typename Traits<MODE>::T (&lo)[K][Traits<MODE>::NC], int (&dom)[K]) {
+  constexpr int F = Traits<MODE>::FOLD;
+  if (WIDE) {
+    for (int j0 = 0; j0 < cnt; j0 += F) {
+      const int j1 = (j0 + F < cnt) ? j0 + F : cnt;
 #pragma unroll 2
-    for (int jj = j0; jj < cnt; jj += js) {
-      const JRec r = tile[jj];
-#pragma unroll
-      for (int k = 0; k < K; ++k)
-        pair_mixed<MASK>(xi[k], vi[k], iidx[k], r, e2, (float *)t[k], dom[k]);
-    }
-  } else if (MODE == kModeFP64) {
-#pragma unroll 2
-    for (int jj = j0; jj < cnt; jj += js) {
-      const JRec r = tile[jj];
-#pragma unroll
-      for (int k = 0; k < K; ++k)
-        pair_fp64<MASK>(xi[k], vi[k], iidx[k], r, eps2, (double *)t[k], dom[k]);
+      for (int jj = j0; jj < j1; ++jj) pair_k<MODE, K, MASK>(tile[jj], I, iidx, eps2, t, dom);
+      fold<MODE, K>(t, hi, lo);
     }
   } else {
-    for (int jj = j0; jj < cnt; jj += js) {
-      const JRec r = tile[jj];
-#pragma unroll
-      for (int k = 0; k < K; ++k) pair_pot(xi[k], iidx[k], r, eps2, (double *)t[k]);
-    }
+    for (int jj = q; jj < cnt; jj += Q) pair_k<MODE, K, MASK>(tile[jj], I, iidx, eps2, t, dom);
+    fold<MODE, K>(t, hi, lo);
   }
 }
 
@@ -227,9 +323,11 @@ struct ForceArgs {
 
 template <int MODE, int SRC, int K>
 __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
-  using T = typename AccT<MODE>::T;
-  constexpr int NC = AccT<MODE>::NC;
-  __shared__ JRec tile[kTJ];
+  using Tr = Traits<MODE>;
+  using T = typename Tr::T;
+  using Rec = typename Tr::Rec;
+  constexpr int NC = Tr::NC;
+  __shared__ Rec tile[kTJ];
   __shared__ double red[kWG / 64][K][NC];
   __shared__ int s_g;
   const Dev &d = A.d;
@@ -258,7 +356,7 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
     const int q = tid & (Q - 1);
     const double eps2 = d.eps2[cp.c];
 
-    double xi[K][3], vi[K][3];
+    typename Tr::Ist I[K];
     int iidx[K], dom[K];
     bool ok[K];
 #pragma unroll
@@ -271,19 +369,19 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
         ok[k] = false;
         if (q == 0 && split == 0) atomicOr(d.err, (int)kErrIndex);
       }
+      double xp[3] = {0.0, 0.0, 0.0}, vp[3] = {0.0, 0.0, 0.0};
       if (!ok[k]) {
         iidx[k] = -1;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) xi[k][c] = vi[k][c] = 0.0;
       } else if (SRC == kSrcState) {
-        predict_state(d, iidx[k], cp.t_pred, xi[k], vi[k]);
+        predict_state(d, iidx[k], cp.t_pred, xp, vp);
       } else {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          xi[k][c] = A.rx[3 * (int64_t)iidx[k] + c];
-          vi[k][c] = A.rv[3 * (int64_t)iidx[k] + c];
+          xp[c] = A.rx[3 * (int64_t)iidx[k] + c];
+          vp[c] = A.rv[3 * (int64_t)iidx[k] + c];
         }
       }
+      make_i(xp, vp, I[k]);
     }
     T t[K][NC], shi[K][NC], slo[K][NC];
 #pragma unroll
@@ -296,45 +394,34 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
       const int cnt = (int)((je - jt < kTJ) ? je - jt : kTJ);
       if (tid < cnt) {
         const int64_t j = jt + tid;
-        JRec r;
-        double xp[3], vp[3];
+        double xp[3], vp[3], m;
         if (SRC == kSrcState) {
           predict_state(d, j, cp.t_pred, xp, vp);
-          r.m = d.m[j];
+          m = d.m[j];
         } else {
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             xp[c] = A.rx[3 * j + c];
             vp[c] = A.rv[3 * j + c];
           }
-          r.m = A.rm[j];
+          m = A.rm[j];
         }
-        r.x = xp[0]; r.y = xp[1]; r.z = xp[2];
-        r.vx = vp[0]; r.vy = vp[1]; r.vz = vp[2];
-        r.mf = (float)r.m;
-        r.idx = (int32_t)j;
+        Rec r;
+        make_rec(xp, vp, m, (int32_t)j, r);
         tile[tid] = r;
       }
       __syncthreads();
       if (Q == 1) {
         if (mask || MODE == kModePot)
-          tile_loop<MODE, K, true, true>(tile, cnt, q, Q, xi, vi, iidx, eps2, t, dom);
+          tile_loop<MODE, K, true, true>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom);
         else
-          tile_loop<MODE, K, true, false>(tile, cnt, q, Q, xi, vi, iidx, eps2, t, dom);
+          tile_loop<MODE, K, true, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom);
       } else {
         if (mask || MODE == kModePot)
-          tile_loop<MODE, K, false, true>(tile, cnt, q, Q, xi, vi, iidx, eps2, t, dom);
+          tile_loop<MODE, K, false, true>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom);
         else
-          tile_loop<MODE, K, false, false>(tile, cnt, q, Q, xi, vi, iidx, eps2, t, dom);
+          tile_loop<MODE, K, false, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom);
       }
-      // fold the tile sums into the compensated running sums
-#pragma unroll
-      for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          two_sum_into(shi[k][c], slo[k][c], t[k][c]);
-          t[k][c] = (T)0;
-        }
       __syncthreads();
     }
 
@@ -364,7 +451,7 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
         }
         __syncthreads();
         if (q == 0) {
-          const int nw = Q >> 6;   // waves of this slot: w0 .. w0 + nw - 1
+          const int nw = Q >> 6;   // waves of this slot: w .. w + nw - 1
 #pragma unroll
           for (int k = 0; k < K; ++k)
 #pragma unroll
