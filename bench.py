@@ -42,7 +42,26 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--workload", default="headline",
+                    choices=("headline", "sweep", "ensemble", "blocksteps"),
+                    help="headline: the contract line (default); sweep: n_active sweep of "
+                         "the King 2^20 evaluation; ensemble: 256-cluster block steps; "
+                         "blocksteps: Plummer 65536 FP64 and Salpeter 262144 mixed runs")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes (to scale the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
+
+
+def calibrate_copy(nbytes):
+    """A plain device-to-device copy of known size, for counter scaling."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": src.numel() * 4}), flush=True)
 
 
 def time_path(binding, torch, m, x, v, precision, steps, warmup):
@@ -97,8 +116,64 @@ def cpu_baseline(m, x, v, seconds):
                       f"compensated sums), {dt:.1f} s"}
 
 
+def sweep(binding, torch, ics, n):
+    """Force evaluations of random active subsets of the King model (the
+    split-j regime): one JSON line per n_active."""
+    import numpy as np
+    m, x, v = ics.king(n, 7.0, 4)
+    xt, vt, mt = (torch.as_tensor(q, device="cuda") for q in (x, v, m))
+    rng = np.random.default_rng(44)
+    for prec in (binding.MIXED, binding.FP64):
+        g = binding.NBody(m, x, v, eps=EPS, precision=prec, tuning="auto")
+        for na in (1, 4, 16, 64, 256, 1024, 4096, 16384, 65536):
+            ia = torch.as_tensor(np.sort(rng.choice(n, na, replace=False)).astype(np.int32),
+                                 device="cuda")
+            g.forces(xt, vt, mt, i_active=ia)
+            torch.cuda.synchronize()
+            reps = max(3, min(200, int(2e10 / (na * n))))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                g.forces(xt, vt, mt, i_active=ia)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            print(json.dumps({"workload": "sweep", "precision": "mixed" if prec else "fp64",
+                              "n": n, "n_active": na, "ms_per_eval": ms,
+                              "interactions_per_s": na * n / (ms * 1e-3),
+                              "j_bytes_per_s": 112.0 * n / (ms * 1e-3)}), flush=True)
+        g.close()
+
+
+def run_blocksteps(binding, torch, label, m, x, v, t_end, precision, cluster_offsets=None,
+                   eps=1e-3, level_min=3):
+    g = binding.NBody(m, x, v, eps=eps, precision=precision, eta=0.01, eta_start=0.01,
+                      level_min=level_min, level_max=20, cluster_offsets=cluster_offsets,
+                      tuning="auto")
+    e0 = g.energy()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, inter = g.step(t_end)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    e1 = g.energy()
+    st = g.stats()
+    de = abs(e1[:, 2] - e0[:, 2]) / abs(e0[:, 2])
+    lz = abs(e1[:, 5] - e0[:, 5])
+    out = {"workload": label, "precision": "mixed" if precision else "fp64", "n": int(m.shape[0]),
+           "clusters": int(e0.shape[0]), "t_end": t_end, "block_steps": steps,
+           "interactions": inter, "wall_s": wall, "interactions_per_s": inter / wall,
+           "dE_over_E_max": float(de.max()), "dE_over_E_median": float(sorted(de)[len(de) // 2]),
+           "dLz_max": float(lz.max()), "floor_clamps": st["floor_clamps"]}
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
+    if a.calibrate_copy:
+        calibrate_copy(a.calibrate_copy)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); the multi-GPU split is a "
               "design note, not a measured path", file=sys.stderr)
@@ -107,6 +182,24 @@ def main():
     import torch
 
     from paper_0909_0879_amd import binding, ics
+
+    if a.workload == "sweep":
+        sweep(binding, torch, ics, a.n)
+        return
+    if a.workload == "ensemble":
+        m, x, v, off = ics.ensemble(256, 256, 16384, seed=5000)
+        run_blocksteps(binding, torch, "ensemble", m, x, v, 0.25, binding.MIXED,
+                       cluster_offsets=off, eps=1e-3, level_min=3)
+        return
+    if a.workload == "blocksteps":
+        m, x, v = ics.plummer(65536, 2)
+        run_blocksteps(binding, torch, "plummer65536", m, x, v, 0.125, binding.FP64, eps=1e-3,
+                       level_min=3)
+        n3 = 262144
+        m, x, v = ics.plummer(n3, 3, masses=ics.salpeter_masses(n3, 3))
+        run_blocksteps(binding, torch, "salpeter262144", m, x, v, 0.0625, binding.MIXED,
+                       eps=1e-4, level_min=4)
+        return
 
     m, x, v = ics.king(a.n, 7.0, 4)
     mixed = time_path(binding, torch, m, x, v, binding.MIXED, a.steps, a.warmup)

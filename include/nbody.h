@@ -62,9 +62,13 @@ typedef enum nbody_status {
 typedef enum nbody_precision {
   /* plain FP64 arithmetic throughout */
   NBODY_FP64 = 0,
-  /* FP64 state, predictor/corrector and coordinate differences
-     x_j - x_i, v_j - v_i; FP32 rsqrt, r^-3 and jerk products, FP32 sums
-     over each j-tile folded into a compensated (TwoSum) FP32 hi/lo pair */
+  /* FP64 state, predictor and corrector; x_j - x_i formed from the FP64
+     predicted positions split into double-single FP32 pairs (the paper's
+     software double precision, Sect. 5); FP32 v_j - v_i, rsqrt, r^-3 and
+     jerk products; FP32 sums of every 64 j folded into a compensated
+     (TwoSum) FP32 hi/lo pair.  Particles whose acceleration is dominated
+     by a single term (see nbody_tuning.refine_ratio) are re-evaluated in
+     FP64. */
   NBODY_MIXED = 1
 } nbody_precision;
 
@@ -154,7 +158,8 @@ int nbody_sync(nbody_ctx *c);
 
 /* Per-context counters since nbody_init (host, 8 int64): block steps,
  * interactions (n_active * n_cluster summed over steps), clamps at the
- * smallest step, current time of cluster 0 in ticks, and 4 reserved.
+ * smallest step, current time of cluster 0 in ticks, particles re-evaluated
+ * in FP64 by the mixed path (steps and nbody_forces), and 3 reserved.
  * Syncs. */
 int nbody_stats(nbody_ctx *c, int64_t *out8);
 
@@ -194,6 +199,11 @@ typedef struct nbody_tuning {
                                launches (results are identical) */
   int32_t steps_per_launch; /* block steps per graph launch / host check */
   int32_t min_split_j;      /* smallest j range of one split (>= 64) */
+  float refine_ratio;       /* mixed path: particles whose largest single
+                               acceleration term, bounded by max_j m_j/s_ij,
+                               exceeds refine_ratio times their net
+                               acceleration are re-evaluated with the FP64
+                               kernel (default 1; < 0 disables) */
   int32_t i_slots[NBODY_TUNE_BUCKETS];
   int32_t target_items[NBODY_TUNE_BUCKETS];
 } nbody_tuning;

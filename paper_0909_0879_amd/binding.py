@@ -49,13 +49,14 @@ class Params(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [
         ("variant", C.c_int32), ("use_graph", C.c_int32), ("steps_per_launch", C.c_int32),
-        ("min_split_j", C.c_int32),
+        ("min_split_j", C.c_int32), ("refine_ratio", C.c_float),
         ("i_slots", C.c_int32 * TUNE_BUCKETS), ("target_items", C.c_int32 * TUNE_BUCKETS),
     ]
 
     def as_dict(self):
         return {"variant": self.variant, "use_graph": self.use_graph,
                 "steps_per_launch": self.steps_per_launch, "min_split_j": self.min_split_j,
+                "refine_ratio": self.refine_ratio,
                 "i_slots": list(self.i_slots), "target_items": list(self.target_items)}
 
     @classmethod
@@ -65,6 +66,7 @@ class Tuning(C.Structure):
         t.use_graph = int(d.get("use_graph", 0))
         t.steps_per_launch = int(d.get("steps_per_launch", 0))
         t.min_split_j = int(d.get("min_split_j", 0))
+        t.refine_ratio = float(d.get("refine_ratio", 0.0))
         for b, v in enumerate(d.get("i_slots", [0] * TUNE_BUCKETS)):
             t.i_slots[b] = int(v)
         for b, v in enumerate(d.get("target_items", [0] * TUNE_BUCKETS)):
@@ -245,7 +247,7 @@ class NBody:
         out = np.zeros(8, np.int64)
         check(lib().nbody_stats(self.ctx, out.ctypes.data_as(C.c_void_p)), "nbody_stats")
         return {"block_steps": int(out[0]), "interactions": int(out[1]),
-                "floor_clamps": int(out[2]), "t_tick": int(out[3])}
+                "floor_clamps": int(out[2]), "t_tick": int(out[3]), "refined": int(out[4])}
 
     def get_tuning(self) -> dict:
         t = Tuning()

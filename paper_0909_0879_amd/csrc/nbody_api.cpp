@@ -32,6 +32,9 @@ int fail(int code, const std::string &msg) {
 
 constexpr size_t kAlign = 256;
 constexpr int kEvPairs = 1024;
+// mixed path: re-evaluate in FP64 the particles whose largest acceleration
+// term exceeds this multiple of their net acceleration
+constexpr float kDefaultRefineRatio = 1.0f;
 constexpr int64_t kMaxN = (int64_t)1 << 30;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -72,6 +75,11 @@ size_t carve(int64_t n, int32_t C, char *base, Dev *d) {
   t.plan_lpt = (nbk::ClusterPlan *)take(sizeof(nbk::ClusterPlan) * C);
   t.item_prefix = (int32_t *)take(sizeof(int32_t) * (C + 1));
   t.partial = (double *)take(sizeof(double) * nbk::kRowStride * t.rows_cap);
+  t.fsum = (double *)take(sizeof(double) * 6 * t.cap_active);
+  t.rflag = (int32_t *)take(sizeof(int32_t) * t.cap_active);
+  t.ref_i = (int32_t *)take(sizeof(int32_t) * t.cap_active);
+  t.ref_k = (int32_t *)take(sizeof(int32_t) * t.cap_active);
+  t.ref_off = (int32_t *)take(sizeof(int32_t) * (C + 1));
   t.work = (int32_t *)take(sizeof(int32_t) * 4);
   t.err = (int32_t *)take(sizeof(int32_t) * 4);
   t.ctr = (int64_t *)take(sizeof(int64_t) * nbk::kCtrCount);
@@ -138,6 +146,7 @@ nbody_tuning default_tuning(int precision) {
   t.use_graph = NBODY_GRAPH_ON;
   t.steps_per_launch = 16;
   t.min_split_j = 256;
+  t.refine_ratio = (precision == NBODY_MIXED) ? kDefaultRefineRatio : -1.0f;
   const int K = (t.variant == NBODY_VARIANT_K2) ? 2 : 1;
   for (int b = 0; b < NBODY_TUNE_BUCKETS; ++b) {
     // one i-tile covers the bucket [2^b, 2^(b+1)) when possible
@@ -180,6 +189,7 @@ struct nbody_ctx {
   nbody_tuning tune{};
   int K = 1;
   int grid_state = 0, grid_raw = 0, grid_pot = 0;
+  int grid_ref_state = 0, grid_ref_raw = 0;   // FP64 K = 1 re-evaluation
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_steps = 0;
@@ -222,7 +232,10 @@ int refresh_grids(nbody_ctx *c) {
   c->grid_state = nbk::force_grid_size(mode_of(c), nbk::kSrcState, c->K, c->device);
   c->grid_raw = nbk::force_grid_size(mode_of(c), nbk::kSrcRaw, c->K, c->device);
   c->grid_pot = nbk::force_grid_size(nbk::kModePot, nbk::kSrcState, 1, c->device);
-  if (c->grid_state < 1 || c->grid_raw < 1 || c->grid_pot < 1)
+  c->grid_ref_state = nbk::force_grid_size(nbk::kModeFP64, nbk::kSrcState, 1, c->device);
+  c->grid_ref_raw = nbk::force_grid_size(nbk::kModeFP64, nbk::kSrcRaw, 1, c->device);
+  if (c->grid_state < 1 || c->grid_raw < 1 || c->grid_pot < 1 || c->grid_ref_state < 1 ||
+      c->grid_ref_raw < 1)
     return fail(NBODY_EHIP, "could not size the force kernel grid");
   return NBODY_OK;
 }
@@ -230,15 +243,15 @@ int refresh_grids(nbody_ctx *c) {
 int harvest_events(nbody_ctx *c);
 
 // Launch the force kernel, bracketed by timing events when profiling.
-int force_launch(nbody_ctx *c, int mode, int src, int K, const nbk::RawSrc *raw, int grid,
-                 hipStream_t s) {
+int force_launch(nbody_ctx *c, int mode, int src, int K, const nbk::RawSrc *raw,
+                 const int32_t *list, int grid, hipStream_t s) {
   const bool prof = c->profiling && s == c->stream;
   if (prof && c->ev_used == kEvPairs) {
     int rc = harvest_events(c);
     if (rc) return rc;
   }
   if (prof) NB_HIP(hipEventRecord(c->ev[2 * c->ev_used], s));
-  NB_HIP(nbk::launch_force(c->d, mode, src, K, raw, grid, s));
+  NB_HIP(nbk::launch_force(c->d, mode, src, K, raw, list, grid, s));
   if (prof) {
     NB_HIP(hipEventRecord(c->ev[2 * c->ev_used + 1], s));
     ++c->ev_used;
@@ -260,14 +273,38 @@ int harvest_events(nbody_ctx *c) {
   return NBODY_OK;
 }
 
+float refine_ratio(const nbody_ctx *c) {
+  return (c->prec == NBODY_MIXED && c->tune.refine_ratio > 0.0f) ? c->tune.refine_ratio : 0.0f;
+}
+
+// Sum the partial rows into fsum and, on the mixed path, re-evaluate the
+// flagged entries with the FP64 kernel (a second plan over the flagged list).
+int sum_and_refine(nbody_ctx *c, const int32_t *list, int64_t na_host, const nbk::RawSrc *raw,
+                   hipStream_t s) {
+  const float ratio = refine_ratio(c);
+  NB_HIP(nbk::launch_sum_and_flag(c->d, list, na_host, ratio, s));
+  if (ratio <= 0.0f) return NBODY_OK;
+  const nbk::Tuning t1 = device_tuning(c, 1);
+  const bool api = raw != nullptr;
+  NB_HIP(nbk::launch_plan(c->d, t1, api ? nbk::kPlanApiRefine : nbk::kPlanRefine,
+                          api ? raw->n_j : 0, s));
+  int rc = force_launch(c, nbk::kModeFP64, api ? nbk::kSrcRaw : nbk::kSrcState, 1, raw,
+                        c->d.ref_i, api ? c->grid_ref_raw : c->grid_ref_state, s);
+  if (rc) return rc;
+  NB_HIP(nbk::launch_refine_finalize(c->d, s));
+  return NBODY_OK;
+}
+
 // One Hermite block step for every cluster, enqueued on s.
 int enqueue_block_step(nbody_ctx *c, hipStream_t s) {
   const nbk::Tuning t = device_tuning(c, c->K);
   NB_HIP(nbk::launch_sched(c->d, s));
   NB_HIP(nbk::launch_compact(c->d, s));
-  NB_HIP(nbk::launch_plan(c->d, t, 0, 0, s));
-  int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->grid_state, s);
+  NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanStep, 0, s));
+  int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->d.active,
+                        c->grid_state, s);
   if (rc) return rc;
+  if ((rc = sum_and_refine(c, c->d.active, -1, nullptr, s))) return rc;
   NB_HIP(nbk::launch_correct(c->d, c->eta, c->dt_shared, c->lmin, c->lmax, s));
   return NBODY_OK;
 }
@@ -315,9 +352,13 @@ int full_evaluation_into_state(nbody_ctx *c) {
   // initial forces: every particle active, predicted to its own time
   const nbk::Tuning t = device_tuning(c, c->K);
   NB_HIP(nbk::launch_all_active(c->d, c->stream));
-  NB_HIP(nbk::launch_plan(c->d, t, 1, 0, c->stream));
-  int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->grid_state, c->stream);
+  NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, c->stream));
+  int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->d.active,
+                        c->grid_state, c->stream);
   if (rc) return rc;
+  // all particles start at T = T_next = 0, so the re-evaluation plan
+  // (predicting to T_next) sees the same positions
+  if ((rc = sum_and_refine(c, c->d.active, -1, nullptr, c->stream))) return rc;
   NB_HIP(nbk::launch_init_levels(c->d, c->eta_start, c->dt_shared, c->lmin, c->lmax,
                                  c->stream));
   return NBODY_OK;
@@ -420,9 +461,11 @@ int nbody_forces(nbody_ctx *c, const int32_t *i_active, int64_t n_active, const 
     r.acc = acc + 3 * k0;
     r.jerk = jerk + 3 * k0;
     NB_HIP(nbk::launch_api_group(c->d, r, c->stream));
-    NB_HIP(nbk::launch_plan(c->d, t, 2, r.n_j, c->stream));
-    int rc = force_launch(c, mode_of(c), nbk::kSrcRaw, c->K, &r, c->grid_raw, c->stream);
+    NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanApi, r.n_j, c->stream));
+    int rc = force_launch(c, mode_of(c), nbk::kSrcRaw, c->K, &r, r.i_active, c->grid_raw,
+                          c->stream);
     if (rc) return rc;
+    if ((rc = sum_and_refine(c, r.i_active, r.n_active, &r, c->stream))) return rc;
     NB_HIP(nbk::launch_api_finalize(c->d, r, c->stream));
   }
   return NBODY_OK;
@@ -473,8 +516,9 @@ int nbody_energy(nbody_ctx *c, double *out) {
   if (!c || !out) return fail(NBODY_EINVAL, "NULL argument");
   const nbk::Tuning t = device_tuning(c, 1);
   NB_HIP(nbk::launch_all_active(c->d, c->stream));
-  NB_HIP(nbk::launch_plan(c->d, t, 1, 0, c->stream));
-  int rc0 = force_launch(c, nbk::kModePot, nbk::kSrcState, 1, nullptr, c->grid_pot, c->stream);
+  NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, c->stream));
+  int rc0 = force_launch(c, nbk::kModePot, nbk::kSrcState, 1, nullptr, c->d.active, c->grid_pot,
+                         c->stream);
   if (rc0) return rc0;
   NB_HIP(nbk::launch_energy_reduce(c->d, c->stream));
   NB_HIP(hipMemcpyAsync(out, c->d.eout, sizeof(double) * 9 * c->C, hipMemcpyDeviceToHost,
@@ -524,7 +568,8 @@ int nbody_stats(nbody_ctx *c, int64_t *out8) {
   out8[1] = c->pinned[nbk::kCtrInter];
   out8[2] = c->pinned[nbk::kCtrFloor];
   out8[3] = c->T_host[0];
-  out8[4] = out8[5] = out8[6] = out8[7] = 0;
+  out8[4] = c->pinned[nbk::kCtrRefined];
+  out8[5] = out8[6] = out8[7] = 0;
   return NBODY_OK;
 }
 
@@ -606,6 +651,10 @@ int nbody_set_tuning(nbody_ctx *c, const nbody_tuning *t) {
   if (t->min_split_j) {
     if (t->min_split_j < 64) return fail(NBODY_EINVAL, "min_split_j must be >= 64");
     n.min_split_j = t->min_split_j;
+  }
+  if (t->refine_ratio != 0.0f) {
+    if (!std::isfinite(t->refine_ratio)) return fail(NBODY_EINVAL, "refine_ratio must be finite");
+    n.refine_ratio = t->refine_ratio;
   }
   for (int b = 0; b < NBODY_TUNE_BUCKETS; ++b) {
     if (t->i_slots[b]) {

@@ -17,7 +17,8 @@ constexpr int kMaxClusters = 4096;
 constexpr int kScanBlock = 1024;    // particles per block of the compaction
 constexpr int kBuckets = 25;        // tuning buckets floor(log2(n_active))
 constexpr int kNoActive = 99;       // threshold level meaning "nothing due"
-constexpr int kRowStride = 6;       // doubles per partial row: a(3), jerk(3)
+constexpr int kRowStride = 8;       // doubles per partial row: a(3), jerk(3),
+                                    // bound on the largest acc term, pad
 
 enum ErrBits : int32_t { kErrNonFinite = 1, kErrDomain = 2, kErrIndex = 4 };
 
@@ -28,6 +29,7 @@ enum Ctr : int {
   kCtrFloor = 2,        // steps clamped at 2^-level_max
   kCtrNotDone = 3,      // clusters still short of t_end after the last step
   kCtrTend = 4,         // t_end in ticks for nbody_step
+  kCtrRefined = 5,      // entries re-evaluated in FP64 (mixed path)
   kCtrCount = 8
 };
 
@@ -53,6 +55,16 @@ struct Tuning {     // device copy of the launch policy (passed by value)
   int32_t target_items[kBuckets];
   int32_t min_split_j;
   int32_t K;        // i-particles per thread slot (1 or 2)
+};
+
+// Plan kinds (k_plan): which time the particles are predicted to, where the
+// j range comes from, and whether the step is committed.
+enum PlanKind : int {
+  kPlanStep = 0,     // block step: predict to T_next, commit T = T_next, count
+  kPlanState = 1,    // init / energy: predict to T
+  kPlanApi = 2,      // nbody_forces: caller's j arrays
+  kPlanRefine = 3,   // FP64 re-evaluation inside a block step (T_next)
+  kPlanApiRefine = 4 // FP64 re-evaluation inside nbody_forces
 };
 
 // Device pointers carved from the caller's workspace.
@@ -85,6 +97,12 @@ struct Dev {
   ClusterPlan *plan_lpt;  // C, largest item cost first
   int32_t *item_prefix;   // C + 1 (LPT order)
   double *partial;        // rows_cap * kRowStride
+  // per active entry k: summed acceleration and jerk, refinement flag
+  double *fsum;           // cap_active * 6
+  int32_t *rflag;         // cap_active
+  int32_t *ref_i;         // cap_active: particles re-evaluated in FP64
+  int32_t *ref_k;         // cap_active: their active-list positions
+  int32_t *ref_off;       // C + 1: per-cluster offsets in ref_i (last = count)
   // words
   int32_t *work;       // item counter of the persistent force kernel
   int32_t *err;        // sticky error bits
@@ -113,10 +131,17 @@ hipError_t launch_init_state(const Dev &d, const double *m, const double *x,
 hipError_t launch_all_active(const Dev &d, hipStream_t s);
 hipError_t launch_sched(const Dev &d, hipStream_t s);
 hipError_t launch_compact(const Dev &d, hipStream_t s);
-hipError_t launch_plan(const Dev &d, const Tuning &t, int use_T,
+hipError_t launch_plan(const Dev &d, const Tuning &t, int kind,
                        int64_t api_nj, hipStream_t s);
+// Sum each active entry's partial rows into fsum; with refine_ratio > 0 also
+// flag entries whose largest acceleration term exceeds refine_ratio times
+// their net acceleration, and build the grouped re-evaluation list.
+hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_host,
+                               float refine_ratio, hipStream_t s);
+hipError_t launch_refine_finalize(const Dev &d, hipStream_t s);
 hipError_t launch_force(const Dev &d, int mode, int src, int K,
-                        const RawSrc *raw, int grid, hipStream_t s);
+                        const RawSrc *raw, const int32_t *list, int grid,
+                        hipStream_t s);
 hipError_t launch_correct(const Dev &d, double eta, double dt_shared,
                           int level_min, int level_max, hipStream_t s);
 hipError_t launch_init_levels(const Dev &d, double eta_start,

@@ -200,9 +200,11 @@ __device__ __forceinline__ void pair_fp64(const I64 &I, int iidx, const JRec64 &
 // Mixed precision: x_j - x_i from the double-single pairs, (hi_j - hi_i) +
 // (lo_j - lo_i), which is the FP64 difference rounded to FP32 within an ulp
 // (the hi difference is exact for close pairs); everything after it in FP32.
-template <bool MASK>
+// SELF: this tile may hold the i-particle itself; its slot must not count in
+// the largest-term bound (its terms are exactly zero, but m_i / eps^2 is not).
+template <bool MASK, bool SELF>
 __device__ __forceinline__ void pair_mixed(const IDS &I, int iidx, const JRecDS &r,
-                                           float eps2, float *t, int &dom) {
+                                           float eps2, float *t, int &dom, float &tmx) {
   const float dx = (r.xh - I.xh[0]) + (r.xl - I.xl[0]);
   const float dy = (r.yh - I.xh[1]) + (r.yl - I.xl[1]);
   const float dz = (r.zh - I.xh[2]) + (r.zl - I.xl[2]);
@@ -217,8 +219,10 @@ __device__ __forceinline__ void pair_mixed(const IDS &I, int iidx, const JRecDS 
     }
   }
   const float rinv2 = rinv * rinv;
-  const float mr3 = (r.m * rinv) * rinv2;
+  const float mq = r.m * rinv2;       // m / s >= |this pair's acceleration term|
+  const float mr3 = mq * rinv;
   const float al = (3.0f * rv) * rinv2;
+  tmx = fmaxf(tmx, (SELF && r.idx == iidx) ? 0.0f : mq);
   t[0] = fmaf(mr3, dx, t[0]);
   t[1] = fmaf(mr3, dy, t[1]);
   t[2] = fmaf(mr3, dz, t[2]);
@@ -271,16 +275,16 @@ __device__ __forceinline__ void fold(typename Traits<MODE>::T (&t)[K][Traits<MOD
     }
 }
 
-template <int MODE, int K, bool MASK>
+template <int MODE, int K, bool MASK, bool SELF>
 __device__ __forceinline__ void pair_k(const typename Traits<MODE>::Rec &r,
                                        const typename Traits<MODE>::Ist (&I)[K],
                                        const int (&iidx)[K], double eps2,
                                        typename Traits<MODE>::T (&t)[K][Traits<MODE>::NC],
-                                       int (&dom)[K]) {
+                                       int (&dom)[K], float (&tmx)[K]) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     if constexpr (MODE == kModeMixed)
-      pair_mixed<MASK>(I[k], iidx[k], r, (float)eps2, t[k], dom[k]);
+      pair_mixed<MASK, SELF>(I[k], iidx[k], r, (float)eps2, t[k], dom[k], tmx[k]);
     else if constexpr (MODE == kModeFP64)
       pair_fp64<MASK>(I[k], iidx[k], r, eps2, t[k], dom[k]);
     else
@@ -292,30 +296,34 @@ __device__ __forceinline__ void pair_k(const typename Traits<MODE>::Rec &r,
 // compensated (hi, lo) pairs every FOLD records.  WIDE: every lane owns its
 // i (Q = 1); otherwise lane q of a slot takes records q, q + Q, ... and
 // folds once per tile.
-template <int MODE, int K, bool WIDE, bool MASK>
+template <int MODE, int K, bool WIDE, bool MASK, bool SELF>
 __device__ __forceinline__ void tile_loop(
     const typename Traits<MODE>::Rec *tile, int cnt, int q, int Q,
     const typename Traits<MODE>::Ist (&I)[K], const int (&iidx)[K], double eps2,
     typename Traits<MODE>::T (&t)[K][Traits<MODE>::NC],
     typename Traits<MODE>::T (&hi)[K][Traits<MODE>::NC],
-    typename Traits<MODE>::T (&lo)[K][Traits<MODE>::NC], int (&dom)[K]) {
+    typename Traits<MODE>::T (&lo)[K][Traits<MODE>::NC], int (&dom)[K],
+    float (&tmx)[K]) {
   constexpr int F = Traits<MODE>::FOLD;
   if (WIDE) {
     for (int j0 = 0; j0 < cnt; j0 += F) {
       const int j1 = (j0 + F < cnt) ? j0 + F : cnt;
 #pragma unroll 2
-      for (int jj = j0; jj < j1; ++jj) pair_k<MODE, K, MASK>(tile[jj], I, iidx, eps2, t, dom);
+      for (int jj = j0; jj < j1; ++jj)
+        pair_k<MODE, K, MASK, SELF>(tile[jj], I, iidx, eps2, t, dom, tmx);
       fold<MODE, K>(t, hi, lo);
     }
   } else {
-    for (int jj = q; jj < cnt; jj += Q) pair_k<MODE, K, MASK>(tile[jj], I, iidx, eps2, t, dom);
+    for (int jj = q; jj < cnt; jj += Q)
+      pair_k<MODE, K, MASK, SELF>(tile[jj], I, iidx, eps2, t, dom, tmx);
     fold<MODE, K>(t, hi, lo);
   }
 }
 
 struct ForceArgs {
   Dev d;
-  const int32_t *active;        // active list (internal or the caller's)
+  const int32_t *active;        // i list: internal active list, the caller's
+                                // i_active, or the FP64 re-evaluation list
   const double *rx, *rv, *rm;   // raw source (nbody_forces)
 };
 
@@ -329,6 +337,7 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
   constexpr int NC = Tr::NC;
   __shared__ Rec tile[kTJ];
   __shared__ double red[kWG / 64][K][NC];
+  __shared__ float red_t[kWG / 64][K];
   __shared__ int s_g;
   const Dev &d = A.d;
   const int tid = threadIdx.x;
@@ -384,10 +393,13 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
       make_i(xp, vp, I[k]);
     }
     T t[K][NC], shi[K][NC], slo[K][NC];
+    float tmx[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+    for (int k = 0; k < K; ++k) {
+      tmx[k] = 0.0f;
 #pragma unroll
       for (int c = 0; c < NC; ++c) t[k][c] = shi[k][c] = slo[k][c] = (T)0;
+    }
 
     const bool mask = (eps2 == 0.0);
     for (int64_t jt = js; jt < je; jt += kTJ) {
@@ -410,17 +422,27 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
         make_rec(xp, vp, m, (int32_t)j, r);
         tile[tid] = r;
       }
-      __syncthreads();
+      // the tile barrier also tells whether any i of this workgroup lies in
+      // the tile (a handful of tiles per item: the active list is ascending)
+      int mine = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) mine |= (iidx[k] >= jt && iidx[k] < jt + cnt);
+      const bool self_tile = __syncthreads_or(mine) != 0;
+      const bool msk = mask || MODE == kModePot;
       if (Q == 1) {
-        if (mask || MODE == kModePot)
-          tile_loop<MODE, K, true, true>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom);
+        if (msk)
+          tile_loop<MODE, K, true, true, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
+        else if (MODE == kModeMixed && self_tile)
+          tile_loop<MODE, K, true, false, true>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
         else
-          tile_loop<MODE, K, true, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom);
+          tile_loop<MODE, K, true, false, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
       } else {
-        if (mask || MODE == kModePot)
-          tile_loop<MODE, K, false, true>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom);
+        if (msk)
+          tile_loop<MODE, K, false, true, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
+        else if (MODE == kModeMixed && self_tile)
+          tile_loop<MODE, K, false, false, true>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
         else
-          tile_loop<MODE, K, false, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom);
+          tile_loop<MODE, K, false, false, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
       }
       __syncthreads();
     }
@@ -437,29 +459,37 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
       const int qw = Q < 64 ? Q : 64;
       for (int off = 1; off < qw; off <<= 1) {
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k) {
 #pragma unroll
           for (int c = 0; c < NC; ++c) res[k][c] += __shfl_xor(res[k][c], off);
+          tmx[k] = fmaxf(tmx[k], __shfl_xor(tmx[k], off));
+        }
       }
       if (Q > 64) {
         const int w = tid >> 6;
         if ((tid & 63) == 0) {
 #pragma unroll
-          for (int k = 0; k < K; ++k)
+          for (int k = 0; k < K; ++k) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) red[w][k][c] = res[k][c];
+            red_t[w][k] = tmx[k];
+          }
         }
         __syncthreads();
         if (q == 0) {
           const int nw = Q >> 6;   // waves of this slot: w .. w + nw - 1
 #pragma unroll
-          for (int k = 0; k < K; ++k)
+          for (int k = 0; k < K; ++k) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
               double s = red[w][k][c];
               for (int u = 1; u < nw; ++u) s += red[w + u][k][c];
               res[k][c] = s;
             }
+            float tm = red_t[w][k];
+            for (int u = 1; u < nw; ++u) tm = fmaxf(tm, red_t[w + u][k]);
+            tmx[k] = tm;
+          }
         }
         __syncthreads();
       }
@@ -472,6 +502,7 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
           double *row = d.partial + (cp.row_off + (int64_t)split * cp.na + slot) * kRowStride;
 #pragma unroll
           for (int c = 0; c < NC; ++c) row[c] = ok[k] ? res[k][c] : 0.0;
+          if (NC == 6) row[6] = ok[k] ? (double)tmx[k] : 0.0;
         }
       }
     }
@@ -693,6 +724,9 @@ __global__ __launch_bounds__(kWG) void k_scatter(Dev d) {
 // kind 1: init / energy (predict to T); kind 2: nbody_forces (raw source).
 __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
                                                 int64_t api_nj) {
+  const bool refine = (kind == kPlanRefine || kind == kPlanApiRefine);
+  const bool api = (kind == kPlanApi || kind == kPlanApiRefine);
+  const int32_t *offs = refine ? d.ref_off : d.act_off;
   __shared__ int64_t cost[kMaxClusters];
   __shared__ int64_t scan64[1024];
   const int C = d.C;
@@ -702,9 +736,9 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
   for (int c = threadIdx.x; c < C; c += 1024) {
     ClusterPlan cp;
     cp.c = c;
-    cp.act_off = d.act_off[c];
-    cp.na = d.act_off[c + 1] - cp.act_off;
-    if (kind == 2 && C == 1 && api_nj > 0) {
+    cp.act_off = offs[c];
+    cp.na = offs[c + 1] - cp.act_off;
+    if (api && C == 1 && api_nj > 0) {
       cp.jb = 0;
       cp.je = api_nj;
     } else {
@@ -712,7 +746,7 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
       cp.je = d.coff[c + 1];
     }
     const int64_t nc = cp.je - cp.jb;
-    cp.t_pred = (kind == 0) ? d.Tnext[c] : d.T[c];
+    cp.t_pred = (kind == kPlanStep || kind == kPlanRefine) ? d.Tnext[c] : d.T[c];
     cp.P = 256;
     cp.Qlog = 0;
     cp.S = 0;
@@ -754,7 +788,7 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
       my_inter += (int64_t)cp.na * nc;
       my_active += cp.na;
     }
-    if (kind == 0) {
+    if (kind == kPlanStep) {
       if (d.Tnext[c] < d.ctr[kCtrTend]) ++my_notdone;
     }
     d.plan_c[c] = cp;
@@ -809,7 +843,7 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
     d.item_prefix[C] = (int32_t)carry;
     *d.work = 0;
   }
-  if (kind == 0) {
+  if (kind == kPlanStep) {
     for (int c = threadIdx.x; c < C; c += 1024) d.T[c] = d.Tnext[c];
     // block totals (deterministic: integer atomics)
     if (my_inter) atomicAdd((unsigned long long *)&d.ctr[kCtrInter],
@@ -837,11 +871,10 @@ __global__ __launch_bounds__(kWG) void k_correct(Dev d, double eta,
        k += gridDim.x * blockDim.x) {
     const int64_t i = d.active[k];
     const int c = d.cid[i];
-    const ClusterPlan cp = d.plan_c[c];
-    const int slot = k - cp.act_off;
     double f[6];
-    sum_rows(d, cp, slot, 6, f);
-    const int64_t tn = cp.t_pred;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) f[q] = d.fsum[6 * (int64_t)k + q];
+    const int64_t tn = d.Tnext[c];
     const double h = (double)(tn - d.tick[i]) * kTick;
     const double h2 = h * h, h3 = h2 * h;
     double x1[3], v1[3], a2e[3], a3v[3], a1[3], j1[3];
@@ -905,9 +938,9 @@ __global__ __launch_bounds__(kWG) void k_init_levels(Dev d, double eta_s,
   const int64_t i = i0 + threadIdx.x;
   if (i < n) {
     const int c = d.cid[i];
-    const ClusterPlan cp = d.plan_c[c];
     double f[6];
-    sum_rows(d, cp, (int)(i - cp.act_off), 6, f);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) f[q] = d.fsum[6 * i + q];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       d.a[q * n + i] = f[q];
@@ -971,25 +1004,173 @@ __global__ void k_api_group(Dev d, const int32_t *ia, int64_t na) {
 __global__ void k_api_finalize(Dev d, int64_t na, double *acc, double *jerk) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < na;
        k += (int64_t)gridDim.x * blockDim.x) {
-    int c = 0;
-    if (d.C > 1) {   // largest c with act_off[c] <= k, among non-empty groups
-      int lo = 0, hi = d.C;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (d.act_off[mid] <= k) lo = mid; else hi = mid;
-      }
-      c = lo;
-    }
-    const ClusterPlan cp = d.plan_c[c];
-    double f[6] = {0, 0, 0, 0, 0, 0};
-    const int slot = (int)(k - cp.act_off);
-    if (slot >= 0 && slot < cp.na && cp.S > 0) sum_rows(d, cp, slot, 6, f);
+    double f[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) f[q] = d.fsum[6 * k + q];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       acc[3 * k + q] = f[q];
       jerk[3 * k + q] = f[3 + q];
     }
     if (!(finite3(f) && finite3(f + 3))) atomicOr(d.err, (int)kErrNonFinite);
+  }
+}
+
+// Cluster of active entry k: from the particle (state lists) or from the
+// group offsets (caller's lists, where i indexes the caller's arrays).
+__device__ __forceinline__ int entry_cluster(const Dev &d, const int32_t *list,
+                                            int64_t k, bool api) {
+  if (d.C == 1) return 0;
+  if (!api) return d.cid[list[k]];
+  int lo = 0, hi = d.C;   // largest c with act_off[c] <= k
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (d.act_off[mid] <= k) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Sum the partial rows of every active entry (split order, compensated) into
+// fsum.  With ratio > 0 (mixed path), flag the entries whose bound on the
+// largest single acceleration term, max_j m_j / s_ij, exceeds ratio times the
+// net acceleration: there the FP32 error of that term is not small against
+// the result, and the entry is re-evaluated in FP64.
+__global__ __launch_bounds__(kWG) void k_sum_flag(Dev d, const int32_t *list,
+                                                  int64_t na_host, float ratio) {
+  const bool api = na_host >= 0;
+  const int64_t total = api ? na_host : d.act_off[d.C];
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const ClusterPlan cp = d.plan_c[entry_cluster(d, list, k, api)];
+    const int slot = (int)(k - cp.act_off);
+    double s[6], cc[6];
+    double tmax = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s[c] = cc[c] = 0.0;
+    if (slot >= 0 && slot < cp.na) {
+      for (int sp = 0; sp < cp.S; ++sp) {
+        const double *row = d.partial + (cp.row_off + (int64_t)sp * cp.na + slot) * kRowStride;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const double x = row[c];
+          const double u = s[c] + x;
+          cc[c] += (fabs(s[c]) >= fabs(x)) ? (s[c] - u) + x : (x - u) + s[c];
+          s[c] = u;
+        }
+        tmax = fmax(tmax, row[6]);
+      }
+    }
+    double f[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      f[c] = s[c] + cc[c];
+      d.fsum[6 * k + c] = f[c];
+    }
+    int flag = 0;
+    if (ratio > 0.0f) {
+      const double an = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+      flag = !(tmax <= (double)ratio * an);
+    }
+    d.rflag[k] = flag;
+  }
+}
+
+// Ordered compaction of the flagged entries (blocks of kScanBlock entries).
+__global__ __launch_bounds__(kWG) void k_rcount(Dev d, int64_t na_host) {
+  __shared__ int sh[4];
+  const int64_t total = na_host >= 0 ? na_host : d.act_off[d.C];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
+  int cnt = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t k = base + e;
+    if (k < total && d.rflag[k]) ++cnt;
+  }
+  cnt = block_sum_i(cnt, sh);
+  if (threadIdx.x == 0) d.blk_cnt[blockIdx.x] = cnt;
+}
+
+__global__ __launch_bounds__(kWG) void k_rscatter(Dev d, const int32_t *list,
+                                                  int64_t na_host) {
+  __shared__ int wsum[4];
+  const int64_t total = na_host >= 0 ? na_host : d.act_off[d.C];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
+  int flag[4];
+  int cnt = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t k = base + e;
+    flag[e] = (k < total && d.rflag[k]) ? 1 : 0;
+    cnt += flag[e];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int incl = cnt;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int wbase = 0;
+  for (int u = 0; u < w; ++u) wbase += wsum[u];
+  int pos = d.blk_off[blockIdx.x] + wbase + incl - cnt;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (flag[e]) {
+      const int64_t k = base + e;
+      d.ref_i[pos] = list[k];
+      d.ref_k[pos] = (int32_t)k;
+      ++pos;
+    }
+  }
+}
+
+// Per-cluster offsets of the (cluster-grouped) re-evaluation list.
+__global__ void k_ref_offsets(Dev d, int api) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > d.C) return;
+  const int cnt = d.blk_off[d.nblk];
+  if (c == d.C) {
+    d.ref_off[c] = cnt;
+    d.ctr[kCtrRefined] += cnt;
+    return;
+  }
+  if (d.C == 1) {
+    d.ref_off[0] = 0;
+    return;
+  }
+  // entry r belongs to the cluster of active entry ref_k[r]
+  int lo = 0, hi = cnt;   // first r whose cluster >= c
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const int cm = api ? entry_cluster(d, nullptr, d.ref_k[mid], true) : d.cid[d.ref_i[mid]];
+    if (cm < c) lo = mid + 1; else hi = mid;
+  }
+  d.ref_off[c] = lo;
+}
+
+// Write the FP64 re-evaluations over the mixed sums of their entries.
+__global__ __launch_bounds__(kWG) void k_ref_final(Dev d) {
+  const int total = d.ref_off[d.C];
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < total;
+       r += gridDim.x * blockDim.x) {
+    int c = 0;
+    if (d.C > 1) {   // largest c with ref_off[c] <= r
+      int lo = 0, hi = d.C;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (d.ref_off[mid] <= r) lo = mid; else hi = mid;
+      }
+      c = lo;
+    }
+    const ClusterPlan cp = d.plan_c[c];
+    const int slot = r - cp.act_off;
+    double f[6];
+    sum_rows(d, cp, slot, 6, f);
+    const int64_t k = d.ref_k[r];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) d.fsum[6 * k + q] = f[q];
   }
 }
 
@@ -1190,14 +1371,14 @@ hipError_t launch_plan(const Dev &d, const Tuning &t, int kind, int64_t api_nj,
 }
 
 hipError_t launch_force(const Dev &d, int mode, int src, int K,
-                        const RawSrc *raw, int grid, hipStream_t s) {
+                        const RawSrc *raw, const int32_t *list, int grid,
+                        hipStream_t s) {
   ForceArgs A;
   A.d = d;
-  A.active = d.active;
+  A.active = list;
   A.rx = A.rv = A.rm = nullptr;
   if (src == kSrcRaw) {
     if (!raw) return hipErrorInvalidValue;
-    A.active = raw->i_active;
     A.rx = raw->x;
     A.rv = raw->v;
     A.rm = raw->m;
@@ -1232,6 +1413,27 @@ int force_grid_size(int mode, int src, int K, int device) {
   NB_CASE(kModePot, kSrcState, 1)
 #undef NB_CASE
   return 0;
+}
+
+hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_host,
+                               float refine_ratio, hipStream_t s) {
+  const int64_t cap = na_host >= 0 ? na_host : d.cap_active;
+  hipLaunchKernelGGL(k_sum_flag, dim3(grid_for(cap, kWG, 2048)), dim3(kWG), 0, s, d,
+                     list, na_host, refine_ratio);
+  if (refine_ratio > 0.0f) {
+    hipLaunchKernelGGL(k_rcount, dim3(d.nblk), dim3(kWG), 0, s, d, na_host);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d);
+    hipLaunchKernelGGL(k_rscatter, dim3(d.nblk), dim3(kWG), 0, s, d, list, na_host);
+    hipLaunchKernelGGL(k_ref_offsets, dim3((d.C + 1 + kWG - 1) / kWG), dim3(kWG), 0, s,
+                       d, na_host >= 0 ? 1 : 0);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_finalize(const Dev &d, hipStream_t s) {
+  hipLaunchKernelGGL(k_ref_final, dim3(grid_for(d.cap_active, kWG, 1024)), dim3(kWG), 0,
+                     s, d);
+  return hipGetLastError();
 }
 
 hipError_t launch_correct(const Dev &d, double eta, double dt_shared,
