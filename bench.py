@@ -53,6 +53,29 @@ def parse():
     return ap.parse_args()
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_0909_0879_amd", "csrc", "nbody_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_force_mixed_king1M.json")
+
+
+def kernel_hash() -> str:
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the mixed force kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter runs, scaled by the same counters' reading
+    of a plain copy of known size; None if the kernel source changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_sha256") != kernel_hash():
+        return None
+    return t["fetch_kib"] * 1024.0 * t["fetch_scale"] + t["write_kib"] * 1024.0 * t["write_scale"]
+
+
 def calibrate_copy(nbytes):
     """A plain device-to-device copy of known size, for counter scaling."""
     import torch
@@ -87,11 +110,13 @@ def time_path(binding, torch, m, x, v, precision, steps, warmup):
         inter += ni
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kms, launches = g.profile_read()
+    kms, launches, rms, rlaunches = g.profile_read()
     g.profile(False)
+    refined = g.stats()["refined"]
     g.close()
     return {"ms_per_step": 1e3 * wall / steps, "interactions": inter,
-            "rate": inter / wall, "kernel_ms": kms / max(launches, 1), "launches": launches}
+            "rate": inter / wall, "kernel_ms": kms / max(launches, 1), "launches": launches,
+            "refine_ms_per_step": rms / steps, "refined_total": refined}
 
 
 def cpu_baseline(m, x, v, seconds):
@@ -146,14 +171,22 @@ def sweep(binding, torch, ics, n):
 
 
 def run_blocksteps(binding, torch, label, m, x, v, t_end, precision, cluster_offsets=None,
-                   eps=1e-3, level_min=3):
+                   eps=1e-3, level_min=3, chunks=8):
+    """Hermite-4 block steps to t_end in `chunks` equal calls (the largest
+    step 2^-level_min divides each chunk); progress to stderr per chunk."""
     g = binding.NBody(m, x, v, eps=eps, precision=precision, eta=0.01, eta_start=0.01,
                       level_min=level_min, level_max=20, cluster_offsets=cluster_offsets,
                       tuning="auto")
     e0 = g.energy()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    steps, inter = g.step(t_end)
+    steps = inter = 0
+    for k in range(1, chunks + 1):
+        s_k, i_k = g.step(t_end * k / chunks)
+        steps += s_k
+        inter += i_k
+        print(f"{label}: t = {t_end * k / chunks:.5f}, {steps} block steps, "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     e1 = g.energy()
@@ -189,16 +222,16 @@ def main():
     if a.workload == "ensemble":
         m, x, v, off = ics.ensemble(256, 256, 16384, seed=5000)
         run_blocksteps(binding, torch, "ensemble", m, x, v, 0.25, binding.MIXED,
-                       cluster_offsets=off, eps=1e-3, level_min=3)
+                       cluster_offsets=off, eps=1e-3, level_min=5, chunks=8)
         return
     if a.workload == "blocksteps":
         m, x, v = ics.plummer(65536, 2)
         run_blocksteps(binding, torch, "plummer65536", m, x, v, 0.125, binding.FP64, eps=1e-3,
-                       level_min=3)
+                       level_min=6, chunks=8)
         n3 = 262144
         m, x, v = ics.plummer(n3, 3, masses=ics.salpeter_masses(n3, 3))
         run_blocksteps(binding, torch, "salpeter262144", m, x, v, 0.0625, binding.MIXED,
-                       eps=1e-4, level_min=4)
+                       eps=1e-4, level_min=7, chunks=8)
         return
 
     m, x, v = ics.king(a.n, 7.0, 4)
@@ -229,9 +262,11 @@ def main():
                    "n": n, "interactions_per_step": n * n},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "k_force<mixed,state,K>",
+                     "traffic": measured_traffic(), "kernel": "k_force<mixed,state,K>",
                      "kernel_ms": mixed["kernel_ms"],
                      "flops_per_launch": per_launch_flops},
+        "fp64_reevaluation": {"ms_per_step": mixed["refine_ms_per_step"],
+                              "particles_since_init": mixed["refined_total"]},
     }
     if fp64:
         f_ach = per_launch_flops / (fp64["kernel_ms"] * 1e-3) / 1e12

@@ -166,11 +166,14 @@ int nbody_stats(nbody_ctx *c, int64_t *out8);
 /* Kernel timing for measurement.  While enabled, block steps launch their
  * kernels eagerly (no graph; results are identical) and the library records
  * a pair of HIP events on the context's stream around every launch of the
- * force kernel (steps, nbody_forces, nbody_energy).  nbody_profile_read
- * syncs and returns the summed event time of those launches in ms and
- * their number since the previous read (either pointer may be NULL). */
+ * force kernel (steps and nbody_forces).  nbody_profile_read syncs and
+ * returns, since the previous read, the summed event time in ms and the
+ * number of launches of the context's own force kernel (FP64 or mixed) and,
+ * separately, of the FP64 re-evaluation launches of the mixed path (any
+ * pointer may be NULL). */
 int nbody_profile(nbody_ctx *c, int enable);
-int nbody_profile_read(nbody_ctx *c, double *force_ms, int64_t *force_launches);
+int nbody_profile_read(nbody_ctx *c, double *force_ms, int64_t *force_launches,
+                       double *refine_ms, int64_t *refine_launches);
 
 /* Free the host-side context (the workspace stays with the caller).  Waits
  * for outstanding work.  NULL is ignored. */

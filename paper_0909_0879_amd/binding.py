@@ -105,7 +105,7 @@ def lib():
         L.nbody_get_tuning.argtypes = [P, P]
         L.nbody_set_tuning.argtypes = [P, P]
         L.nbody_profile.argtypes = [P, C.c_int]
-        L.nbody_profile_read.argtypes = [P, P, P]
+        L.nbody_profile_read.argtypes = [P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -262,10 +262,12 @@ class NBody:
         check(lib().nbody_profile(self.ctx, 1 if enable else 0), "nbody_profile")
 
     def profile_read(self):
-        """(total ms, launches) of force-kernel launches since the last read."""
-        ms, nl = C.c_double(0.0), C.c_int64(0)
-        check(lib().nbody_profile_read(self.ctx, C.byref(ms), C.byref(nl)), "nbody_profile_read")
-        return ms.value, nl.value
+        """Force-kernel event time since the last read: (ms, launches) of the
+        context's own kernel and (ms, launches) of the FP64 re-evaluation."""
+        ms, nl, rms, rnl = C.c_double(0.0), C.c_int64(0), C.c_double(0.0), C.c_int64(0)
+        check(lib().nbody_profile_read(self.ctx, C.byref(ms), C.byref(nl), C.byref(rms),
+                                       C.byref(rnl)), "nbody_profile_read")
+        return ms.value, nl.value, rms.value, rnl.value
 
     def close(self):
         if getattr(self, "ctx", None) and self.ctx.value:

@@ -1016,6 +1016,61 @@ __global__ void k_api_finalize(Dev d, int64_t na, double *acc, double *jerk) {
   }
 }
 
+// Neumaier accumulation and the exact combination of two (sum, correction)
+// pairs; used for the fixed-order reductions over split rows.
+__device__ __forceinline__ void neu_add(double &s, double &c, double x) {
+  const double u = s + x;
+  c += (fabs(s) >= fabs(x)) ? (s - u) + x : (x - u) + s;
+  s = u;
+}
+
+// Wave-wide sum of NC compensated pairs over the 64 lanes (xor tree, same
+// order on every run); every lane ends with the total.
+template <int NC>
+__device__ __forceinline__ void wave_neu_reduce(double (&s)[NC], double (&c)[NC]) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const double os = __shfl_xor(s[q], off), oc = __shfl_xor(c[q], off);
+      // order the pair by lane so both lanes of a butterfly compute the
+      // identical value
+      const bool low = (threadIdx.x & off) == 0;
+      const double a = low ? s[q] : os, b = low ? os : s[q];
+      const double ca = low ? c[q] : oc, cb = low ? oc : c[q];
+      double t = a, tc = ca + cb;
+      neu_add(t, tc, b);
+      s[q] = t;
+      c[q] = tc;
+    }
+  }
+}
+
+// Sum the S partial rows of one slot with the 64 lanes of a wave: lane l
+// takes rows l, l + 64, ...; returns the 6 sums and the max of column 6.
+__device__ __forceinline__ void wave_sum_rows(const Dev &d, const ClusterPlan &cp, int slot,
+                                              double *out, double &tmax) {
+  const int lane = threadIdx.x & 63;
+  double s[6], c[6];
+  double tm = 0.0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) s[q] = c[q] = 0.0;
+  for (int sp = lane; sp < cp.S; sp += 64) {
+    const double *row = d.partial + (cp.row_off + (int64_t)sp * cp.na + slot) * kRowStride;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) neu_add(s[q], c[q], row[q]);
+    tm = fmax(tm, row[6]);
+  }
+  if (cp.S > 1) {
+    wave_neu_reduce<6>(s, c);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) tm = fmax(tm, __shfl_xor(tm, off));
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) out[q] = s[q] + c[q];
+  tmax = tm;
+}
+
 // Cluster of active entry k: from the particle (state lists) or from the
 // group offsets (caller's lists, where i indexes the caller's arrays).
 __device__ __forceinline__ int entry_cluster(const Dev &d, const int32_t *list,
@@ -1039,39 +1094,24 @@ __global__ __launch_bounds__(kWG) void k_sum_flag(Dev d, const int32_t *list,
                                                   int64_t na_host, float ratio) {
   const bool api = na_host >= 0;
   const int64_t total = api ? na_host : d.act_off[d.C];
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total;
-       k += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t k = wave; k < total; k += nwaves) {
     const ClusterPlan cp = d.plan_c[entry_cluster(d, list, k, api)];
     const int slot = (int)(k - cp.act_off);
-    double s[6], cc[6];
+    double f[6] = {0, 0, 0, 0, 0, 0};
     double tmax = 0.0;
+    if (slot >= 0 && slot < cp.na) wave_sum_rows(d, cp, slot, f, tmax);
+    if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) s[c] = cc[c] = 0.0;
-    if (slot >= 0 && slot < cp.na) {
-      for (int sp = 0; sp < cp.S; ++sp) {
-        const double *row = d.partial + (cp.row_off + (int64_t)sp * cp.na + slot) * kRowStride;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          const double x = row[c];
-          const double u = s[c] + x;
-          cc[c] += (fabs(s[c]) >= fabs(x)) ? (s[c] - u) + x : (x - u) + s[c];
-          s[c] = u;
-        }
-        tmax = fmax(tmax, row[6]);
+      for (int c = 0; c < 6; ++c) d.fsum[6 * k + c] = f[c];
+      int flag = 0;
+      if (ratio > 0.0f) {
+        const double an = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+        flag = !(tmax <= (double)ratio * an);
       }
+      d.rflag[k] = flag;
     }
-    double f[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      f[c] = s[c] + cc[c];
-      d.fsum[6 * k + c] = f[c];
-    }
-    int flag = 0;
-    if (ratio > 0.0f) {
-      const double an = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
-      flag = !(tmax <= (double)ratio * an);
-    }
-    d.rflag[k] = flag;
   }
 }
 
@@ -1153,8 +1193,9 @@ __global__ void k_ref_offsets(Dev d, int api) {
 // Write the FP64 re-evaluations over the mixed sums of their entries.
 __global__ __launch_bounds__(kWG) void k_ref_final(Dev d) {
   const int total = d.ref_off[d.C];
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < total;
-       r += gridDim.x * blockDim.x) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  for (int r = wave; r < total; r += nwaves) {
     int c = 0;
     if (d.C > 1) {   // largest c with ref_off[c] <= r
       int lo = 0, hi = d.C;
@@ -1165,12 +1206,13 @@ __global__ __launch_bounds__(kWG) void k_ref_final(Dev d) {
       c = lo;
     }
     const ClusterPlan cp = d.plan_c[c];
-    const int slot = r - cp.act_off;
-    double f[6];
-    sum_rows(d, cp, slot, 6, f);
-    const int64_t k = d.ref_k[r];
+    double f[6], tmax;
+    wave_sum_rows(d, cp, r - cp.act_off, f, tmax);
+    if ((threadIdx.x & 63) == 0) {
+      const int64_t k = d.ref_k[r];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) d.fsum[6 * k + q] = f[q];
+      for (int q = 0; q < 6; ++q) d.fsum[6 * k + q] = f[q];
+    }
   }
 }
 
@@ -1418,7 +1460,8 @@ int force_grid_size(int mode, int src, int K, int device) {
 hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_host,
                                float refine_ratio, hipStream_t s) {
   const int64_t cap = na_host >= 0 ? na_host : d.cap_active;
-  hipLaunchKernelGGL(k_sum_flag, dim3(grid_for(cap, kWG, 2048)), dim3(kWG), 0, s, d,
+  // one wave (64 lanes) per entry, grid-stride
+  hipLaunchKernelGGL(k_sum_flag, dim3(grid_for(cap * 64, kWG, 4096)), dim3(kWG), 0, s, d,
                      list, na_host, refine_ratio);
   if (refine_ratio > 0.0f) {
     hipLaunchKernelGGL(k_rcount, dim3(d.nblk), dim3(kWG), 0, s, d, na_host);
@@ -1431,8 +1474,8 @@ hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_hos
 }
 
 hipError_t launch_refine_finalize(const Dev &d, hipStream_t s) {
-  hipLaunchKernelGGL(k_ref_final, dim3(grid_for(d.cap_active, kWG, 1024)), dim3(kWG), 0,
-                     s, d);
+  hipLaunchKernelGGL(k_ref_final, dim3(grid_for(d.cap_active * 64, kWG, 2048)), dim3(kWG),
+                     0, s, d);
   return hipGetLastError();
 }
 
