@@ -80,6 +80,8 @@ size_t carve(int64_t n, int32_t C, char *base, Dev *d) {
   t.ref_i = (int32_t *)take(sizeof(int32_t) * t.cap_active);
   t.ref_k = (int32_t *)take(sizeof(int32_t) * t.cap_active);
   t.ref_off = (int32_t *)take(sizeof(int32_t) * (C + 1));
+  t.pred = (void *)take((size_t)64 * n);
+  t.pred_on = (int32_t *)take(sizeof(int32_t) * 4);
   t.work = (int32_t *)take(sizeof(int32_t) * 4);
   t.err = (int32_t *)take(sizeof(int32_t) * 4);
   t.ctr = (int64_t *)take(sizeof(int64_t) * nbk::kCtrCount);
@@ -247,14 +249,14 @@ int harvest_events(nbody_ctx *c);
 
 // Launch the force kernel, bracketed by timing events when profiling.
 int force_launch(nbody_ctx *c, int mode, int src, int K, const nbk::RawSrc *raw,
-                 const int32_t *list, int grid, hipStream_t s) {
+                 const int32_t *list, int grid, hipStream_t s, bool use_pred = false) {
   const bool prof = c->profiling && s == c->stream;
   if (prof && c->ev_used == kEvPairs) {
     int rc = harvest_events(c);
     if (rc) return rc;
   }
   if (prof) NB_HIP(hipEventRecord(c->ev[2 * c->ev_used], s));
-  NB_HIP(nbk::launch_force(c->d, mode, src, K, raw, list, grid, s));
+  NB_HIP(nbk::launch_force(c->d, mode, src, K, raw, list, use_pred, grid, s));
   if (prof) {
     NB_HIP(hipEventRecord(c->ev[2 * c->ev_used + 1], s));
     // the potential kernel (energy diagnostics) is not counted
@@ -308,8 +310,9 @@ int enqueue_block_step(nbody_ctx *c, hipStream_t s) {
   NB_HIP(nbk::launch_sched(c->d, s));
   NB_HIP(nbk::launch_compact(c->d, s));
   NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanStep, 0, s));
+  NB_HIP(nbk::launch_predict_all(c->d, mode_of(c), s));
   int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->d.active,
-                        c->grid_state, s);
+                        c->grid_state, s, /*use_pred=*/true);
   if (rc) return rc;
   if ((rc = sum_and_refine(c, c->d.active, -1, nullptr, s))) return rc;
   NB_HIP(nbk::launch_correct(c->d, c->eta, c->dt_shared, c->lmin, c->lmax, s));

@@ -103,6 +103,9 @@ struct Dev {
   int32_t *ref_i;         // cap_active: particles re-evaluated in FP64
   int32_t *ref_k;         // cap_active: their active-list positions
   int32_t *ref_off;       // C + 1: per-cluster offsets in ref_i (last = count)
+  // predicted j records of a block step with many active particles
+  void *pred;             // n records of 64 bytes (the LDS record format)
+  int32_t *pred_on;       // 1 when pred holds this step's predictions
   // words
   int32_t *work;       // item counter of the persistent force kernel
   int32_t *err;        // sticky error bits
@@ -139,9 +142,14 @@ hipError_t launch_plan(const Dev &d, const Tuning &t, int kind,
 hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_host,
                                float refine_ratio, hipStream_t s);
 hipError_t launch_refine_finalize(const Dev &d, hipStream_t s);
+// use_pred: the launch may read j (and i) records from d.pred when
+// *d.pred_on is set (block-step launches of the context's own mode only)
 hipError_t launch_force(const Dev &d, int mode, int src, int K,
-                        const RawSrc *raw, const int32_t *list, int grid,
-                        hipStream_t s);
+                        const RawSrc *raw, const int32_t *list, bool use_pred,
+                        int grid, hipStream_t s);
+// Predict every particle of the stepping clusters once, into d.pred, when at
+// least 1/16 of the particles are active (sets *d.pred_on accordingly).
+hipError_t launch_predict_all(const Dev &d, int mode, hipStream_t s);
 hipError_t launch_correct(const Dev &d, double eta, double dt_shared,
                           int level_min, int level_max, hipStream_t s);
 hipError_t launch_init_levels(const Dev &d, double eta_start,

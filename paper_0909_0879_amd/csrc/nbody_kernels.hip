@@ -325,7 +325,19 @@ struct ForceArgs {
   const int32_t *active;        // i list: internal active list, the caller's
                                 // i_active, or the FP64 re-evaluation list
   const double *rx, *rv, *rm;   // raw source (nbody_forces)
+  const int32_t *pred_on;       // non-null: d.pred may hold predicted records
 };
+
+__device__ __forceinline__ void rec_to_i(const JRec64 &r, I64 &s) {
+  s.x[0] = r.x; s.x[1] = r.y; s.x[2] = r.z;
+  s.v[0] = r.vx; s.v[1] = r.vy; s.v[2] = r.vz;
+}
+
+__device__ __forceinline__ void rec_to_i(const JRecDS &r, IDS &s) {
+  s.xh[0] = r.xh; s.xh[1] = r.yh; s.xh[2] = r.zh;
+  s.xl[0] = r.xl; s.xl[1] = r.yl; s.xl[2] = r.zl;
+  s.v[0] = r.vx; s.v[1] = r.vy; s.v[2] = r.vz;
+}
 
 // ------------------------------------------------------------ force kernel
 
@@ -342,6 +354,10 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
   const Dev &d = A.d;
   const int tid = threadIdx.x;
   const int n_items = d.item_prefix[d.C];
+  // records predicted once for this step (large active sets) or predicted
+  // here while the tile is filled (small active sets, other callers)
+  const bool use_pred = SRC == kSrcState && A.pred_on != nullptr && *A.pred_on != 0;
+  const Rec *pred = reinterpret_cast<const Rec *>(d.pred);
   for (;;) {
     if (tid == 0) s_g = atomicAdd(d.work, 1);
     __syncthreads();
@@ -381,6 +397,9 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
       double xp[3] = {0.0, 0.0, 0.0}, vp[3] = {0.0, 0.0, 0.0};
       if (!ok[k]) {
         iidx[k] = -1;
+      } else if (use_pred) {
+        rec_to_i(pred[iidx[k]], I[k]);
+        continue;
       } else if (SRC == kSrcState) {
         predict_state(d, iidx[k], cp.t_pred, xp, vp);
       } else {
@@ -404,7 +423,9 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
     const bool mask = (eps2 == 0.0);
     for (int64_t jt = js; jt < je; jt += kTJ) {
       const int cnt = (int)((je - jt < kTJ) ? je - jt : kTJ);
-      if (tid < cnt) {
+      if (tid < cnt && use_pred) {
+        tile[tid] = pred[jt + tid];
+      } else if (tid < cnt) {
         const int64_t j = jt + tid;
         double xp[3], vp[3], m;
         if (SRC == kSrcState) {
@@ -1016,6 +1037,30 @@ __global__ void k_api_finalize(Dev d, int64_t na, double *acc, double *jerk) {
   }
 }
 
+// Predict each particle of the stepping clusters once per block step into
+// the LDS record format, so that every workgroup's tile fill is a plain copy.
+// Only worth it when many particles are active (each j is then read by many
+// i-tiles); small steps keep the prediction fused into the tile fill.
+template <int MODE>
+__global__ __launch_bounds__(kWG) void k_predict_all(Dev d) {
+  using Rec = typename Traits<MODE>::Rec;
+  const int64_t total = d.act_off[d.C];
+  const bool on = total * 16 >= d.n;
+  const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gt == 0) *d.pred_on = on ? 1 : 0;
+  if (!on) return;
+  Rec *pred = reinterpret_cast<Rec *>(d.pred);
+  for (int64_t i = gt; i < d.n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = d.cid[i];
+    if (d.Lthr[c] == kNoActive) continue;     // cluster not stepping
+    double xp[3], vp[3];
+    predict_state(d, i, d.Tnext[c], xp, vp);
+    Rec r;
+    make_rec(xp, vp, d.m[i], (int32_t)i, r);
+    pred[i] = r;
+  }
+}
+
 // Neumaier accumulation and the exact combination of two (sum, correction)
 // pairs; used for the fixed-order reductions over split rows.
 __device__ __forceinline__ void neu_add(double &s, double &c, double x) {
@@ -1413,12 +1458,13 @@ hipError_t launch_plan(const Dev &d, const Tuning &t, int kind, int64_t api_nj,
 }
 
 hipError_t launch_force(const Dev &d, int mode, int src, int K,
-                        const RawSrc *raw, const int32_t *list, int grid,
-                        hipStream_t s) {
+                        const RawSrc *raw, const int32_t *list, bool use_pred,
+                        int grid, hipStream_t s) {
   ForceArgs A;
   A.d = d;
   A.active = list;
   A.rx = A.rv = A.rm = nullptr;
+  A.pred_on = use_pred ? d.pred_on : nullptr;
   if (src == kSrcRaw) {
     if (!raw) return hipErrorInvalidValue;
     A.rx = raw->x;
@@ -1455,6 +1501,15 @@ int force_grid_size(int mode, int src, int K, int device) {
   NB_CASE(kModePot, kSrcState, 1)
 #undef NB_CASE
   return 0;
+}
+
+hipError_t launch_predict_all(const Dev &d, int mode, hipStream_t s) {
+  const dim3 g(grid_for(d.n, kWG, 4096)), b(kWG);
+  if (mode == kModeMixed)
+    hipLaunchKernelGGL(k_predict_all<kModeMixed>, g, b, 0, s, d);
+  else
+    hipLaunchKernelGGL(k_predict_all<kModeFP64>, g, b, 0, s, d);
+  return hipGetLastError();
 }
 
 hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_host,
