@@ -189,10 +189,16 @@ const char *nbody_last_error(void);
  * (a power of two, 1..256; the other 256 / i_slots lanes split j inside the
  * workgroup) and the j range is split until the cluster has about
  * target_items[b] items.  variant selects the compiled kernel shape:
- * NBODY_VARIANT_K1 (one i per thread slot) or NBODY_VARIANT_K2 (two).
+ * NBODY_VARIANT_K1 (one i per thread slot) or NBODY_VARIANT_K2 (two), both
+ * staging j through LDS; NBODY_VARIANT_S1 / _S2 add the broadcast kernel
+ * (j records read into scalar registers) for evaluations with at least
+ * n_j / 16 active particles and i_slots = 256 in every cluster, with one or
+ * two i per lane (the LDS kernel with the same K takes the others).  All
+ * variants with the same K give bitwise-identical results.
  * Zero fields keep the defaults. */
 #define NBODY_TUNE_BUCKETS 25
-enum { NBODY_VARIANT_DEFAULT = 0, NBODY_VARIANT_K1 = 1, NBODY_VARIANT_K2 = 2 };
+enum { NBODY_VARIANT_DEFAULT = 0, NBODY_VARIANT_K1 = 1, NBODY_VARIANT_K2 = 2,
+       NBODY_VARIANT_S1 = 3, NBODY_VARIANT_S2 = 4 };
 enum { NBODY_GRAPH_ON = 1, NBODY_GRAPH_OFF = 2 };
 
 typedef struct nbody_tuning {

@@ -4,7 +4,8 @@ For one precision and system size it times nbody_forces on random active
 subsets of every size bucket 2^b and picks, per bucket, the number of
 i thread-slots per workgroup (the rest of the 256 lanes split j inside the
 workgroup) and the work-item target of the j-split; the kernel variant (one
-or two i-particles per slot) is chosen on the full evaluation.  Results are
+or two i-particles per slot, j staged through LDS or broadcast from scalar
+registers) is chosen on the full evaluation.  Results are
 cached as JSON keyed by device architecture, precision and log2(N).
 
 Every candidate computes the same sums in a different order, so tuning only
@@ -66,14 +67,14 @@ def tune(n: int, precision: int, eps: float = 1e-3, seed: int = 77, buckets=None
     # 1. kernel variant on the full evaluation
     full = torch.arange(n, dtype=torch.int32, device="cuda")
     best_var, best_t = None, math.inf
-    for var in (binding.VARIANT_K1, binding.VARIANT_K2):
+    for var in (binding.VARIANT_K1, binding.VARIANT_K2, binding.VARIANT_S1, binding.VARIANT_S2):
         g.set_tuning({"variant": var})
         t = _time_forces(g, xt, vt, mt, full, 2)
         if verbose:
             print(f"variant {var}: full evaluation {t:.2f} ms", flush=True)
         if t < best_t:
             best_var, best_t = var, t
-    K = 2 if best_var == binding.VARIANT_K2 else 1
+    K = 2 if best_var in (binding.VARIANT_K2, binding.VARIANT_S2) else 1
     slots = list(base["i_slots"])
     targets = list(base["target_items"])
     # 2. per bucket: i-slots and split target

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libnbody.so")
 
 OK, EINVAL, ENODEV, ENOMEM, EHIP, EINDEX, ENONFINITE, EDOMAIN = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, MIXED = 0, 1
-VARIANT_DEFAULT, VARIANT_K1, VARIANT_K2 = 0, 1, 2
+VARIANT_DEFAULT, VARIANT_K1, VARIANT_K2, VARIANT_S1, VARIANT_S2 = 0, 1, 2, 3, 4
 GRAPH_ON, GRAPH_OFF = 1, 2
 TUNE_BUCKETS = 25
 TICK_BITS = 20

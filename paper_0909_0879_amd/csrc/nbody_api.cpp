@@ -192,7 +192,8 @@ struct nbody_ctx {
   Dev d{};
   nbody_tuning tune{};
   int K = 1;
-  int grid_state = 0, grid_raw = 0, grid_pot = 0;
+  bool sb = false;                // broadcast kernel for large evaluations
+  int grid_state = 0, grid_raw = 0, grid_pot = 0, grid_sb = 0;
   int grid_ref_state = 0, grid_ref_raw = 0;   // FP64 K = 1 re-evaluation
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -233,14 +234,17 @@ void drop_graph(nbody_ctx *c) {
 }
 
 int refresh_grids(nbody_ctx *c) {
-  c->K = (c->tune.variant == NBODY_VARIANT_K2) ? 2 : 1;
+  const int v = c->tune.variant;
+  c->K = (v == NBODY_VARIANT_K2 || v == NBODY_VARIANT_S2) ? 2 : 1;
+  c->sb = (v == NBODY_VARIANT_S1 || v == NBODY_VARIANT_S2);
+  c->grid_sb = c->sb ? nbk::force_sb_grid_size(mode_of(c), c->K, c->device) : 1;
   c->grid_state = nbk::force_grid_size(mode_of(c), nbk::kSrcState, c->K, c->device);
   c->grid_raw = nbk::force_grid_size(mode_of(c), nbk::kSrcRaw, c->K, c->device);
   c->grid_pot = nbk::force_grid_size(nbk::kModePot, nbk::kSrcState, 1, c->device);
   c->grid_ref_state = nbk::force_grid_size(nbk::kModeFP64, nbk::kSrcState, 1, c->device);
   c->grid_ref_raw = nbk::force_grid_size(nbk::kModeFP64, nbk::kSrcRaw, 1, c->device);
   if (c->grid_state < 1 || c->grid_raw < 1 || c->grid_pot < 1 || c->grid_ref_state < 1 ||
-      c->grid_ref_raw < 1)
+      c->grid_ref_raw < 1 || c->grid_sb < 1)
     return fail(NBODY_EHIP, "could not size the force kernel grid");
   return NBODY_OK;
 }
@@ -248,15 +252,20 @@ int refresh_grids(nbody_ctx *c) {
 int harvest_events(nbody_ctx *c);
 
 // Launch the force kernel, bracketed by timing events when profiling.
+// rec_kind >= 0 (a PlanKind): build the evaluation's j records first when its
+// active set is large, and let the broadcast kernel take it when enabled.
 int force_launch(nbody_ctx *c, int mode, int src, int K, const nbk::RawSrc *raw,
-                 const int32_t *list, int grid, hipStream_t s, bool use_pred = false) {
+                 const int32_t *list, int grid, hipStream_t s, int rec_kind = -1) {
   const bool prof = c->profiling && s == c->stream;
+  const bool use_pred = rec_kind >= 0;
+  if (use_pred) NB_HIP(nbk::launch_records(c->d, mode, rec_kind, raw, c->sb, s));
   if (prof && c->ev_used == kEvPairs) {
     int rc = harvest_events(c);
     if (rc) return rc;
   }
   if (prof) NB_HIP(hipEventRecord(c->ev[2 * c->ev_used], s));
   NB_HIP(nbk::launch_force(c->d, mode, src, K, raw, list, use_pred, grid, s));
+  if (use_pred && c->sb) NB_HIP(nbk::launch_force_sb(c->d, mode, K, raw, list, c->grid_sb, s));
   if (prof) {
     NB_HIP(hipEventRecord(c->ev[2 * c->ev_used + 1], s));
     // the potential kernel (energy diagnostics) is not counted
@@ -310,9 +319,8 @@ int enqueue_block_step(nbody_ctx *c, hipStream_t s) {
   NB_HIP(nbk::launch_sched(c->d, s));
   NB_HIP(nbk::launch_compact(c->d, s));
   NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanStep, 0, s));
-  NB_HIP(nbk::launch_predict_all(c->d, mode_of(c), s));
   int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->d.active,
-                        c->grid_state, s, /*use_pred=*/true);
+                        c->grid_state, s, nbk::kPlanStep);
   if (rc) return rc;
   if ((rc = sum_and_refine(c, c->d.active, -1, nullptr, s))) return rc;
   NB_HIP(nbk::launch_correct(c->d, c->eta, c->dt_shared, c->lmin, c->lmax, s));
@@ -364,7 +372,7 @@ int full_evaluation_into_state(nbody_ctx *c) {
   NB_HIP(nbk::launch_all_active(c->d, c->stream));
   NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, c->stream));
   int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->d.active,
-                        c->grid_state, c->stream);
+                        c->grid_state, c->stream, nbk::kPlanState);
   if (rc) return rc;
   // all particles start at T = T_next = 0, so the re-evaluation plan
   // (predicting to T_next) sees the same positions
@@ -473,7 +481,7 @@ int nbody_forces(nbody_ctx *c, const int32_t *i_active, int64_t n_active, const 
     NB_HIP(nbk::launch_api_group(c->d, r, c->stream));
     NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanApi, r.n_j, c->stream));
     int rc = force_launch(c, mode_of(c), nbk::kSrcRaw, c->K, &r, r.i_active, c->grid_raw,
-                          c->stream);
+                          c->stream, nbk::kPlanApi);
     if (rc) return rc;
     if ((rc = sum_and_refine(c, r.i_active, r.n_active, &r, c->stream))) return rc;
     NB_HIP(nbk::launch_api_finalize(c->d, r, c->stream));
@@ -648,7 +656,8 @@ int nbody_set_tuning(nbody_ctx *c, const nbody_tuning *t) {
   if (!c || !t) return fail(NBODY_EINVAL, "NULL argument");
   nbody_tuning n = c->tune;
   if (t->variant) {
-    if (t->variant != NBODY_VARIANT_K1 && t->variant != NBODY_VARIANT_K2)
+    if (t->variant != NBODY_VARIANT_K1 && t->variant != NBODY_VARIANT_K2 &&
+        t->variant != NBODY_VARIANT_S1 && t->variant != NBODY_VARIANT_S2)
       return fail(NBODY_EINVAL, "unknown variant");
     n.variant = t->variant;
   }

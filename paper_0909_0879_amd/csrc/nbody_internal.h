@@ -103,9 +103,9 @@ struct Dev {
   int32_t *ref_i;         // cap_active: particles re-evaluated in FP64
   int32_t *ref_k;         // cap_active: their active-list positions
   int32_t *ref_off;       // C + 1: per-cluster offsets in ref_i (last = count)
-  // predicted j records of a block step with many active particles
+  // j records of an evaluation with many active particles
   void *pred;             // n records of 64 bytes (the LDS record format)
-  int32_t *pred_on;       // 1 when pred holds this step's predictions
+  int32_t *pred_on;       // 0 none, 1 built, 2 built for the broadcast kernel
   // words
   int32_t *work;       // item counter of the persistent force kernel
   int32_t *err;        // sticky error bits
@@ -142,14 +142,22 @@ hipError_t launch_plan(const Dev &d, const Tuning &t, int kind,
 hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_host,
                                float refine_ratio, hipStream_t s);
 hipError_t launch_refine_finalize(const Dev &d, hipStream_t s);
-// use_pred: the launch may read j (and i) records from d.pred when
-// *d.pred_on is set (block-step launches of the context's own mode only)
+// use_pred: the launch reads j (and i) records from d.pred when *d.pred_on
+// is 1, and leaves the evaluation to the broadcast kernel when it is 2
 hipError_t launch_force(const Dev &d, int mode, int src, int K,
                         const RawSrc *raw, const int32_t *list, bool use_pred,
                         int grid, hipStream_t s);
-// Predict every particle of the stepping clusters once, into d.pred, when at
-// least 1/16 of the particles are active (sets *d.pred_on accordingly).
-hipError_t launch_predict_all(const Dev &d, int mode, hipStream_t s);
+// Build the records of one evaluation into d.pred when its active set is at
+// least 1/16 of its j particles, and set *d.pred_on (0, 1, or 2 when the
+// broadcast kernel may take it: allow_sb and kWG i-slots in every cluster).
+// kind: kPlanStep (predict to T_next), kPlanState (to T), kPlanApi (raw).
+hipError_t launch_records(const Dev &d, int mode, int kind, const RawSrc *raw,
+                          bool allow_sb, hipStream_t s);
+// The broadcast force kernel (j records in scalar registers); it does the
+// evaluation only when *d.pred_on == 2 and returns at once otherwise.
+hipError_t launch_force_sb(const Dev &d, int mode, int K, const RawSrc *raw,
+                           const int32_t *list, int grid, hipStream_t s);
+int force_sb_grid_size(int mode, int K, int device);
 hipError_t launch_correct(const Dev &d, double eta, double dt_shared,
                           int level_min, int level_max, hipStream_t s);
 hipError_t launch_init_levels(const Dev &d, double eta_start,

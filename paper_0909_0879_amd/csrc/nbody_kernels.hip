@@ -354,9 +354,11 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
   const Dev &d = A.d;
   const int tid = threadIdx.x;
   const int n_items = d.item_prefix[d.C];
-  // records predicted once for this step (large active sets) or predicted
+  // records built once for this evaluation (large active sets) or built
   // here while the tile is filled (small active sets, other callers)
-  const bool use_pred = SRC == kSrcState && A.pred_on != nullptr && *A.pred_on != 0;
+  const int pred_flag = (A.pred_on != nullptr) ? *A.pred_on : 0;
+  if (pred_flag == 2) return;       // the broadcast kernel takes this evaluation
+  const bool use_pred = pred_flag == 1;
   const Rec *pred = reinterpret_cast<const Rec *>(d.pred);
   for (;;) {
     if (tid == 0) s_g = atomicAdd(d.work, 1);
@@ -1037,27 +1039,247 @@ __global__ void k_api_finalize(Dev d, int64_t na, double *acc, double *jerk) {
   }
 }
 
-// Predict each particle of the stepping clusters once per block step into
-// the LDS record format, so that every workgroup's tile fill is a plain copy.
-// Only worth it when many particles are active (each j is then read by many
-// i-tiles); small steps keep the prediction fused into the tile fill.
+// Build the j records of one force evaluation once, in the LDS record
+// format, when its active set is large (at least 1/16 of the j particles, so
+// that each j is read by many i-tiles): the tile fill of the workgroup
+// kernel is then a plain copy, and the broadcast kernel reads the records
+// straight into scalar registers.  Small evaluations keep the prediction
+// fused into the tile fill, which reads each j once.  The decision is taken
+// on the device so that captured block steps adapt to their active sets.
+// *pred_on: 0 = records not built, 1 = built, 2 = built and every cluster
+// with work runs kWG i-slots per workgroup (the broadcast kernel takes the
+// evaluation; only with allow_sb).
 template <int MODE>
-__global__ __launch_bounds__(kWG) void k_predict_all(Dev d) {
+__global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, int allow_sb) {
   using Rec = typename Traits<MODE>::Rec;
-  const int64_t total = d.act_off[d.C];
-  const bool on = total * 16 >= d.n;
-  const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (gt == 0) *d.pred_on = on ? 1 : 0;
+  const bool api = kind == kPlanApi;
+  const int64_t nj = (api && raw.n_j > 0) ? raw.n_j : d.n;
+  const int64_t total = api ? raw.n_active : (int64_t)d.act_off[d.C];
+  const bool on = total * 16 >= nj && nj <= d.n;     // the buffer holds d.n records
+  if (blockIdx.x == 0) {
+    int elig = (on && allow_sb) ? 1 : 0;
+    if (elig) {
+      for (int c = threadIdx.x; c < d.C; c += blockDim.x) {
+        const ClusterPlan &p = d.plan_c[c];
+        if (p.na > 0 && p.P != kWG) elig = 0;
+      }
+    }
+    elig = __syncthreads_and(elig);
+    if (threadIdx.x == 0) *d.pred_on = on ? (elig ? 2 : 1) : 0;
+  }
   if (!on) return;
   Rec *pred = reinterpret_cast<Rec *>(d.pred);
-  for (int64_t i = gt; i < d.n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int c = d.cid[i];
-    if (d.Lthr[c] == kNoActive) continue;     // cluster not stepping
-    double xp[3], vp[3];
-    predict_state(d, i, d.Tnext[c], xp, vp);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nj;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double xp[3], vp[3], m;
+    if (api) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        xp[c] = raw.x[3 * i + c];
+        vp[c] = raw.v[3 * i + c];
+      }
+      m = raw.m[i];
+    } else {
+      const int c = d.cid[i];
+      if (kind == kPlanStep && d.Lthr[c] == kNoActive) continue;   // not stepping
+      predict_state(d, i, kind == kPlanStep ? d.Tnext[c] : d.T[c], xp, vp);
+      m = d.m[i];
+    }
     Rec r;
-    make_rec(xp, vp, d.m[i], (int32_t)i, r);
+    make_rec(xp, vp, m, (int32_t)i, r);
     pred[i] = r;
+  }
+}
+
+// ------------------------------------------------------------ broadcast kernel
+//
+// Every lane of a wave meets the same j record at the same time, so the
+// record belongs in scalar registers: it is read through the scalar cache
+// (one load per wave instead of an LDS broadcast to 64 lanes) and feeds the
+// vector ALU as an operand.  No LDS tile, no barrier in the j loop, and the
+// vector registers hold only i-state and sums.  Each lane owns K i-particles
+// (kWG i-slots per workgroup); the sums are the same operations in the same
+// order as the workgroup kernel with one j-lane per slot, so both give
+// bitwise-identical rows.
+
+template <typename T>
+using ScalarPtr = const __attribute__((address_space(4))) T *;
+
+// member-wise copies (the implicit copy constructor takes a generic pointer)
+__device__ __forceinline__ JRecDS load_rec(ScalarPtr<JRecDS> p) {
+  JRecDS r;
+  r.xh = p->xh; r.yh = p->yh; r.zh = p->zh; r.m = p->m;
+  r.xl = p->xl; r.yl = p->yl; r.zl = p->zl; r.pad = 0.0f;
+  r.vx = p->vx; r.vy = p->vy; r.vz = p->vz; r.idx = p->idx;
+  return r;
+}
+
+__device__ __forceinline__ JRec64 load_rec(ScalarPtr<JRec64> p) {
+  JRec64 r;
+  r.x = p->x; r.y = p->y; r.z = p->z; r.m = p->m;
+  r.vx = p->vx; r.vy = p->vy; r.vz = p->vz;
+  r.mf = 0.0f; r.idx = p->idx;
+  return r;
+}
+
+// Four records per group, read with as few scalar loads as possible (a
+// 64-byte load is one request to the scalar cache).
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ JRecDS rec_at(const f32x16 &a, int o) {
+  JRecDS r;
+  r.xh = a[o]; r.yh = a[o + 1]; r.zh = a[o + 2]; r.m = a[o + 3];
+  r.xl = a[o + 4]; r.yl = a[o + 5]; r.zl = a[o + 6]; r.pad = 0.0f;
+  r.vx = a[o + 8]; r.vy = a[o + 9]; r.vz = a[o + 10];
+  r.idx = __float_as_int(a[o + 11]);
+  return r;
+}
+
+// 4 x 48 bytes = three 64-byte blocks
+__device__ __forceinline__ void load4(ScalarPtr<JRecDS> p, JRecDS (&r)[4]) {
+  const ScalarPtr<f32x16> b = (ScalarPtr<f32x16>)p;
+  const f32x16 b0 = b[0], b1 = b[1], b2 = b[2];
+  r[0] = rec_at(b0, 0);
+  r[1].xh = b0[12]; r[1].yh = b0[13]; r[1].zh = b0[14]; r[1].m = b0[15];
+  r[1].xl = b1[0]; r[1].yl = b1[1]; r[1].zl = b1[2]; r[1].pad = 0.0f;
+  r[1].vx = b1[4]; r[1].vy = b1[5]; r[1].vz = b1[6];
+  r[1].idx = __float_as_int(b1[7]);
+  r[2].xh = b1[8]; r[2].yh = b1[9]; r[2].zh = b1[10]; r[2].m = b1[11];
+  r[2].xl = b1[12]; r[2].yl = b1[13]; r[2].zl = b1[14]; r[2].pad = 0.0f;
+  r[2].vx = b2[0]; r[2].vy = b2[1]; r[2].vz = b2[2];
+  r[2].idx = __float_as_int(b2[3]);
+  r[3] = rec_at(b2, 4);
+}
+
+__device__ __forceinline__ void load4(ScalarPtr<JRec64> p, JRec64 (&r)[4]) {
+  const ScalarPtr<f32x16> b = (ScalarPtr<f32x16>)p;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const f32x16 a = b[u];
+    r[u].x = __builtin_bit_cast(double, __builtin_shufflevector(a, a, 0, 1));
+    r[u].y = __builtin_bit_cast(double, __builtin_shufflevector(a, a, 2, 3));
+    r[u].z = __builtin_bit_cast(double, __builtin_shufflevector(a, a, 4, 5));
+    r[u].m = __builtin_bit_cast(double, __builtin_shufflevector(a, a, 6, 7));
+    r[u].vx = __builtin_bit_cast(double, __builtin_shufflevector(a, a, 8, 9));
+    r[u].vy = __builtin_bit_cast(double, __builtin_shufflevector(a, a, 10, 11));
+    r[u].vz = __builtin_bit_cast(double, __builtin_shufflevector(a, a, 12, 13));
+    r[u].mf = 0.0f;
+    r[u].idx = __float_as_int(a[15]);
+  }
+}
+
+template <int MODE, int K, bool MASK, bool SELF>
+__device__ __forceinline__ void sb_run(
+    ScalarPtr<typename Traits<MODE>::Rec> rec, int cnt,
+    const typename Traits<MODE>::Ist (&I)[K], const int (&iidx)[K], double eps2,
+    typename Traits<MODE>::T (&t)[K][Traits<MODE>::NC], int (&dom)[K], float (&tmx)[K]) {
+  using Rec = typename Traits<MODE>::Rec;
+  int jj = 0;
+  for (; jj + 4 <= cnt; jj += 4) {
+    Rec r[4];
+    load4(rec + jj, r);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) pair_k<MODE, K, MASK, SELF>(r[u], I, iidx, eps2, t, dom, tmx);
+  }
+  for (; jj < cnt; ++jj) {
+    const Rec r = load_rec(rec + jj);
+    pair_k<MODE, K, MASK, SELF>(r, I, iidx, eps2, t, dom, tmx);
+  }
+}
+
+template <int MODE, int K>
+__global__ __launch_bounds__(kWG) void k_force_sb(ForceArgs A) {
+  using Tr = Traits<MODE>;
+  using T = typename Tr::T;
+  using Rec = typename Tr::Rec;
+  constexpr int NC = Tr::NC;
+  constexpr int F = Tr::FOLD;
+  __shared__ int s_g;
+  const Dev &d = A.d;
+  if (*A.pred_on != 2) return;      // the workgroup kernel takes this evaluation
+  const int tid = threadIdx.x;
+  const int n_items = d.item_prefix[d.C];
+  const Rec *pred = reinterpret_cast<const Rec *>(d.pred);
+  const ScalarPtr<Rec> spred = (ScalarPtr<Rec>)d.pred;
+  const bool raw = A.rx != nullptr;
+  for (;;) {
+    if (tid == 0) s_g = atomicAdd(d.work, 1);
+    __syncthreads();
+    const int g = __builtin_amdgcn_readfirstlane(s_g);
+    __syncthreads();
+    if (g >= n_items) break;
+    int lo = 0, hi = d.C;   // item_prefix[lo] <= g < item_prefix[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (d.item_prefix[mid] <= g) lo = mid; else hi = mid;
+    }
+    const ClusterPlan cp = d.plan_lpt[lo];
+    const int t_item = g - d.item_prefix[lo];
+    const int tile_i = t_item / cp.S;
+    const int split = t_item - tile_i * cp.S;
+    const int64_t js = cp.jb + (int64_t)split * cp.chunk;
+    const int64_t je = (js + cp.chunk < cp.je) ? js + cp.chunk : cp.je;
+    const double eps2 = d.eps2[cp.c];
+
+    typename Tr::Ist I[K];
+    int iidx[K], dom[K];
+    bool ok[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int slot = tile_i * kWG * K + k * kWG + tid;
+      ok[k] = slot < cp.na;
+      iidx[k] = ok[k] ? A.active[cp.act_off + slot] : -1;
+      dom[k] = 0;
+      if (raw && ok[k] && (iidx[k] < cp.jb || iidx[k] >= cp.je)) {
+        ok[k] = false;
+        if (split == 0) atomicOr(d.err, (int)kErrIndex);
+      }
+      if (ok[k]) {
+        rec_to_i(pred[iidx[k]], I[k]);
+      } else {
+        iidx[k] = -1;
+        const double z[3] = {0.0, 0.0, 0.0};
+        make_i(z, z, I[k]);
+      }
+    }
+    T t[K][NC], shi[K][NC], slo[K][NC];
+    float tmx[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      tmx[k] = 0.0f;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) t[k][c] = shi[k][c] = slo[k][c] = (T)0;
+    }
+
+    const bool mask = (eps2 == 0.0);
+    for (int64_t jb = js; jb < je; jb += F) {
+      const int cnt = (int)((je - jb < F) ? je - jb : F);
+      int mine = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) mine |= (iidx[k] >= jb && iidx[k] < jb + cnt);
+      const bool self = __any(mine);
+      const ScalarPtr<Rec> rb = spred + jb;
+      if (mask)
+        sb_run<MODE, K, true, false>(rb, cnt, I, iidx, eps2, t, dom, tmx);
+      else if (MODE == kModeMixed && self)
+        sb_run<MODE, K, false, true>(rb, cnt, I, iidx, eps2, t, dom, tmx);
+      else
+        sb_run<MODE, K, false, false>(rb, cnt, I, iidx, eps2, t, dom, tmx);
+      fold<MODE, K>(t, shi, slo);
+    }
+
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (ok[k] && dom[k]) atomicOr(d.err, (int)kErrDomain);
+      const int slot = tile_i * kWG * K + k * kWG + tid;
+      if (slot < cp.na) {
+        double *row = d.partial + (cp.row_off + (int64_t)split * cp.na + slot) * kRowStride;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          row[c] = ok[k] ? (double)shi[k][c] + (double)slo[k][c] : 0.0;
+        row[6] = ok[k] ? (double)tmx[k] : 0.0;
+      }
+    }
   }
 }
 
@@ -1503,13 +1725,50 @@ int force_grid_size(int mode, int src, int K, int device) {
   return 0;
 }
 
-hipError_t launch_predict_all(const Dev &d, int mode, hipStream_t s) {
-  const dim3 g(grid_for(d.n, kWG, 4096)), b(kWG);
+hipError_t launch_records(const Dev &d, int mode, int kind, const RawSrc *raw,
+                          bool allow_sb, hipStream_t s) {
+  RawSrc r{};
+  if (raw) r = *raw;
+  const int64_t nj = (kind == kPlanApi && r.n_j > 0) ? r.n_j : d.n;
+  const dim3 g(grid_for(nj, kWG, 4096)), b(kWG);
   if (mode == kModeMixed)
-    hipLaunchKernelGGL(k_predict_all<kModeMixed>, g, b, 0, s, d);
+    hipLaunchKernelGGL(k_records<kModeMixed>, g, b, 0, s, d, kind, r, allow_sb ? 1 : 0);
   else
-    hipLaunchKernelGGL(k_predict_all<kModeFP64>, g, b, 0, s, d);
+    hipLaunchKernelGGL(k_records<kModeFP64>, g, b, 0, s, d, kind, r, allow_sb ? 1 : 0);
   return hipGetLastError();
+}
+
+hipError_t launch_force_sb(const Dev &d, int mode, int K, const RawSrc *raw,
+                           const int32_t *list, int grid, hipStream_t s) {
+  ForceArgs A;
+  A.d = d;
+  A.active = list;
+  A.rx = raw ? raw->x : nullptr;
+  A.rv = raw ? raw->v : nullptr;
+  A.rm = raw ? raw->m : nullptr;
+  A.pred_on = d.pred_on;
+  const dim3 g(grid), b(kWG);
+  if (mode == kModeMixed && K == 1) hipLaunchKernelGGL((k_force_sb<kModeMixed, 1>), g, b, 0, s, A);
+  else if (mode == kModeMixed && K == 2) hipLaunchKernelGGL((k_force_sb<kModeMixed, 2>), g, b, 0, s, A);
+  else if (mode == kModeFP64 && K == 1) hipLaunchKernelGGL((k_force_sb<kModeFP64, 1>), g, b, 0, s, A);
+  else if (mode == kModeFP64 && K == 2) hipLaunchKernelGGL((k_force_sb<kModeFP64, 2>), g, b, 0, s, A);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+int force_sb_grid_size(int mode, int K, int device) {
+  const void *f = nullptr;
+  if (mode == kModeMixed && K == 1) f = (const void *)k_force_sb<kModeMixed, 1>;
+  else if (mode == kModeMixed && K == 2) f = (const void *)k_force_sb<kModeMixed, 2>;
+  else if (mode == kModeFP64 && K == 1) f = (const void *)k_force_sb<kModeFP64, 1>;
+  else if (mode == kModeFP64 && K == 2) f = (const void *)k_force_sb<kModeFP64, 2>;
+  if (!f) return 0;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kWG, 0) != hipSuccess) per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    cus = 256;
+  if (per_cu < 1) per_cu = 1;
+  return per_cu * cus;
 }
 
 hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_host,

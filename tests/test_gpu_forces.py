@@ -152,7 +152,8 @@ def test_split_and_tile_shape_invariance(prec, tol, jtol):
     g = _ctx(m, x, v, 1e-3, prec)
     idx = np.arange(0, 6000, 3, dtype=np.int32)[:150]
     base_a, base_j = (to_np(t) for t in g.forces(x, v, m, i_active=idx))
-    for variant in (binding.VARIANT_K1, binding.VARIANT_K2):
+    for variant in (binding.VARIANT_K1, binding.VARIANT_K2, binding.VARIANT_S1,
+                    binding.VARIANT_S2):
         for slots, target in ((1, 1), (4, 64), (64, 4096), (256, 1)):
             g.set_tuning({"variant": variant, "i_slots": [slots] * 25,
                           "target_items": [target] * 25, "min_split_j": 64})
