@@ -61,6 +61,9 @@ def lib():
         L.oracle_init.argtypes = [C.c_int64, P, P, P, P, P, P, P, P, P]
         L.oracle_run.argtypes = [C.c_int64, P, P, P, P, P, P, P, P, C.c_int64, C.c_int64, P]
         L.oracle_threads.argtypes = []
+        L.oracle_symplectic_weights.argtypes = [C.c_int, P]
+        L.oracle_symplectic.argtypes = [C.c_int64, P, P, P, C.c_double, C.c_double, C.c_int64,
+                                        C.c_int]
         _lib = L
     return _lib
 
@@ -93,6 +96,31 @@ def forces(x, v, m, eps, idx=None, want_pot=False):
     if rc:
         raise OracleError(rc, "forces")
     return (acc, jerk, pot) if want_pot else (acc, jerk)
+
+
+LEAPFROG, SYMPLECTIC6 = 0, 1
+
+
+def symplectic_weights(scheme):
+    """Stage weights of the leapfrog (0) or the sixth-order scheme (1)."""
+    w = np.empty(7)
+    k = lib().oracle_symplectic_weights(int(scheme), _p(w))
+    if k == 0:
+        raise OracleError(EINVAL, "symplectic_weights")
+    return w[:k].copy()
+
+
+def symplectic(x, v, m, eps, h, n_steps, scheme):
+    """n_steps steps of size h of a symplectic driver; returns new (x, v)."""
+    m = _f64(m)
+    n = m.shape[0]
+    x = _f64(x, (n, 3)).copy()
+    v = _f64(v, (n, 3)).copy()
+    rc = lib().oracle_symplectic(n, _p(m), _p(x), _p(v), float(eps), float(h), int(n_steps),
+                                 int(scheme))
+    if rc:
+        raise OracleError(rc, "symplectic")
+    return x, v
 
 
 def energy(x, v, m, eps):

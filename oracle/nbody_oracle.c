@@ -16,7 +16,9 @@
  * the Plummer form phi = -m / sqrt(r^2 + eps^2).  The jerk is the time
  * derivative of a_i along the current velocities (not in the paper).
  *
- * Time integration: fourth-order Hermite predictor-corrector (Makino &
+ * Time integration: the paper's symplectic drivers (leapfrog and a
+ * sixth-order composition of leapfrog stages, Sect. 4) for shared steps,
+ * and a fourth-order Hermite predictor-corrector (Makino &
  * Aarseth 1992 form) with individual, power-of-two block time steps chosen
  * by Aarseth's criterion.  The paper motivates individual per-particle steps
  * and the care they need for synchronisation (Sect. 3); the integrator
@@ -419,6 +421,85 @@ done:
   free(a1);
   free(j1);
   free(act);
+  return err;
+}
+
+/* ------------------------------------------------------ symplectic drivers */
+
+/* Stage weights of the paper's two symplectic schemes (Sect. 4, time
+ * integration).  Leapfrog: one stage of weight 1.  Sixth order: the paper
+ * takes the first column of Kinoshita, Yoshida & Nakai (1991), Table 1,
+ * which is not reproduced in the paper; it is read here as Yoshida's (1990)
+ * solution A of the order conditions for a symmetric product of seven
+ * second-order leapfrog stages, weights w3 w2 w1 w0 w1 w2 w3 with
+ * w0 = 1 - 2 (w1 + w2 + w3).  Returns the number of stages.  Pins: the
+ * weights sum to 1, their cubes and fifth powers sum to 0 (the third- and
+ * fifth-order error terms of the symmetric product vanish), and the Kepler
+ * error falls as h^6. */
+int oracle_symplectic_weights(int scheme, double *w) {
+  if (scheme == 0) {
+    w[0] = 1.0;
+    return 1;
+  }
+  if (scheme != 1) return 0;
+  const double w1 = -1.17767998417887;
+  const double w2 = 0.235573213359357;
+  const double w3 = 0.784513610477560;
+  const double w0 = 1.0 - 2.0 * (w1 + w2 + w3);
+  const double ws[7] = {w3, w2, w1, w0, w1, w2, w3};
+  for (int k = 0; k < 7; ++k) w[k] = ws[k];
+  return 7;
+}
+
+/* Accelerations of all n particles at positions x (acc-only use of the
+ * pair sum above; velocities do not enter the acceleration). */
+static int accel_all(int64_t n, const double *x, const double *m, double eps,
+                     double *acc, double *tmp_v, double *tmp_j) {
+  int err = OR_OK;
+  (void)tmp_v;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; ++i) {
+    double p;
+    const double zero[3] = {0.0, 0.0, 0.0};
+    int e = force_one(i, &x[3 * i], zero, n, x, tmp_v, m, eps, &acc[3 * i],
+                      &tmp_j[3 * i], &p);
+    if (e) {
+#pragma omp atomic write
+      err = e;
+    }
+  }
+  return err;
+}
+
+/* n_steps steps of size h of the leapfrog (scheme 0) or the sixth-order
+ * composition (scheme 1) for one isolated system; x, v ((n, 3)) are updated
+ * in place.  Each stage of weight w is the kick-drift-kick leapfrog of step
+ * w h: v += (w h / 2) a(x); x += w h v; v += (w h / 2) a(x).  The
+ * acceleration at the current positions is kept between stages, so a stage
+ * costs one evaluation.  Pins: Kepler period and convergence order, time
+ * reversibility, bounded energy error. */
+int oracle_symplectic(int64_t n, const double *m, double *x, double *v,
+                      double eps, double h, int64_t n_steps, int scheme) {
+  double w[7];
+  const int ns = oracle_symplectic_weights(scheme, w);
+  if (ns == 0 || n < 1 || n_steps < 0 || !(h > 0.0)) return OR_EINVAL;
+  double *a = (double *)calloc((size_t)(3 * n), sizeof(double));
+  double *zv = (double *)calloc((size_t)(3 * n), sizeof(double));
+  double *jk = (double *)calloc((size_t)(3 * n), sizeof(double));
+  int err = (a && zv && jk) ? OR_OK : OR_EINVAL;
+  if (!err) err = accel_all(n, x, m, eps, a, zv, jk);
+  for (int64_t st = 0; st < n_steps && !err; ++st) {
+    for (int k = 0; k < ns && !err; ++k) {
+      const double c = w[k] * h;
+      for (int64_t q = 0; q < 3 * n; ++q) v[q] += 0.5 * c * a[q];
+      for (int64_t q = 0; q < 3 * n; ++q) x[q] += c * v[q];
+      err = accel_all(n, x, m, eps, a, zv, jk);
+      for (int64_t q = 0; q < 3 * n; ++q) v[q] += 0.5 * c * a[q];
+    }
+  }
+  free(a);
+  free(zv);
+  free(jk);
   return err;
 }
 
