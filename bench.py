@@ -43,10 +43,12 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="headline",
-                    choices=("headline", "sweep", "ensemble", "blocksteps"),
+                    choices=("headline", "sweep", "ensemble", "blocksteps", "symplectic"),
                     help="headline: the contract line (default); sweep: n_active sweep of "
                          "the King 2^20 evaluation; ensemble: 256-cluster block steps; "
-                         "blocksteps: Plummer 65536 FP64 and Salpeter 262144 mixed runs")
+                         "blocksteps: Plummer 65536 FP64 and Salpeter 262144 mixed runs; "
+                         "symplectic: time per leapfrog / sixth-order step vs N on the "
+                         "paper's uniform-sphere initial conditions")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (to scale the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -202,6 +204,51 @@ def run_blocksteps(binding, torch, label, m, x, v, t_end, precision, cluster_off
     print(json.dumps(out), flush=True)
 
 
+def symplectic_scaling(binding, torch, ics, with_cpu):
+    """Time per integration step of the paper's symplectic drivers against N
+    (uniform sphere, Q = 1, eps = 1e-3, h = 2^-10): the difference of two
+    runs of k1 < k2 steps cancels each call's fixed work (the extra first
+    evaluation and the closing Hermite re-evaluation).  One JSON line per
+    (N, precision, scheme); with_cpu adds the oracle's time per leapfrog
+    step (measured up to N = 65536 and scaled by N^2 above)."""
+    import numpy as np
+    h = 2.0 ** -10
+    for n in (1024, 4096, 16384, 65536, 262144, 1048576):
+        m, x, v = ics.uniform_sphere_virial(n, 7)
+        for prec in (binding.MIXED, binding.FP64):
+            g = binding.NBody(m, x, v, eps=1e-3, precision=prec, level_min=10, level_max=10,
+                              tuning="auto")
+            for scheme, name, stages in ((binding.LEAPFROG, "leapfrog", 1),
+                                         (binding.SYMPLECTIC6, "sixth-order", 7)):
+                k = max(1, min(400, int(4e11 / (stages * n * n))))
+                times = []
+                for steps in (1, 1 + k):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    g.step_symplectic(scheme, h, steps)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t0)
+                ms = 1e3 * (times[1] - times[0]) / k
+                print(json.dumps({"workload": "symplectic", "scheme": name, "n": n,
+                                  "precision": "mixed" if prec else "fp64",
+                                  "ms_per_step": ms, "steps_timed": k,
+                                  "interactions_per_s": stages * n * n / (ms * 1e-3)}),
+                      flush=True)
+            g.close()
+        if with_cpu:
+            # the oracle's own leapfrog: one step costs two evaluations here
+            # (the call starts with one); above 65536 scaled by N^2
+            import oracle
+            nn = min(n, 65536)
+            t0 = time.perf_counter()
+            oracle.symplectic(x[:nn], v[:nn], m[:nn] * (n / nn), 1e-3, h, 1, oracle.LEAPFROG)
+            dt = (time.perf_counter() - t0) / 2 * (n / nn) ** 2
+            print(json.dumps({"workload": "symplectic", "scheme": "leapfrog", "n": n,
+                              "precision": "oracle-fp64", "ms_per_step": 1e3 * dt,
+                              "cores": oracle.threads(), "scaled_from_n": nn,
+                              "interactions_per_s": n * n / dt}), flush=True)
+
+
 def main():
     a = parse()
     if a.calibrate_copy:
@@ -223,6 +270,9 @@ def main():
         m, x, v, off = ics.ensemble(256, 256, 16384, seed=5000)
         run_blocksteps(binding, torch, "ensemble", m, x, v, 0.25, binding.MIXED,
                        cluster_offsets=off, eps=1e-3, level_min=5, chunks=8)
+        return
+    if a.workload == "symplectic":
+        symplectic_scaling(binding, torch, ics, not a.no_cpu)
         return
     if a.workload == "blocksteps":
         m, x, v = ics.plummer(65536, 2)

@@ -118,6 +118,37 @@ int nbody_forces(nbody_ctx *c, const int32_t *i_active, int64_t n_active,
                  const double *xj, const double *vj, const double *mj,
                  int64_t n_j, double *acc, double *jerk);
 
+/* Acceleration only (eq. (1) with Plummer softening; the force function of
+ * the paper's symplectic drivers): acc[k] ((n_active, 3), device) receives
+ * the sum over xj ((n_j, 3)) and mj (n_j) of the pair accelerations on
+ * i = i_active[k], skipping j == i.  Same rules as nbody_forces for n_j,
+ * clusters, grouping, repeats, errors and asynchrony; no velocities are
+ * read.  The mixed path's FP64 re-evaluation applies as in nbody_forces. */
+int nbody_accel(nbody_ctx *c, const int32_t *i_active, int64_t n_active,
+                const double *xj, const double *mj, int64_t n_j, double *acc);
+
+/* The paper's symplectic drivers (Sect. 4, time integration):
+ * NBODY_LEAPFROG, the second-order kick-drift-kick leapfrog (one force
+ * evaluation per step), and NBODY_SYMPLECTIC6, the sixth-order explicit
+ * scheme built as the symmetric composition of seven leapfrog stages with
+ * Yoshida's solution A weights (seven evaluations per step). */
+enum { NBODY_LEAPFROG = 0, NBODY_SYMPLECTIC6 = 1 };
+
+/* Advance every particle by n_steps steps of the constant size h with a
+ * symplectic driver, using acceleration-only evaluations in the context's
+ * precision (consecutive half kicks merge, so a step costs one evaluation
+ * per stage, plus one at the start of the call since the state's
+ * accelerations were taken at predicted positions).  Every particle must
+ * sit at its cluster's time (true after nbody_init and nbody_step;
+ * otherwise NBODY_EINVAL at the end of the call).  h must be a positive
+ * multiple of 2^-20 and n_steps * h a multiple of 2^-level_min, so that
+ * block steps can follow.  On return every time has advanced by
+ * n_steps * h and acceleration, jerk and levels are re-evaluated at the new
+ * positions, as nbody_init does.  n_interactions (if non-NULL) receives
+ * the pair slots of the acceleration evaluations.  Syncs. */
+int nbody_step_symplectic(nbody_ctx *c, int scheme, double h, int64_t n_steps,
+                          int64_t *n_interactions);
+
 /* Advance every cluster with Hermite-4 block steps to the absolute time
  * t_end, which must be a multiple of 2^-level_min and not earlier than the
  * current time.  Each block step: per cluster, the next time

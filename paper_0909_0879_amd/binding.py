@@ -19,6 +19,7 @@ OK, EINVAL, ENODEV, ENOMEM, EHIP, EINDEX, ENONFINITE, EDOMAIN = 0, -1, -2, -3, -
 FP64, MIXED = 0, 1
 VARIANT_DEFAULT, VARIANT_K1, VARIANT_K2, VARIANT_S1, VARIANT_S2 = 0, 1, 2, 3, 4
 GRAPH_ON, GRAPH_OFF = 1, 2
+LEAPFROG, SYMPLECTIC6 = 0, 1
 TUNE_BUCKETS = 25
 TICK_BITS = 20
 
@@ -26,7 +27,7 @@ EXPORTED = [
     "nbody_workspace_bytes", "nbody_init", "nbody_forces", "nbody_step", "nbody_energy",
     "nbody_get_state", "nbody_set_state", "nbody_sync", "nbody_stats", "nbody_destroy",
     "nbody_strerror", "nbody_last_error", "nbody_get_tuning", "nbody_set_tuning",
-    "nbody_profile", "nbody_profile_read",
+    "nbody_profile", "nbody_profile_read", "nbody_accel", "nbody_step_symplectic",
 ]
 
 
@@ -106,6 +107,8 @@ def lib():
         L.nbody_set_tuning.argtypes = [P, P]
         L.nbody_profile.argtypes = [P, C.c_int]
         L.nbody_profile_read.argtypes = [P, P, P, P, P]
+        L.nbody_accel.argtypes = [P, P, C.c_int64, P, P, C.c_int64, P]
+        L.nbody_step_symplectic.argtypes = [P, C.c_int, C.c_double, C.c_int64, P]
         _lib = L
     return _lib
 
@@ -209,6 +212,30 @@ class NBody:
         check(lib().nbody_forces(self.ctx, _ptr(ia), na, _ptr(xj), _ptr(vj), _ptr(mj), nj,
                                  _ptr(acc), _ptr(jerk)), "nbody_forces")
         return acc, jerk
+
+    def accel(self, xj, mj, i_active=None):
+        """Acceleration only on i_active from (xj, mj); device tensors."""
+        torch = self._torch
+        dev = self.workspace.device
+        xj = torch.as_tensor(xj, dtype=torch.float64, device=dev).contiguous()
+        mj = torch.as_tensor(mj, dtype=torch.float64, device=dev).contiguous()
+        nj = mj.shape[0]
+        if i_active is None:
+            i_active = torch.arange(nj, dtype=torch.int32, device=dev)
+        ia = torch.as_tensor(i_active, dtype=torch.int32, device=dev).contiguous()
+        na = ia.shape[0]
+        acc = torch.empty((na, 3), dtype=torch.float64, device=dev)
+        check(lib().nbody_accel(self.ctx, _ptr(ia), na, _ptr(xj), _ptr(mj), nj, _ptr(acc)),
+              "nbody_accel")
+        return acc
+
+    def step_symplectic(self, scheme, h, n_steps):
+        """n_steps steps of size h with LEAPFROG or SYMPLECTIC6; returns the
+        pair slots evaluated."""
+        ni = C.c_int64(0)
+        check(lib().nbody_step_symplectic(self.ctx, int(scheme), float(h), int(n_steps),
+                                          C.byref(ni)), "nbody_step_symplectic")
+        return ni.value
 
     def step(self, t_end):
         ns, ni = C.c_int64(0), C.c_int64(0)

@@ -195,6 +195,9 @@ struct nbody_ctx {
   bool sb = false;                // broadcast kernel for large evaluations
   int grid_state = 0, grid_raw = 0, grid_pot = 0, grid_sb = 0;
   int grid_ref_state = 0, grid_ref_raw = 0;   // FP64 K = 1 re-evaluation
+  // acceleration-only kernels (symplectic drivers, nbody_accel)
+  int grid_acc_state = 0, grid_acc_raw = 0, grid_acc_sb = 0;
+  int grid_ref_acc_state = 0, grid_ref_acc_raw = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_steps = 0;
@@ -225,6 +228,10 @@ int mode_of(const nbody_ctx *c) {
   return c->prec == NBODY_MIXED ? nbk::kModeMixed : nbk::kModeFP64;
 }
 
+int acc_mode_of(const nbody_ctx *c) {
+  return c->prec == NBODY_MIXED ? nbk::kModeMixedAcc : nbk::kModeFP64Acc;
+}
+
 void drop_graph(nbody_ctx *c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -238,13 +245,19 @@ int refresh_grids(nbody_ctx *c) {
   c->K = (v == NBODY_VARIANT_K2 || v == NBODY_VARIANT_S2) ? 2 : 1;
   c->sb = (v == NBODY_VARIANT_S1 || v == NBODY_VARIANT_S2);
   c->grid_sb = c->sb ? nbk::force_sb_grid_size(mode_of(c), c->K, c->device) : 1;
+  c->grid_acc_sb = c->sb ? nbk::force_sb_grid_size(acc_mode_of(c), c->K, c->device) : 1;
+  c->grid_acc_state = nbk::force_grid_size(acc_mode_of(c), nbk::kSrcState, c->K, c->device);
+  c->grid_acc_raw = nbk::force_grid_size(acc_mode_of(c), nbk::kSrcRaw, c->K, c->device);
+  c->grid_ref_acc_state = nbk::force_grid_size(nbk::kModeFP64Acc, nbk::kSrcState, 1, c->device);
+  c->grid_ref_acc_raw = nbk::force_grid_size(nbk::kModeFP64Acc, nbk::kSrcRaw, 1, c->device);
   c->grid_state = nbk::force_grid_size(mode_of(c), nbk::kSrcState, c->K, c->device);
   c->grid_raw = nbk::force_grid_size(mode_of(c), nbk::kSrcRaw, c->K, c->device);
   c->grid_pot = nbk::force_grid_size(nbk::kModePot, nbk::kSrcState, 1, c->device);
   c->grid_ref_state = nbk::force_grid_size(nbk::kModeFP64, nbk::kSrcState, 1, c->device);
   c->grid_ref_raw = nbk::force_grid_size(nbk::kModeFP64, nbk::kSrcRaw, 1, c->device);
   if (c->grid_state < 1 || c->grid_raw < 1 || c->grid_pot < 1 || c->grid_ref_state < 1 ||
-      c->grid_ref_raw < 1 || c->grid_sb < 1)
+      c->grid_ref_raw < 1 || c->grid_sb < 1 || c->grid_acc_sb < 1 || c->grid_acc_state < 1 ||
+      c->grid_acc_raw < 1 || c->grid_ref_acc_state < 1 || c->grid_ref_acc_raw < 1)
     return fail(NBODY_EHIP, "could not size the force kernel grid");
   return NBODY_OK;
 }
@@ -265,11 +278,16 @@ int force_launch(nbody_ctx *c, int mode, int src, int K, const nbk::RawSrc *raw,
   }
   if (prof) NB_HIP(hipEventRecord(c->ev[2 * c->ev_used], s));
   NB_HIP(nbk::launch_force(c->d, mode, src, K, raw, list, use_pred, grid, s));
-  if (use_pred && c->sb) NB_HIP(nbk::launch_force_sb(c->d, mode, K, raw, list, c->grid_sb, s));
+  if (use_pred && c->sb)
+    NB_HIP(nbk::launch_force_sb(c->d, mode, K, raw, list,
+                                nbk::mode_acc_only(mode) ? c->grid_acc_sb : c->grid_sb, s));
   if (prof) {
     NB_HIP(hipEventRecord(c->ev[2 * c->ev_used + 1], s));
-    // the potential kernel (energy diagnostics) is not counted
-    c->ev_tag[c->ev_used] = (mode == nbk::kModePot) ? -1 : (mode == mode_of(c) ? 0 : 1);
+    // the potential kernel (energy diagnostics) is not counted; FP64 launches
+    // of a mixed context are its re-evaluations
+    const bool fp64 = mode == nbk::kModeFP64 || mode == nbk::kModeFP64Acc;
+    c->ev_tag[c->ev_used] =
+        (mode == nbk::kModePot) ? -1 : ((fp64 && c->prec == NBODY_MIXED) ? 1 : 0);
     ++c->ev_used;
   }
   return NBODY_OK;
@@ -298,7 +316,7 @@ float refine_ratio(const nbody_ctx *c) {
 // Sum the partial rows into fsum and, on the mixed path, re-evaluate the
 // flagged entries with the FP64 kernel (a second plan over the flagged list).
 int sum_and_refine(nbody_ctx *c, const int32_t *list, int64_t na_host, const nbk::RawSrc *raw,
-                   hipStream_t s) {
+                   hipStream_t s, bool acc_only = false) {
   const float ratio = refine_ratio(c);
   NB_HIP(nbk::launch_sum_and_flag(c->d, list, na_host, ratio, s));
   if (ratio <= 0.0f) return NBODY_OK;
@@ -306,8 +324,10 @@ int sum_and_refine(nbody_ctx *c, const int32_t *list, int64_t na_host, const nbk
   const bool api = raw != nullptr;
   NB_HIP(nbk::launch_plan(c->d, t1, api ? nbk::kPlanApiRefine : nbk::kPlanRefine,
                           api ? raw->n_j : 0, s));
-  int rc = force_launch(c, nbk::kModeFP64, api ? nbk::kSrcRaw : nbk::kSrcState, 1, raw,
-                        c->d.ref_i, api ? c->grid_ref_raw : c->grid_ref_state, s);
+  const int grid = acc_only ? (api ? c->grid_ref_acc_raw : c->grid_ref_acc_state)
+                            : (api ? c->grid_ref_raw : c->grid_ref_state);
+  int rc = force_launch(c, acc_only ? nbk::kModeFP64Acc : nbk::kModeFP64,
+                        api ? nbk::kSrcRaw : nbk::kSrcState, 1, raw, c->d.ref_i, grid, s);
   if (rc) return rc;
   NB_HIP(nbk::launch_refine_finalize(c->d, s));
   return NBODY_OK;
@@ -379,6 +399,43 @@ int full_evaluation_into_state(nbody_ctx *c) {
   if ((rc = sum_and_refine(c, c->d.active, -1, nullptr, c->stream))) return rc;
   NB_HIP(nbk::launch_init_levels(c->d, c->eta_start, c->dt_shared, c->lmin, c->lmax,
                                  c->stream));
+  return NBODY_OK;
+}
+
+// nbody_forces / nbody_accel: the caller's j arrays, chunks of at most
+// cap_active i entries.
+int api_forces(nbody_ctx *c, bool acc_only, const int32_t *i_active, int64_t n_active,
+               const double *xj, const double *vj, const double *mj, int64_t n_j, double *acc,
+               double *jerk) {
+  if (!c) return fail(NBODY_EINVAL, "context is NULL");
+  if (n_active < 0) return fail(NBODY_EINVAL, "n_active < 0");
+  if (n_active == 0) return NBODY_OK;
+  if (!i_active || !xj || !mj || !acc) return fail(NBODY_EINVAL, "NULL array argument");
+  if (n_j < 1 || n_j > kMaxN) return fail(NBODY_EINVAL, "n_j must be in [1, 2^30]");
+  if (c->C > 1 && n_j != c->n)
+    return fail(NBODY_EINVAL, "with several clusters n_j must equal the context's n");
+  const int mode = acc_only ? acc_mode_of(c) : mode_of(c);
+  const int grid = acc_only ? c->grid_acc_raw : c->grid_raw;
+  const nbk::Tuning t = device_tuning(c, c->K);
+  const int64_t cap = c->d.cap_active;
+  for (int64_t k0 = 0; k0 < n_active; k0 += cap) {
+    nbk::RawSrc r;
+    r.x = xj;
+    r.v = vj;
+    r.m = mj;
+    r.n_j = (c->C == 1) ? n_j : 0;
+    r.i_active = i_active + k0;
+    r.n_active = (n_active - k0 < cap) ? n_active - k0 : cap;
+    r.acc = acc + 3 * k0;
+    r.jerk = jerk ? jerk + 3 * k0 : nullptr;
+    NB_HIP(nbk::launch_api_group(c->d, r, c->stream));
+    NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanApi, r.n_j, c->stream));
+    int rc = force_launch(c, mode, nbk::kSrcRaw, c->K, &r, r.i_active, grid, c->stream,
+                          nbk::kPlanApi);
+    if (rc) return rc;
+    if ((rc = sum_and_refine(c, r.i_active, r.n_active, &r, c->stream, acc_only))) return rc;
+    NB_HIP(nbk::launch_api_finalize(c->d, r, c->stream));
+  }
   return NBODY_OK;
 }
 
@@ -458,33 +515,91 @@ int nbody_init(nbody_ctx **out, const nbody_params *p, int64_t n, const double *
 
 int nbody_forces(nbody_ctx *c, const int32_t *i_active, int64_t n_active, const double *xj,
                  const double *vj, const double *mj, int64_t n_j, double *acc, double *jerk) {
+  if (!vj || !jerk) return fail(NBODY_EINVAL, "NULL array argument");
+  return api_forces(c, false, i_active, n_active, xj, vj, mj, n_j, acc, jerk);
+}
+
+int nbody_accel(nbody_ctx *c, const int32_t *i_active, int64_t n_active, const double *xj,
+                const double *mj, int64_t n_j, double *acc) {
+  return api_forces(c, true, i_active, n_active, xj, nullptr, mj, n_j, acc, nullptr);
+}
+
+int nbody_step_symplectic(nbody_ctx *c, int scheme, double h, int64_t n_steps,
+                          int64_t *n_interactions) {
   if (!c) return fail(NBODY_EINVAL, "context is NULL");
-  if (n_active < 0) return fail(NBODY_EINVAL, "n_active < 0");
-  if (n_active == 0) return NBODY_OK;
-  if (!i_active || !xj || !vj || !mj || !acc || !jerk)
-    return fail(NBODY_EINVAL, "NULL array argument");
-  if (n_j < 1 || n_j > kMaxN) return fail(NBODY_EINVAL, "n_j must be in [1, 2^30]");
-  if (c->C > 1 && n_j != c->n)
-    return fail(NBODY_EINVAL, "with several clusters n_j must equal the context's n");
+  if (scheme != NBODY_LEAPFROG && scheme != NBODY_SYMPLECTIC6)
+    return fail(NBODY_EINVAL, "unknown symplectic scheme");
+  if (n_steps < 0) return fail(NBODY_EINVAL, "n_steps < 0");
+  const double ht = h * (double)(1 << nbk::kTickBits);
+  if (!(h > 0.0) || !std::isfinite(h) || ht != std::floor(ht) || ht > 9.0e15)
+    return fail(NBODY_EINVAL, "h must be a positive multiple of 2^-20");
+  const int64_t hticks = (int64_t)ht;
+  const int64_t dtmax = (int64_t)1 << (nbk::kTickBits - c->lmin);
+  if (n_steps > (int64_t)9.0e15 / hticks) return fail(NBODY_EINVAL, "n_steps * h too large");
+  const int64_t span = n_steps * hticks;
+  if (span % dtmax)
+    return fail(NBODY_EINVAL, "n_steps * h must be a multiple of 2^-level_min");
+  int rc = readback(c);
+  if (rc) return rc;
+  if ((rc = take_error(c))) return rc;
+  if (n_interactions) *n_interactions = 0;
+  if (n_steps == 0) return NBODY_OK;
+  // stage weights: one leapfrog stage, or the symmetric seven-stage
+  // composition of sixth order (w3 w2 w1 w0 w1 w2 w3, w0 = 1 - 2 (w1 + w2 + w3))
+  std::vector<double> w;
+  if (scheme == NBODY_LEAPFROG) {
+    w = {1.0};
+  } else {
+    const double w1 = -1.17767998417887, w2 = 0.235573213359357, w3 = 0.784513610477560;
+    const double w0 = 1.0 - 2.0 * (w1 + w2 + w3);
+    w = {w3, w2, w1, w0, w1, w2, w3};
+  }
+  const int mode = acc_mode_of(c);
   const nbk::Tuning t = device_tuning(c, c->K);
-  const int64_t cap = c->d.cap_active;
-  for (int64_t k0 = 0; k0 < n_active; k0 += cap) {
-    nbk::RawSrc r;
-    r.x = xj;
-    r.v = vj;
-    r.m = mj;
-    r.n_j = (c->C == 1) ? n_j : 0;
-    r.i_active = i_active + k0;
-    r.n_active = (n_active - k0 < cap) ? n_active - k0 : cap;
-    r.acc = acc + 3 * k0;
-    r.jerk = jerk + 3 * k0;
-    NB_HIP(nbk::launch_api_group(c->d, r, c->stream));
-    NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanApi, r.n_j, c->stream));
-    int rc = force_launch(c, mode_of(c), nbk::kSrcRaw, c->K, &r, r.i_active, c->grid_raw,
-                          c->stream, nbk::kPlanApi);
-    if (rc) return rc;
-    if ((rc = sum_and_refine(c, r.i_active, r.n_active, &r, c->stream))) return rc;
-    NB_HIP(nbk::launch_api_finalize(c->d, r, c->stream));
+  hipStream_t s = c->stream;
+  NB_HIP(nbk::launch_all_active(c->d, s));
+  auto evaluate = [&]() -> int {
+    NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, s));
+    int r = force_launch(c, mode, nbk::kSrcState, c->K, nullptr, c->d.active, c->grid_acc_state,
+                         s, nbk::kPlanState);
+    if (r) return r;
+    return sum_and_refine(c, c->d.active, -1, nullptr, s, /*acc_only=*/true);
+  };
+  // the state's acceleration was taken at predicted positions: evaluate
+  // at the current ones first
+  if ((rc = evaluate())) return rc;
+  double pending = 0.0;
+  bool first = true;
+  int64_t evals = 1;
+  for (int64_t st = 0; st < n_steps; ++st) {
+    for (double wk : w) {
+      const double cw = wk * h;
+      NB_HIP(nbk::launch_sym_kick_drift(c->d, pending + 0.5 * cw, cw, first, s));
+      first = false;
+      if ((rc = evaluate())) return rc;
+      pending = 0.5 * cw;
+      ++evals;
+    }
+    // bound the host's lead over the device on long runs
+    if ((st & 63) == 63) {
+      if ((rc = readback(c))) return rc;
+      if ((rc = take_error(c))) return rc;
+    }
+  }
+  NB_HIP(nbk::launch_sym_kick(c->d, pending, s));
+  NB_HIP(nbk::launch_sym_advance(c->d, span, s));
+  for (int k = 0; k < c->C; ++k) c->T_host[k] += span;
+  // leave a consistent Hermite state: a, jerk and levels at the new positions
+  if ((rc = full_evaluation_into_state(c))) return rc;
+  if ((rc = readback(c))) return rc;
+  if ((rc = take_error(c))) return rc;
+  if (n_interactions) {
+    int64_t pairs = 0;
+    for (int k = 0; k < c->C; ++k) {
+      const int64_t nc = c->coff[k + 1] - c->coff[k];
+      pairs += nc * nc;
+    }
+    *n_interactions = evals * pairs;
   }
   return NBODY_OK;
 }

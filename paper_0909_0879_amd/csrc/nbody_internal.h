@@ -20,7 +20,9 @@ constexpr int kNoActive = 99;       // threshold level meaning "nothing due"
 constexpr int kRowStride = 8;       // doubles per partial row: a(3), jerk(3),
                                     // bound on the largest acc term, pad
 
-enum ErrBits : int32_t { kErrNonFinite = 1, kErrDomain = 2, kErrIndex = 4 };
+// kErrState: a state given to nbody_set_state, or found by a driver, that
+// breaks the block-step invariants
+enum ErrBits : int32_t { kErrNonFinite = 1, kErrDomain = 2, kErrIndex = 4, kErrState = 8 };
 
 // counters in Dev::ctr
 enum Ctr : int {
@@ -115,8 +117,17 @@ struct Dev {
 
 // Where the force kernel takes j (and i) particles from.
 enum Source : int { kSrcState = 0, kSrcRaw = 1 };
-// What the force kernel computes.
-enum Mode : int { kModeFP64 = 0, kModeMixed = 1, kModePot = 2 };
+// What the force kernel computes: acceleration and jerk, the potential, or
+// the acceleration alone (the symplectic drivers and nbody_accel).
+enum Mode : int {
+  kModeFP64 = 0,
+  kModeMixed = 1,
+  kModePot = 2,
+  kModeFP64Acc = 3,
+  kModeMixedAcc = 4
+};
+constexpr bool mode_acc_only(int m) { return m == kModeFP64Acc || m == kModeMixedAcc; }
+constexpr bool mode_mixed(int m) { return m == kModeMixed || m == kModeMixedAcc; }
 
 // Host-side launchers (defined in nbody_kernels.hip).  Every launcher only
 // enqueues on `s`; none synchronises.  They return the hipError_t of the
@@ -158,6 +169,12 @@ hipError_t launch_records(const Dev &d, int mode, int kind, const RawSrc *raw,
 hipError_t launch_force_sb(const Dev &d, int mode, int K, const RawSrc *raw,
                            const int32_t *list, int grid, hipStream_t s);
 int force_sb_grid_size(int mode, int K, int device);
+// Symplectic drivers: kick (v += ck a, a from fsum) then drift (x += cd v);
+// final kick; advance all times by dticks.
+hipError_t launch_sym_kick_drift(const Dev &d, double ck, double cd, bool check,
+                                 hipStream_t s);
+hipError_t launch_sym_kick(const Dev &d, double ck, hipStream_t s);
+hipError_t launch_sym_advance(const Dev &d, int64_t dticks, hipStream_t s);
 hipError_t launch_correct(const Dev &d, double eta, double dt_shared,
                           int level_min, int level_max, hipStream_t s);
 hipError_t launch_init_levels(const Dev &d, double eta_start,

@@ -231,6 +231,50 @@ __device__ __forceinline__ void pair_mixed(const IDS &I, int iidx, const JRecDS 
   t[5] = fmaf(mr3, fmaf(-al, dz, wz), t[5]);
 }
 
+// Acceleration only: the same operations as the two functions above up to
+// the acceleration sums (so both give identical accelerations), no jerk.
+template <bool MASK>
+__device__ __forceinline__ void pair_fp64_acc(const I64 &I, int iidx, const JRec64 &r,
+                                              double eps2, double *t, int &dom) {
+  const double dx = r.x - I.x[0], dy = r.y - I.x[1], dz = r.z - I.x[2];
+  const double s = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+  double rinv = rsq64(s);
+  if (MASK) {
+    if (s == 0.0) {
+      rinv = 0.0;
+      dom |= (r.idx != iidx);
+    }
+  }
+  const double rinv2 = rinv * rinv;
+  const double mr3 = (r.m * rinv) * rinv2;
+  t[0] = fma(mr3, dx, t[0]);
+  t[1] = fma(mr3, dy, t[1]);
+  t[2] = fma(mr3, dz, t[2]);
+}
+
+template <bool MASK, bool SELF>
+__device__ __forceinline__ void pair_mixed_acc(const IDS &I, int iidx, const JRecDS &r,
+                                               float eps2, float *t, int &dom, float &tmx) {
+  const float dx = (r.xh - I.xh[0]) + (r.xl - I.xl[0]);
+  const float dy = (r.yh - I.xh[1]) + (r.yl - I.xl[1]);
+  const float dz = (r.zh - I.xh[2]) + (r.zl - I.xl[2]);
+  const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+  float rinv = __builtin_amdgcn_rsqf(s);
+  if (MASK) {
+    if (dx == 0.0f && dy == 0.0f && dz == 0.0f) {
+      rinv = 0.0f;
+      dom |= (r.idx != iidx);
+    }
+  }
+  const float rinv2 = rinv * rinv;
+  const float mq = r.m * rinv2;
+  const float mr3 = mq * rinv;
+  tmx = fmaxf(tmx, (SELF && r.idx == iidx) ? 0.0f : mq);
+  t[0] = fmaf(mr3, dx, t[0]);
+  t[1] = fmaf(mr3, dy, t[1]);
+  t[2] = fmaf(mr3, dz, t[2]);
+}
+
 __device__ __forceinline__ void pair_pot(const I64 &I, int iidx, const JRec64 &r,
                                          double eps2, double *t) {
   const double dx = r.x - I.x[0], dy = r.y - I.x[1], dz = r.z - I.x[2];
@@ -251,6 +295,20 @@ template <> struct Traits<kModeMixed> {
   using Rec = JRecDS;
   using Ist = IDS;
   static constexpr int NC = 6;
+  static constexpr int FOLD = 64;
+};
+template <> struct Traits<kModeFP64Acc> {
+  using T = double;
+  using Rec = JRec64;
+  using Ist = I64;
+  static constexpr int NC = 3;
+  static constexpr int FOLD = kTJ;
+};
+template <> struct Traits<kModeMixedAcc> {
+  using T = float;
+  using Rec = JRecDS;
+  using Ist = IDS;
+  static constexpr int NC = 3;
   static constexpr int FOLD = 64;
 };
 template <> struct Traits<kModePot> {
@@ -287,6 +345,10 @@ __device__ __forceinline__ void pair_k(const typename Traits<MODE>::Rec &r,
       pair_mixed<MASK, SELF>(I[k], iidx[k], r, (float)eps2, t[k], dom[k], tmx[k]);
     else if constexpr (MODE == kModeFP64)
       pair_fp64<MASK>(I[k], iidx[k], r, eps2, t[k], dom[k]);
+    else if constexpr (MODE == kModeMixedAcc)
+      pair_mixed_acc<MASK, SELF>(I[k], iidx[k], r, (float)eps2, t[k], dom[k], tmx[k]);
+    else if constexpr (MODE == kModeFP64Acc)
+      pair_fp64_acc<MASK>(I[k], iidx[k], r, eps2, t[k], dom[k]);
     else
       pair_pot(I[k], iidx[k], r, eps2, t[k]);
   }
@@ -408,7 +470,7 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           xp[c] = A.rx[3 * (int64_t)iidx[k] + c];
-          vp[c] = A.rv[3 * (int64_t)iidx[k] + c];
+          vp[c] = mode_acc_only(MODE) ? 0.0 : A.rv[3 * (int64_t)iidx[k] + c];
         }
       }
       make_i(xp, vp, I[k]);
@@ -437,7 +499,7 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             xp[c] = A.rx[3 * j + c];
-            vp[c] = A.rv[3 * j + c];
+            vp[c] = mode_acc_only(MODE) ? 0.0 : A.rv[3 * j + c];
           }
           m = A.rm[j];
         }
@@ -455,14 +517,14 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
       if (Q == 1) {
         if (msk)
           tile_loop<MODE, K, true, true, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
-        else if (MODE == kModeMixed && self_tile)
+        else if (mode_mixed(MODE) && self_tile)
           tile_loop<MODE, K, true, false, true>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
         else
           tile_loop<MODE, K, true, false, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
       } else {
         if (msk)
           tile_loop<MODE, K, false, true, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
-        else if (MODE == kModeMixed && self_tile)
+        else if (mode_mixed(MODE) && self_tile)
           tile_loop<MODE, K, false, false, true>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
         else
           tile_loop<MODE, K, false, false, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
@@ -525,7 +587,11 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
           double *row = d.partial + (cp.row_off + (int64_t)split * cp.na + slot) * kRowStride;
 #pragma unroll
           for (int c = 0; c < NC; ++c) row[c] = ok[k] ? res[k][c] : 0.0;
-          if (NC == 6) row[6] = ok[k] ? (double)tmx[k] : 0.0;
+          if (MODE != kModePot) {
+#pragma unroll
+            for (int c = NC; c < 6; ++c) row[c] = 0.0;    // no jerk in acc-only modes
+            row[6] = ok[k] ? (double)tmx[k] : 0.0;
+          }
         }
       }
     }
@@ -1033,7 +1099,7 @@ __global__ void k_api_finalize(Dev d, int64_t na, double *acc, double *jerk) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       acc[3 * k + q] = f[q];
-      jerk[3 * k + q] = f[3 + q];
+      if (jerk) jerk[3 * k + q] = f[3 + q];
     }
     if (!(finite3(f) && finite3(f + 3))) atomicOr(d.err, (int)kErrNonFinite);
   }
@@ -1076,7 +1142,7 @@ __global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, in
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         xp[c] = raw.x[3 * i + c];
-        vp[c] = raw.v[3 * i + c];
+        vp[c] = raw.v ? raw.v[3 * i + c] : 0.0;
       }
       m = raw.m[i];
     } else {
@@ -1261,7 +1327,7 @@ __global__ __launch_bounds__(kWG) void k_force_sb(ForceArgs A) {
       const ScalarPtr<Rec> rb = spred + jb;
       if (mask)
         sb_run<MODE, K, true, false>(rb, cnt, I, iidx, eps2, t, dom, tmx);
-      else if (MODE == kModeMixed && self)
+      else if (mode_mixed(MODE) && self)
         sb_run<MODE, K, false, true>(rb, cnt, I, iidx, eps2, t, dom, tmx);
       else
         sb_run<MODE, K, false, false>(rb, cnt, I, iidx, eps2, t, dom, tmx);
@@ -1277,9 +1343,65 @@ __global__ __launch_bounds__(kWG) void k_force_sb(ForceArgs A) {
 #pragma unroll
         for (int c = 0; c < NC; ++c)
           row[c] = ok[k] ? (double)shi[k][c] + (double)slo[k][c] : 0.0;
+#pragma unroll
+        for (int c = NC; c < 6; ++c) row[c] = 0.0;
         row[6] = ok[k] ? (double)tmx[k] : 0.0;
       }
     }
+  }
+}
+
+// ------------------------------------------------------------ symplectic drivers
+//
+// The paper's time-symmetric integrators as kick / drift sweeps over the
+// state, with the accelerations of the last evaluation in fsum (entry k =
+// particle k: every particle is active).  A stage of step c = w h is
+//   v += (pending + c / 2) a;  x += c v;  a = F(x);  pending = c / 2,
+// so consecutive half kicks merge and each stage costs one evaluation.
+
+// Kick by ck, then drift by cd.  check: every particle must sit at its
+// cluster's time (no particle in the middle of a block step).
+__global__ void k_sym_kick_drift(Dev d, double ck, double cd, int check) {
+  const int64_t n = d.n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (check && d.tick[i] != d.T[d.cid[i]]) atomicOr(d.err, kErrState);
+    bool fin = true;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double v = d.v[c * n + i];
+      if (ck != 0.0) v = fma(ck, d.fsum[6 * i + c], v);
+      const double x = fma(cd, v, d.x[c * n + i]);
+      d.v[c * n + i] = v;
+      d.x[c * n + i] = x;
+      fin = fin && isfinite(x) && isfinite(v);
+    }
+    if (!fin) atomicOr(d.err, (int)kErrNonFinite);
+  }
+}
+
+__global__ void k_sym_kick(Dev d, double ck) {
+  const int64_t n = d.n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    bool fin = true;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double v = fma(ck, d.fsum[6 * i + c], d.v[c * n + i]);
+      d.v[c * n + i] = v;
+      fin = fin && isfinite(v);
+    }
+    if (!fin) atomicOr(d.err, (int)kErrNonFinite);
+  }
+}
+
+// Advance every particle's and cluster's time by dticks.
+__global__ void k_sym_advance(Dev d, int64_t dticks) {
+  const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t i = gt; i < d.n; i += (int64_t)gridDim.x * blockDim.x) d.tick[i] += dticks;
+  if (gt < d.C) {
+    d.T[gt] += dticks;
+    d.Tnext[gt] = d.T[gt];
   }
 }
 
@@ -1566,8 +1688,6 @@ __global__ void k_get_state(Dev d, double *x, double *v, double *a, double *jk,
   }
 }
 
-constexpr int32_t kErrState = 8;
-
 // set_state pass 1: copy in, validate levels, cluster time = max tick.
 __global__ void k_set_state1(Dev d, const double *x, const double *v,
                              const double *a, const double *jk,
@@ -1704,6 +1824,14 @@ hipError_t launch_force(const Dev &d, int mode, int src, int K,
   NB_CASE(kModeMixed, kSrcState, 2)
   NB_CASE(kModeMixed, kSrcRaw, 1)
   NB_CASE(kModeMixed, kSrcRaw, 2)
+  NB_CASE(kModeFP64Acc, kSrcState, 1)
+  NB_CASE(kModeFP64Acc, kSrcState, 2)
+  NB_CASE(kModeFP64Acc, kSrcRaw, 1)
+  NB_CASE(kModeFP64Acc, kSrcRaw, 2)
+  NB_CASE(kModeMixedAcc, kSrcState, 1)
+  NB_CASE(kModeMixedAcc, kSrcState, 2)
+  NB_CASE(kModeMixedAcc, kSrcRaw, 1)
+  NB_CASE(kModeMixedAcc, kSrcRaw, 2)
   NB_CASE(kModePot, kSrcState, 1)
 #undef NB_CASE
   return hipErrorInvalidValue;
@@ -1720,9 +1848,36 @@ int force_grid_size(int mode, int src, int K, int device) {
   NB_CASE(kModeMixed, kSrcState, 2)
   NB_CASE(kModeMixed, kSrcRaw, 1)
   NB_CASE(kModeMixed, kSrcRaw, 2)
+  NB_CASE(kModeFP64Acc, kSrcState, 1)
+  NB_CASE(kModeFP64Acc, kSrcState, 2)
+  NB_CASE(kModeFP64Acc, kSrcRaw, 1)
+  NB_CASE(kModeFP64Acc, kSrcRaw, 2)
+  NB_CASE(kModeMixedAcc, kSrcState, 1)
+  NB_CASE(kModeMixedAcc, kSrcState, 2)
+  NB_CASE(kModeMixedAcc, kSrcRaw, 1)
+  NB_CASE(kModeMixedAcc, kSrcRaw, 2)
   NB_CASE(kModePot, kSrcState, 1)
 #undef NB_CASE
   return 0;
+}
+
+hipError_t launch_sym_kick_drift(const Dev &d, double ck, double cd, bool check,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_sym_kick_drift, dim3(grid_for(d.n)), dim3(kWG), 0, s, d, ck, cd,
+                     check ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_sym_kick(const Dev &d, double ck, hipStream_t s) {
+  hipLaunchKernelGGL(k_sym_kick, dim3(grid_for(d.n)), dim3(kWG), 0, s, d, ck);
+  return hipGetLastError();
+}
+
+hipError_t launch_sym_advance(const Dev &d, int64_t dticks, hipStream_t s) {
+  const int64_t need = d.n > d.C ? d.n : d.C;
+  // the cluster update needs one thread per cluster: C <= 4096 * kWG
+  hipLaunchKernelGGL(k_sym_advance, dim3(grid_for(need)), dim3(kWG), 0, s, d, dticks);
+  return hipGetLastError();
 }
 
 hipError_t launch_records(const Dev &d, int mode, int kind, const RawSrc *raw,
@@ -1731,7 +1886,7 @@ hipError_t launch_records(const Dev &d, int mode, int kind, const RawSrc *raw,
   if (raw) r = *raw;
   const int64_t nj = (kind == kPlanApi && r.n_j > 0) ? r.n_j : d.n;
   const dim3 g(grid_for(nj, kWG, 4096)), b(kWG);
-  if (mode == kModeMixed)
+  if (mode_mixed(mode))
     hipLaunchKernelGGL(k_records<kModeMixed>, g, b, 0, s, d, kind, r, allow_sb ? 1 : 0);
   else
     hipLaunchKernelGGL(k_records<kModeFP64>, g, b, 0, s, d, kind, r, allow_sb ? 1 : 0);
@@ -1748,20 +1903,33 @@ hipError_t launch_force_sb(const Dev &d, int mode, int K, const RawSrc *raw,
   A.rm = raw ? raw->m : nullptr;
   A.pred_on = d.pred_on;
   const dim3 g(grid), b(kWG);
-  if (mode == kModeMixed && K == 1) hipLaunchKernelGGL((k_force_sb<kModeMixed, 1>), g, b, 0, s, A);
-  else if (mode == kModeMixed && K == 2) hipLaunchKernelGGL((k_force_sb<kModeMixed, 2>), g, b, 0, s, A);
-  else if (mode == kModeFP64 && K == 1) hipLaunchKernelGGL((k_force_sb<kModeFP64, 1>), g, b, 0, s, A);
-  else if (mode == kModeFP64 && K == 2) hipLaunchKernelGGL((k_force_sb<kModeFP64, 2>), g, b, 0, s, A);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
+#define NB_CASE(M, KK) \
+  if (mode == M && K == KK) { hipLaunchKernelGGL((k_force_sb<M, KK>), g, b, 0, s, A); return hipGetLastError(); }
+  NB_CASE(kModeFP64, 1)
+  NB_CASE(kModeFP64, 2)
+  NB_CASE(kModeMixed, 1)
+  NB_CASE(kModeMixed, 2)
+  NB_CASE(kModeFP64Acc, 1)
+  NB_CASE(kModeFP64Acc, 2)
+  NB_CASE(kModeMixedAcc, 1)
+  NB_CASE(kModeMixedAcc, 2)
+#undef NB_CASE
+  return hipErrorInvalidValue;
 }
 
 int force_sb_grid_size(int mode, int K, int device) {
   const void *f = nullptr;
-  if (mode == kModeMixed && K == 1) f = (const void *)k_force_sb<kModeMixed, 1>;
-  else if (mode == kModeMixed && K == 2) f = (const void *)k_force_sb<kModeMixed, 2>;
-  else if (mode == kModeFP64 && K == 1) f = (const void *)k_force_sb<kModeFP64, 1>;
-  else if (mode == kModeFP64 && K == 2) f = (const void *)k_force_sb<kModeFP64, 2>;
+#define NB_CASE(M, KK) \
+  if (mode == M && K == KK) f = (const void *)k_force_sb<M, KK>;
+  NB_CASE(kModeFP64, 1)
+  NB_CASE(kModeFP64, 2)
+  NB_CASE(kModeMixed, 1)
+  NB_CASE(kModeMixed, 2)
+  NB_CASE(kModeFP64Acc, 1)
+  NB_CASE(kModeFP64Acc, 2)
+  NB_CASE(kModeMixedAcc, 1)
+  NB_CASE(kModeMixedAcc, 2)
+#undef NB_CASE
   if (!f) return 0;
   int per_cu = 0, cus = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kWG, 0) != hipSuccess) per_cu = 1;

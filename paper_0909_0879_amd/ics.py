@@ -260,3 +260,18 @@ def uniform_sphere(n: int, seed: int, radius: float = 1.0,
     x = r[:, None] * isotropic(rng, n)
     v = rng.uniform(0.0, 1.0, n)[:, None] * isotropic(rng, n)
     return m, x, v
+
+
+def uniform_sphere_virial(n: int, seed: int, q: float = 1.0):
+    """The initial conditions of the paper's code (Sect. 4): unit mass
+    uniform in a sphere of unit radius, velocities uniform in direction and
+    magnitude, rescaled to the virial ratio Q = 2K/|W|.  |W| is taken as
+    the continuous uniform sphere's 3/5 (G = M = R = 1), which the sample
+    approaches as N grows; the sample is shifted to its centre-of-mass frame."""
+    m, x, v = uniform_sphere(n, seed)
+    x = x - (m[:, None] * x).sum(axis=0) / m.sum()
+    v = v - (m[:, None] * v).sum(axis=0) / m.sum()
+    k = 0.5 * (m * (v * v).sum(axis=1)).sum()
+    if k > 0:
+        v = v * np.sqrt(0.5 * q * 0.6 / k)
+    return m, x, v

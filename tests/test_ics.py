@@ -76,3 +76,17 @@ def test_ensemble_sizes_and_layout():
         assert abs(m[sl].sum() - 1.0) < 1e-12
         mc, xc, vc = ics.plummer(int(off[c + 1] - off[c]), 5000 + c)
         assert np.array_equal(xc, x[sl])
+
+
+def test_uniform_sphere_virial_matches_paper_setup():
+    # unit mass inside the unit sphere, COM frame, K = Q |W| / 2 with the
+    # continuous sphere's |W| = 3/5; the sampled W approaches -3/5
+    import oracle
+    m, x, v = ics.uniform_sphere_virial(2048, 11, q=1.0)
+    assert abs(m.sum() - 1.0) < 1e-12
+    assert np.linalg.norm(x, axis=1).max() <= 1.0 + 0.05
+    assert np.abs((m[:, None] * x).sum(axis=0)).max() < 1e-12
+    k = 0.5 * (m * (v * v).sum(axis=1)).sum()
+    assert abs(k - 0.3) < 1e-12
+    e = oracle.energy(x, v, m, 0.0)
+    assert abs(e["W"] + 0.6) < 0.03
