@@ -3,16 +3,18 @@
 Workload: King model W0 = 7, N = 1,048,576 equal-mass particles in Henon
 units, eps = 1e-4 (seeded synthetic input).  One benchmark step is one
 Hermite-4 block step of the whole hot path with every particle active:
-scheduler and compaction, prediction of all particles while they are
-staged through LDS, the O(N^2) acceleration + jerk evaluation, corrector,
+scheduler and compaction, prediction of all particles into the j-record
+buffer, the O(N^2) acceleration + jerk evaluation, corrector,
 Aarseth step choice and level bookkeeping (all particles held on one level
 so that every step is a full N x N evaluation).  Interactions per step are
 N^2 kernel slots.  The mixed-precision path is the headline value; the
 plain FP64 path is timed the same way beside it.
 
 Prints ONE JSON line.  Extra keys: "fp64" (the FP64 path's throughput),
-"mixed_over_fp64", "roofline" (force kernel, HIP-event timed), "cpu_baseline"
-(the CPU oracle on a bounded sample of the same evaluation).
+"mixed_over_fp64", "roofline" (force kernel, HIP-event timed), "counters"
+(counter-based FLOP rates and observed clock from the committed rocprofv3
+runs), "cpu_baseline" (the CPU oracle on a bounded sample of the same
+evaluation).
 """
 import argparse
 import json
@@ -76,6 +78,26 @@ def measured_traffic():
     if t.get("kernel_sha256") != kernel_hash():
         return None
     return t["fetch_kib"] * 1024.0 * t["fetch_scale"] + t["write_kib"] * 1024.0 * t["write_scale"]
+
+
+COUNTER_FILE = os.path.join(ROOT, "profiles", "counters_k_force_king1M.json")
+
+
+def measured_counters():
+    """Counter-based FLOP rates and the observed clock of the two force
+    kernels from the committed rocprofv3 SQ counter runs (every executed FP
+    operation: FMA 2, add / mul / transcendental 1, x 64 lanes); None if the
+    kernel source changed since."""
+    if not os.path.exists(COUNTER_FILE):
+        return None
+    with open(COUNTER_FILE) as f:
+        c = json.load(f)
+    if c.get("kernel_sha256") != kernel_hash():
+        return None
+    return {k: {"kernel": c[k]["kernel"], "counter_tflops": c[k]["counter_tflops"],
+                "frac_peak": c[k]["frac_fp32_peak" if k == "mixed" else "frac_fp64_peak"],
+                "valu_instr_per_interaction": c[k]["valu_instr_per_interaction"],
+                "clock_ghz": c[k]["clock_ghz"]} for k in ("mixed", "fp64")}
 
 
 def calibrate_copy(nbytes):
@@ -317,6 +339,7 @@ def main():
                      "flops_per_launch": per_launch_flops},
         "fp64_reevaluation": {"ms_per_step": mixed["refine_ms_per_step"],
                               "particles_since_init": mixed["refined_total"]},
+        "counters": measured_counters(),
     }
     if fp64:
         f_ach = per_launch_flops / (fp64["kernel_ms"] * 1e-3) / 1e12
