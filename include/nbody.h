@@ -161,6 +161,14 @@ int nbody_step_symplectic(nbody_ctx *c, int scheme, double h, int64_t n_steps,
 int nbody_step(nbody_ctx *c, double t_end, int64_t *n_block_steps,
                int64_t *n_interactions);
 
+/* As nbody_step, but stop after at most max_block_steps block-step
+ * iterations (eager launches, no graph): for output or checks at block-step
+ * granularity.  Clusters may stop short of t_end, each at the time of its
+ * last block step, with particles in the middle of their own steps; a later
+ * nbody_step or nbody_step_blocks continues from there.  Syncs. */
+int nbody_step_blocks(nbody_ctx *c, double t_end, int64_t max_block_steps,
+                      int64_t *n_block_steps, int64_t *n_interactions);
+
 /* Diagnostics per cluster, computed in FP64 at each cluster's current time
  * (every particle predicted to it): out (host) receives 9 doubles per
  * cluster: K, W, E, Lx, Ly, Lz, Px, Py, Pz, with K = 1/2 sum m v^2,

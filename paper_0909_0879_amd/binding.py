@@ -28,6 +28,7 @@ EXPORTED = [
     "nbody_get_state", "nbody_set_state", "nbody_sync", "nbody_stats", "nbody_destroy",
     "nbody_strerror", "nbody_last_error", "nbody_get_tuning", "nbody_set_tuning",
     "nbody_profile", "nbody_profile_read", "nbody_accel", "nbody_step_symplectic",
+    "nbody_step_blocks",
 ]
 
 
@@ -109,6 +110,7 @@ def lib():
         L.nbody_profile_read.argtypes = [P, P, P, P, P]
         L.nbody_accel.argtypes = [P, P, C.c_int64, P, P, C.c_int64, P]
         L.nbody_step_symplectic.argtypes = [P, C.c_int, C.c_double, C.c_int64, P]
+        L.nbody_step_blocks.argtypes = [P, C.c_double, C.c_int64, P, P]
         _lib = L
     return _lib
 
@@ -240,6 +242,13 @@ class NBody:
     def step(self, t_end):
         ns, ni = C.c_int64(0), C.c_int64(0)
         check(lib().nbody_step(self.ctx, float(t_end), C.byref(ns), C.byref(ni)), "nbody_step")
+        return ns.value, ni.value
+
+    def step_blocks(self, t_end, max_block_steps):
+        """At most max_block_steps block steps toward t_end."""
+        ns, ni = C.c_int64(0), C.c_int64(0)
+        check(lib().nbody_step_blocks(self.ctx, float(t_end), int(max_block_steps), C.byref(ns),
+                                      C.byref(ni)), "nbody_step_blocks")
         return ns.value, ni.value
 
     def energy(self):

@@ -402,6 +402,21 @@ int full_evaluation_into_state(nbody_ctx *c) {
   return NBODY_OK;
 }
 
+// t_end of nbody_step / nbody_step_blocks in ticks, validated.
+int check_t_end(const nbody_ctx *c, double t_end, int64_t *tend_out) {
+  if (!std::isfinite(t_end) || t_end < 0.0) return fail(NBODY_EINVAL, "t_end must be finite and >= 0");
+  const double tt = t_end * (double)(1 << nbk::kTickBits);
+  if (tt > 9.0e15 || tt != std::floor(tt))
+    return fail(NBODY_EINVAL, "t_end must be a multiple of 2^-20");
+  const int64_t tend = (int64_t)tt;
+  const int64_t dtmax = (int64_t)1 << (nbk::kTickBits - c->lmin);
+  if (tend % dtmax) return fail(NBODY_EINVAL, "t_end must be a multiple of 2^-level_min");
+  for (int k = 0; k < c->C; ++k)
+    if (tend < c->T_host[k]) return fail(NBODY_EINVAL, "t_end is earlier than the current time");
+  *tend_out = tend;
+  return NBODY_OK;
+}
+
 // nbody_forces / nbody_accel: the caller's j arrays, chunks of at most
 // cap_active i entries.
 int api_forces(nbody_ctx *c, bool acc_only, const int32_t *i_active, int64_t n_active,
@@ -606,16 +621,10 @@ int nbody_step_symplectic(nbody_ctx *c, int scheme, double h, int64_t n_steps,
 
 int nbody_step(nbody_ctx *c, double t_end, int64_t *n_block_steps, int64_t *n_interactions) {
   if (!c) return fail(NBODY_EINVAL, "context is NULL");
-  if (!std::isfinite(t_end) || t_end < 0.0) return fail(NBODY_EINVAL, "t_end must be finite and >= 0");
-  const double tt = t_end * (double)(1 << nbk::kTickBits);
-  if (tt > 9.0e15 || tt != std::floor(tt))
-    return fail(NBODY_EINVAL, "t_end must be a multiple of 2^-20");
-  const int64_t tend = (int64_t)tt;
-  const int64_t dtmax = (int64_t)1 << (nbk::kTickBits - c->lmin);
-  if (tend % dtmax) return fail(NBODY_EINVAL, "t_end must be a multiple of 2^-level_min");
-  for (int k = 0; k < c->C; ++k)
-    if (tend < c->T_host[k]) return fail(NBODY_EINVAL, "t_end is earlier than the current time");
-  int rc = readback(c);
+  int64_t tend = 0;
+  int rc = check_t_end(c, t_end, &tend);
+  if (rc) return rc;
+  rc = readback(c);
   if (rc) return rc;
   if ((rc = take_error(c))) return rc;
   const int64_t steps0 = c->pinned[nbk::kCtrSteps], inter0 = c->pinned[nbk::kCtrInter];
@@ -640,6 +649,36 @@ int nbody_step(nbody_ctx *c, double t_end, int64_t *n_block_steps, int64_t *n_in
   }
   if ((rc = take_error(c))) return rc;
   for (int k = 0; k < c->C; ++k) c->T_host[k] = tend;
+  if (n_block_steps) *n_block_steps = c->pinned[nbk::kCtrSteps] - steps0;
+  if (n_interactions) *n_interactions = c->pinned[nbk::kCtrInter] - inter0;
+  return NBODY_OK;
+}
+
+int nbody_step_blocks(nbody_ctx *c, double t_end, int64_t max_block_steps,
+                      int64_t *n_block_steps, int64_t *n_interactions) {
+  if (!c) return fail(NBODY_EINVAL, "context is NULL");
+  if (max_block_steps < 0) return fail(NBODY_EINVAL, "max_block_steps < 0");
+  int64_t tend = 0;
+  int rc = check_t_end(c, t_end, &tend);
+  if (rc) return rc;
+  if ((rc = readback(c))) return rc;
+  if ((rc = take_error(c))) return rc;
+  const int64_t steps0 = c->pinned[nbk::kCtrSteps], inter0 = c->pinned[nbk::kCtrInter];
+  NB_HIP(nbk::launch_set_word64(c->d.ctr + nbk::kCtrTend, tend, c->stream));
+  for (int64_t k = 0; k < max_block_steps; ++k) {
+    if ((rc = enqueue_block_step(c, c->stream))) return rc;
+    if ((k & 63) == 63 || k + 1 == max_block_steps) {
+      if ((rc = readback(c))) return rc;
+      if (*(const int32_t *)(c->pinned + 16)) break;
+      if (c->pinned[nbk::kCtrNotDone] == 0) break;
+    }
+  }
+  if ((rc = readback(c))) return rc;
+  if ((rc = take_error(c))) return rc;
+  // clusters may stop anywhere on the way: take their times from the device
+  NB_HIP(hipMemcpyAsync(c->T_host.data(), c->d.T, sizeof(int64_t) * c->C,
+                        hipMemcpyDeviceToHost, c->stream));
+  NB_HIP(hipStreamSynchronize(c->stream));
   if (n_block_steps) *n_block_steps = c->pinned[nbk::kCtrSteps] - steps0;
   if (n_interactions) *n_interactions = c->pinned[nbk::kCtrInter] - inter0;
   return NBODY_OK;

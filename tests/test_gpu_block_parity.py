@@ -1,0 +1,89 @@
+"""Forces inside real block steps at the sizes of the larger runs: after a
+sampled block step, the stored acceleration and jerk of the particles it
+advanced (taken at the predicted positions of every particle) against the
+oracle fed the same predicted state — every particle predicted from the
+previous state over its own interval to the step's time.  Covers the step
+path's own plans, records and kernels on partial active sets, both below
+and above the size at which the step builds its j records."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0909_0879_amd import binding, ics
+from tests.gpu_util import check_parity, require_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+TICK = 2.0 ** -20
+
+
+def _state(g):
+    return {k: to_np(t) for k, t in g.get_state().items()}
+
+
+def _check_block_steps(g, m, eps, t_end, checks, every, sample, mixed, label):
+    rng = np.random.default_rng(17)
+    n = m.shape[0]
+    sizes = []
+    for c in range(checks):
+        if every > 1:
+            g.step_blocks(t_end, every - 1)
+        s0 = _state(g)
+        ns, _ = g.step_blocks(t_end, 1)
+        assert ns == 1
+        s1 = _state(g)
+        active = np.nonzero(s1["tick"] != s0["tick"])[0]
+        assert active.size > 0
+        t_next = s1["tick"][active]
+        assert np.all(t_next == t_next[0])
+        dt = (t_next[0] - s0["tick"]) * TICK
+        xp, vp = oracle.predict(s0["x"], s0["v"], s0["a"], s0["j"], dt)
+        idx = active if active.size <= sample else np.sort(rng.choice(active, sample, False))
+        a_ref, j_ref = oracle.forces(xp, vp, m, eps, idx=idx.astype(np.int64))
+        print(f"  {label} check {c}: n_active {active.size} of {n}", flush=True)
+        check_parity(s1["a"][idx], s1["j"][idx], a_ref, j_ref, mixed, f"{label} {c}")
+        sizes.append(active.size)
+    return sizes
+
+
+def test_fp64_block_steps_plummer_65536():
+    # Plummer N = 65536, eps = 1e-3, FP64, levels 2^-6 ... 2^-20
+    require_gpu()
+    m, x, v = ics.plummer(65536, 2)
+    g = binding.NBody(m, x, v, eps=1e-3, precision=binding.FP64, eta=0.01, eta_start=0.01,
+                      level_min=6, level_max=20, tuning="auto")
+    g.step(1 / 64)
+    sizes = _check_block_steps(g, m, 1e-3, 1 / 8, checks=8, every=16, sample=256,
+                               mixed=False, label="plummer65536")
+    # the next step after a synchronised time moves only the finest level
+    assert min(sizes) < 65536 // 16
+    g.step(1 / 8)                         # the run still reaches t_end
+    assert np.all(_state(g)["tick"] == (1 << 20) // 8)
+
+
+def test_mixed_block_steps_salpeter_262144():
+    # Plummer N = 262144 with Salpeter masses, eps = 1e-4, mixed precision
+    require_gpu()
+    n = 262144
+    m, x, v = ics.plummer(n, 3, masses=ics.salpeter_masses(n, 3))
+    g = binding.NBody(m, x, v, eps=1e-4, precision=binding.MIXED, eta=0.01, eta_start=0.01,
+                      level_min=7, level_max=20, tuning="auto")
+    g.step(1 / 128)
+    _check_block_steps(g, m, 1e-4, 1 / 16, checks=6, every=24, sample=256, mixed=True,
+                       label="salpeter262144")
+
+
+def test_whole_level_step_builds_records():
+    # a block step that moves every particle of a level >= n/16 takes the
+    # record path (and the broadcast kernel under the FP64 tuning)
+    require_gpu()
+    n = 16384
+    m, x, v = ics.plummer(n, 8)
+    for prec in (binding.FP64, binding.MIXED):
+        g = binding.NBody(m, x, v, eps=1e-3, precision=prec, dt_shared=1 / 256, level_min=4,
+                          level_max=8, tuning={"variant": binding.VARIANT_S2
+                                               if prec == binding.FP64 else binding.VARIANT_K1})
+        sizes = _check_block_steps(g, m, 1e-3, 1 / 16, checks=2, every=1, sample=512,
+                                   mixed=prec == binding.MIXED, label=f"shared prec={prec}")
+        assert sizes == [n, n]
+        g.close()
