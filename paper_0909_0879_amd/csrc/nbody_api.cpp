@@ -195,6 +195,7 @@ struct nbody_ctx {
   bool sb = false;                // broadcast kernel for large evaluations
   int grid_state = 0, grid_raw = 0, grid_pot = 0, grid_sb = 0;
   int grid_ref_state = 0, grid_ref_raw = 0;   // FP64 K = 1 re-evaluation
+  int grid_small = 0;             // FP64, the context's K: small mixed block steps
   // acceleration-only kernels (symplectic drivers, nbody_accel)
   int grid_acc_state = 0, grid_acc_raw = 0, grid_acc_sb = 0;
   int grid_ref_acc_state = 0, grid_ref_acc_raw = 0;
@@ -255,8 +256,9 @@ int refresh_grids(nbody_ctx *c) {
   c->grid_pot = nbk::force_grid_size(nbk::kModePot, nbk::kSrcState, 1, c->device);
   c->grid_ref_state = nbk::force_grid_size(nbk::kModeFP64, nbk::kSrcState, 1, c->device);
   c->grid_ref_raw = nbk::force_grid_size(nbk::kModeFP64, nbk::kSrcRaw, 1, c->device);
+  c->grid_small = nbk::force_grid_size(nbk::kModeFP64, nbk::kSrcState, c->K, c->device);
   if (c->grid_state < 1 || c->grid_raw < 1 || c->grid_pot < 1 || c->grid_ref_state < 1 ||
-      c->grid_ref_raw < 1 || c->grid_sb < 1 || c->grid_acc_sb < 1 || c->grid_acc_state < 1 ||
+      c->grid_ref_raw < 1 || c->grid_small < 1 || c->grid_sb < 1 || c->grid_acc_sb < 1 || c->grid_acc_state < 1 ||
       c->grid_acc_raw < 1 || c->grid_ref_acc_state < 1 || c->grid_ref_acc_raw < 1)
     return fail(NBODY_EHIP, "could not size the force kernel grid");
   return NBODY_OK;
@@ -271,16 +273,22 @@ int force_launch(nbody_ctx *c, int mode, int src, int K, const nbk::RawSrc *raw,
                  const int32_t *list, int grid, hipStream_t s, int rec_kind = -1) {
   const bool prof = c->profiling && s == c->stream;
   const bool use_pred = rec_kind >= 0;
+  // clusters of a mixed block step with few active particles run in FP64
+  const bool small = rec_kind == nbk::kPlanStep && mode == nbk::kModeMixed;
   if (use_pred) NB_HIP(nbk::launch_records(c->d, mode, rec_kind, raw, c->sb, s));
   if (prof && c->ev_used == kEvPairs) {
     int rc = harvest_events(c);
     if (rc) return rc;
   }
   if (prof) NB_HIP(hipEventRecord(c->ev[2 * c->ev_used], s));
-  NB_HIP(nbk::launch_force(c->d, mode, src, K, raw, list, use_pred, grid, s));
+  NB_HIP(nbk::launch_force(c->d, mode, src, K, raw, list,
+                            use_pred ? nbk::kRoleMain : nbk::kRoleAlways, grid, s));
   if (use_pred && c->sb)
     NB_HIP(nbk::launch_force_sb(c->d, mode, K, raw, list,
                                 nbk::mode_acc_only(mode) ? c->grid_acc_sb : c->grid_sb, s));
+  if (small)
+    NB_HIP(nbk::launch_force(c->d, nbk::kModeFP64, src, K, raw, list, nbk::kRoleSmall,
+                             c->grid_small, s));
   if (prof) {
     NB_HIP(hipEventRecord(c->ev[2 * c->ev_used + 1], s));
     // the potential kernel (energy diagnostics) is not counted; FP64 launches
@@ -323,7 +331,7 @@ int sum_and_refine(nbody_ctx *c, const int32_t *list, int64_t na_host, const nbk
   const nbk::Tuning t1 = device_tuning(c, 1);
   const bool api = raw != nullptr;
   NB_HIP(nbk::launch_plan(c->d, t1, api ? nbk::kPlanApiRefine : nbk::kPlanRefine,
-                          api ? raw->n_j : 0, s));
+                          api ? raw->n_j : 0, false, s));
   const int grid = acc_only ? (api ? c->grid_ref_acc_raw : c->grid_ref_acc_state)
                             : (api ? c->grid_ref_raw : c->grid_ref_state);
   int rc = force_launch(c, acc_only ? nbk::kModeFP64Acc : nbk::kModeFP64,
@@ -338,7 +346,7 @@ int enqueue_block_step(nbody_ctx *c, hipStream_t s) {
   const nbk::Tuning t = device_tuning(c, c->K);
   NB_HIP(nbk::launch_sched(c->d, s));
   NB_HIP(nbk::launch_compact(c->d, s));
-  NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanStep, 0, s));
+  NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanStep, 0, c->prec == NBODY_MIXED, s));
   int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->d.active,
                         c->grid_state, s, nbk::kPlanStep);
   if (rc) return rc;
@@ -390,7 +398,7 @@ int full_evaluation_into_state(nbody_ctx *c) {
   // initial forces: every particle active, predicted to its own time
   const nbk::Tuning t = device_tuning(c, c->K);
   NB_HIP(nbk::launch_all_active(c->d, c->stream));
-  NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, c->stream));
+  NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, false, c->stream));
   int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->d.active,
                         c->grid_state, c->stream, nbk::kPlanState);
   if (rc) return rc;
@@ -444,7 +452,7 @@ int api_forces(nbody_ctx *c, bool acc_only, const int32_t *i_active, int64_t n_a
     r.acc = acc + 3 * k0;
     r.jerk = jerk ? jerk + 3 * k0 : nullptr;
     NB_HIP(nbk::launch_api_group(c->d, r, c->stream));
-    NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanApi, r.n_j, c->stream));
+    NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanApi, r.n_j, false, c->stream));
     int rc = force_launch(c, mode, nbk::kSrcRaw, c->K, &r, r.i_active, grid, c->stream,
                           nbk::kPlanApi);
     if (rc) return rc;
@@ -574,7 +582,7 @@ int nbody_step_symplectic(nbody_ctx *c, int scheme, double h, int64_t n_steps,
   hipStream_t s = c->stream;
   NB_HIP(nbk::launch_all_active(c->d, s));
   auto evaluate = [&]() -> int {
-    NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, s));
+    NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, false, s));
     int r = force_launch(c, mode, nbk::kSrcState, c->K, nullptr, c->d.active, c->grid_acc_state,
                          s, nbk::kPlanState);
     if (r) return r;
@@ -688,7 +696,7 @@ int nbody_energy(nbody_ctx *c, double *out) {
   if (!c || !out) return fail(NBODY_EINVAL, "NULL argument");
   const nbk::Tuning t = device_tuning(c, 1);
   NB_HIP(nbk::launch_all_active(c->d, c->stream));
-  NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, c->stream));
+  NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, false, c->stream));
   int rc0 = force_launch(c, nbk::kModePot, nbk::kSrcState, 1, nullptr, c->d.active, c->grid_pot,
                          c->stream);
   if (rc0) return rc0;

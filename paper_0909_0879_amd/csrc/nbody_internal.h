@@ -17,6 +17,8 @@ constexpr int kMaxClusters = 4096;
 constexpr int kScanBlock = 1024;    // particles per block of the compaction
 constexpr int kBuckets = 25;        // tuning buckets floor(log2(n_active))
 constexpr int kNoActive = 99;       // threshold level meaning "nothing due"
+constexpr int kSmallStep = 256;     // mixed block steps up to this many active
+                                    // particles are evaluated by the FP64 kernel
 constexpr int kRowStride = 8;       // doubles per partial row: a(3), jerk(3),
                                     // bound on the largest acc term, pad
 
@@ -50,6 +52,9 @@ struct ClusterPlan {
   int64_t jb, je;   // j range [jb, je)
   int64_t chunk;    // j per split (multiple of kTJ)
   int64_t t_pred;   // tick every particle of the cluster is predicted to
+  int32_t small;    // mixed block step with <= kSmallStep active particles:
+                    // evaluated by the FP64 kernel, never re-evaluated
+  int32_t pad_;
 };
 
 struct Tuning {     // device copy of the launch policy (passed by value)
@@ -109,7 +114,8 @@ struct Dev {
   void *pred;             // n records of 64 bytes (the LDS record format)
   int32_t *pred_on;       // 0 none, 1 built, 2 built for the broadcast kernel
   // words
-  int32_t *work;       // item counter of the persistent force kernel
+  int32_t *work;       // [0] main item counter, [1] small-step item counter,
+                       // [2] number of main items (written by k_plan)
   int32_t *err;        // sticky error bits
   int64_t *ctr;        // kCtrCount counters
   double *eout;        // C * 9 energy output
@@ -145,22 +151,32 @@ hipError_t launch_init_state(const Dev &d, const double *m, const double *x,
 hipError_t launch_all_active(const Dev &d, hipStream_t s);
 hipError_t launch_sched(const Dev &d, hipStream_t s);
 hipError_t launch_compact(const Dev &d, hipStream_t s);
+// allow_small: clusters of a block step with at most kSmallStep active
+// particles are planned for the small-step FP64 launch (mixed contexts).
 hipError_t launch_plan(const Dev &d, const Tuning &t, int kind,
-                       int64_t api_nj, hipStream_t s);
+                       int64_t api_nj, bool allow_small, hipStream_t s);
 // Sum each active entry's partial rows into fsum; with refine_ratio > 0 also
 // flag entries whose largest acceleration term exceeds refine_ratio times
 // their net acceleration, and build the grouped re-evaluation list.
 hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_host,
                                float refine_ratio, hipStream_t s);
 hipError_t launch_refine_finalize(const Dev &d, hipStream_t s);
-// use_pred: the launch reads j (and i) records from d.pred when *d.pred_on
-// is 1, and leaves the evaluation to the broadcast kernel when it is 2
+// Which work a force launch takes.  The plan splits the items in two:
+// [0, work[2]) for the main launches, [work[2], total) for the small-step
+// launch.  kRoleAlways: the main items, whatever the record flag
+// (re-evaluation, potential); kRoleMain: the main items unless the record
+// flag (*d.pred_on, set by launch_records) is 2 — then the broadcast kernel
+// takes them — reading records when it is 1; kRoleSmall: the small-step
+// items (clusters of a mixed block step with <= kSmallStep active), in FP64
+// with the prediction fused into the tile fill.
+enum Role : int { kRoleAlways = 0, kRoleMain = 1, kRoleSmall = 2 };
 hipError_t launch_force(const Dev &d, int mode, int src, int K,
-                        const RawSrc *raw, const int32_t *list, bool use_pred,
+                        const RawSrc *raw, const int32_t *list, int role,
                         int grid, hipStream_t s);
 // Build the records of one evaluation into d.pred when its active set is at
 // least 1/16 of its j particles, and set *d.pred_on (0, 1, or 2 when the
-// broadcast kernel may take it: allow_sb and kWG i-slots in every cluster).
+// broadcast kernel may take it: allow_sb and kWG i-slots in every cluster
+// with work for the main kernels).
 // kind: kPlanStep (predict to T_next), kPlanState (to T), kPlanApi (raw).
 hipError_t launch_records(const Dev &d, int mode, int kind, const RawSrc *raw,
                           bool allow_sb, hipStream_t s);

@@ -387,7 +387,8 @@ struct ForceArgs {
   const int32_t *active;        // i list: internal active list, the caller's
                                 // i_active, or the FP64 re-evaluation list
   const double *rx, *rv, *rm;   // raw source (nbody_forces)
-  const int32_t *pred_on;       // non-null: d.pred may hold predicted records
+  const int32_t *pred_on;       // the evaluation's record flag (d.pred_on)
+  int role;                     // which flags this launch serves (Role)
 };
 
 __device__ __forceinline__ void rec_to_i(const JRec64 &r, I64 &s) {
@@ -415,15 +416,28 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
   __shared__ int s_g;
   const Dev &d = A.d;
   const int tid = threadIdx.x;
-  const int n_items = d.item_prefix[d.C];
-  // records built once for this evaluation (large active sets) or built
-  // here while the tile is filled (small active sets, other callers)
-  const int pred_flag = (A.pred_on != nullptr) ? *A.pred_on : 0;
-  if (pred_flag == 2) return;       // the broadcast kernel takes this evaluation
+  // items [0, work[2]) belong to the main launches, [work[2], total) to the
+  // small-step FP64 launch (clusters of a mixed block step with few active
+  // particles); records built once for this evaluation (large active sets)
+  // or built here while the tile is filled (small active sets, other calls)
+  int pred_flag = 0;
+  int item_base = 0, n_items = d.work[2];
+  int32_t *counter = d.work;
+  if (A.role == kRoleMain) {
+    pred_flag = *A.pred_on;
+    if (pred_flag == 2) return;     // the broadcast kernel takes these items
+  } else if (A.role == kRoleSmall) {
+    item_base = d.work[2];
+    n_items = d.item_prefix[d.C];
+    counter = d.work + 1;
+  }
+  // a launch with no items leaves before touching the shared counter (the
+  // whole grid queueing on one atomic costs more than the launch itself)
+  if (n_items <= item_base) return;
   const bool use_pred = pred_flag == 1;
   const Rec *pred = reinterpret_cast<const Rec *>(d.pred);
   for (;;) {
-    if (tid == 0) s_g = atomicAdd(d.work, 1);
+    if (tid == 0) s_g = item_base + atomicAdd(counter, 1);
     __syncthreads();
     const int g = s_g;
     __syncthreads();
@@ -808,52 +822,90 @@ __global__ __launch_bounds__(kWG) void k_scatter(Dev d) {
   if (blockIdx.x == 0 && threadIdx.x == 0) d.act_off[d.C] = d.blk_off[d.nblk];
 }
 
-// Launch plan for every cluster, in one 1024-thread workgroup.
-// kind 0: block step (predict to T_next, commit T = T_next, count);
-// kind 1: init / energy (predict to T); kind 2: nbody_forces (raw source).
+// Exclusive scan of one int64 per thread over a 1024-thread workgroup
+// (wave shuffles, then the 16 wave totals); returns the prefix and sets
+// *total.  sh: 16 int64 of LDS.
+__device__ __forceinline__ int64_t block_exscan64(int64_t v, int64_t *sh, int64_t *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) sh[w] = incl;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int64_t t = sh[u];
+    before += (u < w) ? t : 0;
+    all += t;
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - v;
+}
+
+// Launch plan for every cluster, in one 1024-thread workgroup; thread t owns
+// clusters t, t + 1024, ..., at most QN of them (C <= 1024 QN), kept in
+// registers.
+template <int QN>
 __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
-                                                int64_t api_nj) {
+                                                int64_t api_nj, int allow_small) {
   const bool refine = (kind == kPlanRefine || kind == kPlanApiRefine);
   const bool api = (kind == kPlanApi || kind == kPlanApiRefine);
   const int32_t *offs = refine ? d.ref_off : d.act_off;
-  __shared__ int64_t cost[kMaxClusters];
-  __shared__ int64_t scan64[1024];
+  __shared__ uint64_t key[QN * 1024];           // LPT order key per cluster
+  __shared__ int32_t items_by_rank[QN * 1024];
+  __shared__ int64_t sh[16];
   const int C = d.C;
   const int K = tu.K;
+  const int tid = threadIdx.x;
   int64_t my_inter = 0;
   int my_active = 0, my_notdone = 0;
-  for (int c = threadIdx.x; c < C; c += 1024) {
-    ClusterPlan cp;
-    cp.c = c;
-    cp.act_off = offs[c];
-    cp.na = offs[c + 1] - cp.act_off;
+  ClusterPlan cp[QN];
+#pragma unroll
+  for (int q = 0; q < QN; ++q) {
+    const int c = tid + 1024 * q;
+    ClusterPlan &p = cp[q];
+    p.c = c;
+    p.P = 256;
+    p.Qlog = 0;
+    p.S = 0;
+    p.na = 0;
+    p.act_off = 0;
+    p.tiles = 0;
+    p.items = 0;
+    p.row_off = 0;
+    p.jb = p.je = 0;
+    p.chunk = kTJ;
+    p.t_pred = 0;
+    p.small = 0;
+    p.pad_ = 0;
+    if (c >= C) continue;
+    p.act_off = offs[c];
+    p.na = offs[c + 1] - p.act_off;
     if (api && C == 1 && api_nj > 0) {
-      cp.jb = 0;
-      cp.je = api_nj;
+      p.jb = 0;
+      p.je = api_nj;
     } else {
-      cp.jb = d.coff[c];
-      cp.je = d.coff[c + 1];
+      p.jb = d.coff[c];
+      p.je = d.coff[c + 1];
     }
-    const int64_t nc = cp.je - cp.jb;
-    cp.t_pred = (kind == kPlanStep || kind == kPlanRefine) ? d.Tnext[c] : d.T[c];
-    cp.P = 256;
-    cp.Qlog = 0;
-    cp.S = 0;
-    cp.tiles = 0;
-    cp.items = 0;
-    cp.chunk = kTJ;
-    cp.row_off = 0;
-    if (cp.na > 0 && nc > 0) {
-      int b = 31 - __builtin_clz((unsigned)cp.na);
+    const int64_t nc = p.je - p.jb;
+    p.t_pred = (kind == kPlanStep || kind == kPlanRefine) ? d.Tnext[c] : d.T[c];
+    if (p.na > 0 && nc > 0) {
+      int b = 31 - __builtin_clz((unsigned)p.na);
       if (b >= kBuckets) b = kBuckets - 1;
       int P = tu.i_slots[b];
       if (P < 1) P = 1;
       if (P > 256) P = 256;
       P = 1 << (31 - __builtin_clz((unsigned)P));      // power of two
-      cp.P = P;
-      cp.Qlog = 8 - (31 - __builtin_clz((unsigned)P));
+      p.P = P;
+      p.Qlog = 8 - (31 - __builtin_clz((unsigned)P));
       const int64_t ipt = (int64_t)P * K;
-      const int64_t tiles = (cp.na + ipt - 1) / ipt;
+      const int64_t tiles = (p.na + ipt - 1) / ipt;
       int64_t target = tu.target_items[b] > 0 ? tu.target_items[b] : 1;
       int64_t S = (target + tiles - 1) / tiles;
       const int64_t mj = tu.min_split_j > 0 ? tu.min_split_j : 64;
@@ -864,86 +916,105 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
       // in an ensemble), and never more than the workspace holds
       int64_t rowcap = 4 * nc;
       if (rowcap > d.rows_cap) rowcap = d.rows_cap;
-      const int64_t s_r = rowcap / cp.na;
+      const int64_t s_r = rowcap / p.na;
       if (S > s_r) S = s_r;
       if (S < 1) S = 1;
       int64_t chunk = (nc + S - 1) / S;
       chunk = ((chunk + kTJ - 1) / kTJ) * kTJ;
       S = (nc + chunk - 1) / chunk;
-      cp.S = (int32_t)S;
-      cp.chunk = chunk;
-      cp.tiles = (int32_t)tiles;
-      cp.items = (int32_t)(tiles * S);
-      my_inter += (int64_t)cp.na * nc;
-      my_active += cp.na;
+      p.S = (int32_t)S;
+      p.chunk = chunk;
+      p.tiles = (int32_t)tiles;
+      p.items = (int32_t)(tiles * S);
+      p.small = (allow_small && kind == kPlanStep && p.na <= kSmallStep) ? 1 : 0;
+      my_inter += (int64_t)p.na * nc;
+      my_active += p.na;
     }
-    if (kind == kPlanStep) {
-      if (d.Tnext[c] < d.ctr[kCtrTend]) ++my_notdone;
-    }
-    d.plan_c[c] = cp;
-    cost[c] = cp.items > 0 ? (int64_t)cp.P * K * cp.chunk : -1;
+    if (kind == kPlanStep && d.Tnext[c] < d.ctr[kCtrTend]) ++my_notdone;
+    // main-kernel clusters first, then small-step ones; within each, largest
+    // item cost first, ties by cluster id (keys are unique)
+    const uint64_t cost = p.items > 0 ? (uint64_t)p.P * K * p.chunk : 0;   // < 2^40
+    key[c] = ((uint64_t)p.small << 63) | ((((uint64_t)1 << 40) - 1 - cost) << 12) |
+             (uint64_t)c;
   }
-  __syncthreads();
-  // row offsets in cluster order
+  // partial-row offsets in cluster order
   int64_t carry = 0;
-  for (int base = 0; base < C; base += 1024) {
-    const int c = base + threadIdx.x;
-    const int64_t r = (c < C) ? (int64_t)d.plan_c[c].S * d.plan_c[c].na : 0;
-    scan64[threadIdx.x] = r;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      const int64_t add = (threadIdx.x >= off) ? scan64[threadIdx.x - off] : 0;
-      __syncthreads();
-      scan64[threadIdx.x] += add;
-      __syncthreads();
-    }
-    if (c < C) d.plan_c[c].row_off = carry + scan64[threadIdx.x] - r;
-    carry += scan64[1023];
-    __syncthreads();
+#pragma unroll
+  for (int q = 0; q < QN; ++q) {
+    if (1024 * q >= C) break;                       // uniform
+    int64_t tot;
+    const int64_t r = (int64_t)cp[q].S * cp[q].na;
+    cp[q].row_off = carry + block_exscan64(r, sh, &tot);
+    carry += tot;
   }
-  // largest item cost first; ties by cluster id
-  for (int c = threadIdx.x; c < C; c += 1024) {
-    const int64_t mc = cost[c];
-    int rank = 0;
-    for (int u = 0; u < C; ++u) {
-      const int64_t o = cost[u];
-      rank += (o > mc) || (o == mc && u < c);
-    }
-    d.plan_lpt[rank] = d.plan_c[c];
+  __syncthreads();                                  // keys complete
+  // rank of each owned cluster in LPT order
+  int rank[QN];
+#pragma unroll
+  for (int q = 0; q < QN; ++q) rank[q] = 0;
+  uint64_t mine[QN];
+#pragma unroll
+  for (int q = 0; q < QN; ++q) mine[q] = (tid + 1024 * q < C) ? key[tid + 1024 * q] : ~0ull;
+  int u = 0;
+  for (; u + 4 <= C; u += 4) {
+    const uint64_t k0 = key[u], k1 = key[u + 1], k2 = key[u + 2], k3 = key[u + 3];
+#pragma unroll
+    for (int q = 0; q < QN; ++q)
+      rank[q] += (k0 < mine[q]) + (k1 < mine[q]) + (k2 < mine[q]) + (k3 < mine[q]);
+  }
+  for (; u < C; ++u) {
+    const uint64_t k0 = key[u];
+#pragma unroll
+    for (int q = 0; q < QN; ++q) rank[q] += (k0 < mine[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < QN; ++q) {
+    const int c = tid + 1024 * q;
+    if (c >= C) continue;
+    d.plan_c[c] = cp[q];
+    d.plan_lpt[rank[q]] = cp[q];
+    items_by_rank[rank[q]] = cp[q].items;
   }
   __syncthreads();
+  // item prefix over the LPT order; the main items come first
   carry = 0;
-  for (int base = 0; base < C; base += 1024) {
-    const int r = base + threadIdx.x;
-    const int64_t it = (r < C) ? d.plan_lpt[r].items : 0;
-    scan64[threadIdx.x] = it;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      const int64_t add = (threadIdx.x >= off) ? scan64[threadIdx.x - off] : 0;
-      __syncthreads();
-      scan64[threadIdx.x] += add;
-      __syncthreads();
-    }
-    if (r < C) d.item_prefix[r] = (int32_t)(carry + scan64[threadIdx.x] - it);
-    carry += scan64[1023];
-    __syncthreads();
+  int64_t big = 0;
+#pragma unroll
+  for (int q = 0; q < QN; ++q) {
+    if (1024 * q >= C) break;
+    const int r = tid + 1024 * q;
+    const int64_t it = (r < C) ? items_by_rank[r] : 0;
+    int64_t tot;
+    const int64_t pre = block_exscan64(it, sh, &tot);
+    if (r < C) d.item_prefix[r] = (int32_t)(carry + pre);
+    carry += tot;
   }
-  if (threadIdx.x == 0) {
+#pragma unroll
+  for (int q = 0; q < QN; ++q)
+    if (tid + 1024 * q < C && !cp[q].small) big += cp[q].items;
+  __shared__ int64_t big_sh;
+  if (tid == 0) big_sh = 0;
+  __syncthreads();
+  if (big) atomicAdd((unsigned long long *)&big_sh, (unsigned long long)big);
+  __syncthreads();
+  if (tid == 0) {
     d.item_prefix[C] = (int32_t)carry;
-    *d.work = 0;
+    d.work[0] = 0;            // item counter of the main kernels
+    d.work[1] = 0;            // item counter of the small-step FP64 kernel
+    d.work[2] = (int32_t)big_sh;   // items [0, big) are main, [big, total) small
   }
   if (kind == kPlanStep) {
-    for (int c = threadIdx.x; c < C; c += 1024) d.T[c] = d.Tnext[c];
+    for (int c = tid; c < C; c += 1024) d.T[c] = d.Tnext[c];
     // block totals (deterministic: integer atomics)
     if (my_inter) atomicAdd((unsigned long long *)&d.ctr[kCtrInter],
                             (unsigned long long)my_inter);
     __shared__ int any_active, notdone;
-    if (threadIdx.x == 0) { any_active = 0; notdone = 0; }
+    if (tid == 0) { any_active = 0; notdone = 0; }
     __syncthreads();
     if (my_active) atomicAdd(&any_active, my_active);
     if (my_notdone) atomicAdd(&notdone, my_notdone);
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       if (any_active) d.ctr[kCtrSteps] += 1;
       d.ctr[kCtrNotDone] = notdone;
     }
@@ -1113,8 +1184,8 @@ __global__ void k_api_finalize(Dev d, int64_t na, double *acc, double *jerk) {
 // fused into the tile fill, which reads each j once.  The decision is taken
 // on the device so that captured block steps adapt to their active sets.
 // *pred_on: 0 = records not built, 1 = built, 2 = built and every cluster
-// with work runs kWG i-slots per workgroup (the broadcast kernel takes the
-// evaluation; only with allow_sb).
+// with work for the main kernels runs kWG i-slots per workgroup (the
+// broadcast kernel takes the evaluation; only with allow_sb).
 template <int MODE>
 __global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, int allow_sb) {
   using Rec = typename Traits<MODE>::Rec;
@@ -1127,7 +1198,7 @@ __global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, in
     if (elig) {
       for (int c = threadIdx.x; c < d.C; c += blockDim.x) {
         const ClusterPlan &p = d.plan_c[c];
-        if (p.na > 0 && p.P != kWG) elig = 0;
+        if (p.na > 0 && !p.small && p.P != kWG) elig = 0;
       }
     }
     elig = __syncthreads_and(elig);
@@ -1264,7 +1335,8 @@ __global__ __launch_bounds__(kWG) void k_force_sb(ForceArgs A) {
   const Dev &d = A.d;
   if (*A.pred_on != 2) return;      // the workgroup kernel takes this evaluation
   const int tid = threadIdx.x;
-  const int n_items = d.item_prefix[d.C];
+  const int n_items = d.work[2];    // the main items
+  if (n_items <= 0) return;
   const Rec *pred = reinterpret_cast<const Rec *>(d.pred);
   const ScalarPtr<Rec> spred = (ScalarPtr<Rec>)d.pred;
   const bool raw = A.rx != nullptr;
@@ -1495,7 +1567,7 @@ __global__ __launch_bounds__(kWG) void k_sum_flag(Dev d, const int32_t *list,
 #pragma unroll
       for (int c = 0; c < 6; ++c) d.fsum[6 * k + c] = f[c];
       int flag = 0;
-      if (ratio > 0.0f) {
+      if (ratio > 0.0f && !cp.small) {     // small-step clusters ran in FP64
         const double an = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
         flag = !(tmax <= (double)ratio * an);
       }
@@ -1794,19 +1866,25 @@ hipError_t launch_compact(const Dev &d, hipStream_t s) {
 }
 
 hipError_t launch_plan(const Dev &d, const Tuning &t, int kind, int64_t api_nj,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, s, d, t, kind, api_nj);
+                       bool allow_small, hipStream_t s) {
+  if (d.C <= 1024)
+    hipLaunchKernelGGL(k_plan<1>, dim3(1), dim3(1024), 0, s, d, t, kind, api_nj,
+                       allow_small ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_plan<kMaxClusters / 1024>, dim3(1), dim3(1024), 0, s, d, t, kind,
+                       api_nj, allow_small ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_force(const Dev &d, int mode, int src, int K,
-                        const RawSrc *raw, const int32_t *list, bool use_pred,
+                        const RawSrc *raw, const int32_t *list, int role,
                         int grid, hipStream_t s) {
   ForceArgs A;
   A.d = d;
   A.active = list;
   A.rx = A.rv = A.rm = nullptr;
-  A.pred_on = use_pred ? d.pred_on : nullptr;
+  A.pred_on = d.pred_on;
+  A.role = role;
   if (src == kSrcRaw) {
     if (!raw) return hipErrorInvalidValue;
     A.rx = raw->x;
@@ -1885,11 +1963,12 @@ hipError_t launch_records(const Dev &d, int mode, int kind, const RawSrc *raw,
   RawSrc r{};
   if (raw) r = *raw;
   const int64_t nj = (kind == kPlanApi && r.n_j > 0) ? r.n_j : d.n;
-  const dim3 g(grid_for(nj, kWG, 4096)), b(kWG);
+  const dim3 g(grid_for(nj, kWG, 1024)), b(kWG);
+  const int sb = allow_sb ? 1 : 0;
   if (mode_mixed(mode))
-    hipLaunchKernelGGL(k_records<kModeMixed>, g, b, 0, s, d, kind, r, allow_sb ? 1 : 0);
+    hipLaunchKernelGGL(k_records<kModeMixed>, g, b, 0, s, d, kind, r, sb);
   else
-    hipLaunchKernelGGL(k_records<kModeFP64>, g, b, 0, s, d, kind, r, allow_sb ? 1 : 0);
+    hipLaunchKernelGGL(k_records<kModeFP64>, g, b, 0, s, d, kind, r, sb);
   return hipGetLastError();
 }
 
@@ -1902,6 +1981,7 @@ hipError_t launch_force_sb(const Dev &d, int mode, int K, const RawSrc *raw,
   A.rv = raw ? raw->v : nullptr;
   A.rm = raw ? raw->m : nullptr;
   A.pred_on = d.pred_on;
+  A.role = kRoleMain;
   const dim3 g(grid), b(kWG);
 #define NB_CASE(M, KK) \
   if (mode == M && K == KK) { hipLaunchKernelGGL((k_force_sb<M, KK>), g, b, 0, s, A); return hipGetLastError(); }
@@ -1956,7 +2036,7 @@ hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_hos
 }
 
 hipError_t launch_refine_finalize(const Dev &d, hipStream_t s) {
-  hipLaunchKernelGGL(k_ref_final, dim3(grid_for(d.cap_active * 64, kWG, 2048)), dim3(kWG),
+  hipLaunchKernelGGL(k_ref_final, dim3(grid_for(d.cap_active * 64, kWG, 512)), dim3(kWG),
                      0, s, d);
   return hipGetLastError();
 }

@@ -226,3 +226,32 @@ def test_mixed_refines_dominated_particles_in_fp64():
     g.sync()
     assert np.median(rel_err(to_np(acc2), a_ref)) <= 1e-7
     assert rel_err(to_np(acc2)[:2], a_ref[:2]).max() > 1e-12
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_more_clusters_than_plan_threads(prec):
+    # more than 1024 clusters: the plan's threads each own several clusters
+    require_gpu()
+    rng = np.random.default_rng(77)
+    sizes = rng.integers(2, 24, 1500).tolist()
+    m, x, v, off = ics.ensemble(1500, sizes=sizes, seed=940)
+    eps = rng.uniform(1e-3, 1e-2, 1500)
+    g = _ctx(m, x, v, list(eps), prec, cluster_offsets=off)
+    acc, jerk = g.forces(x, v, m)
+    g.sync()
+    a, j = to_np(acc), to_np(jerk)
+    worst_a = worst_j = 0.0
+    for c in range(1500):
+        sl = slice(off[c], off[c + 1])
+        a_ref, j_ref = oracle.forces(x[sl], v[sl], m[sl], eps[c])
+        worst_a = max(worst_a, rel_err(a[sl], a_ref).max())
+        worst_j = max(worst_j, rel_err(j[sl], j_ref).max())
+    tol = MIXED_TOL if prec == binding.MIXED else FP64_TOL
+    jtol = MIXED_JERK_MAX if prec == binding.MIXED else FP64_TOL
+    assert worst_a <= tol and worst_j <= jtol, (worst_a, worst_j)
+    # block steps run the plan every step
+    e0 = g.energy()[:, 2]
+    g.step(0.125)
+    e1 = g.energy()[:, 2]
+    assert np.all(np.isfinite(e1))
+    assert np.median(np.abs(e1 - e0) / np.abs(e0)) < 1e-5
