@@ -195,12 +195,14 @@ def sweep(binding, torch, ics, n):
 
 
 def run_blocksteps(binding, torch, label, m, x, v, t_end, precision, cluster_offsets=None,
-                   eps=1e-3, level_min=3, chunks=8):
+                   eps=1e-3, level_min=3, chunks=8, dt_shared=0.0, level_max=20,
+                   oracle_time=False):
     """Hermite-4 block steps to t_end in `chunks` equal calls (the largest
-    step 2^-level_min divides each chunk); progress to stderr per chunk."""
+    step 2^-level_min divides each chunk); progress to stderr per chunk.
+    oracle_time: also run the CPU oracle over the same steps (small N)."""
     g = binding.NBody(m, x, v, eps=eps, precision=precision, eta=0.01, eta_start=0.01,
-                      level_min=level_min, level_max=20, cluster_offsets=cluster_offsets,
-                      tuning="auto")
+                      dt_shared=dt_shared, level_min=level_min, level_max=level_max,
+                      cluster_offsets=cluster_offsets, tuning="auto")
     e0 = g.energy()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -217,12 +219,24 @@ def run_blocksteps(binding, torch, label, m, x, v, t_end, precision, cluster_off
     st = g.stats()
     de = abs(e1[:, 2] - e0[:, 2]) / abs(e0[:, 2])
     lz = abs(e1[:, 5] - e0[:, 5])
+    q_vir = 2 * e1[:, 0] / abs(e1[:, 1])
+    dp = (e1[:, 6:9] - e0[:, 6:9])
     out = {"workload": label, "precision": "mixed" if precision else "fp64", "n": int(m.shape[0]),
            "clusters": int(e0.shape[0]), "t_end": t_end, "block_steps": steps,
            "interactions": inter, "wall_s": wall, "interactions_per_s": inter / wall,
            "dE_over_E_max": float(de.max()), "dE_over_E_median": float(sorted(de)[len(de) // 2]),
-           "dLz_max": float(lz.max()), "floor_clamps": st["floor_clamps"]}
+           "dLz_max": float(lz.max()), "dP_max": float(abs(dp).max()),
+           "virial_Q_median": float(sorted(q_vir)[len(q_vir) // 2]),
+           "floor_clamps": st["floor_clamps"]}
     g.close()
+    if oracle_time:
+        import oracle
+        ref = oracle.System(m, x, v, eps, eta=0.01, eta_start=0.01, dt_shared=dt_shared,
+                            level_min=level_min, level_max=level_max)
+        t0 = time.perf_counter()
+        ref.run(t_end)
+        out["oracle_wall_s"] = time.perf_counter() - t0
+        out["oracle_cores"] = oracle.threads()
     print(json.dumps(out), flush=True)
 
 
@@ -297,6 +311,10 @@ def main():
         symplectic_scaling(binding, torch, ics, not a.no_cpu)
         return
     if a.workload == "blocksteps":
+        m, x, v = ics.plummer(1024, 1)
+        run_blocksteps(binding, torch, "plummer1024-shared", m, x, v, 1.0, binding.FP64,
+                       eps=1e-3, level_min=8, level_max=8, dt_shared=1 / 256, chunks=4,
+                       oracle_time=not a.no_cpu)
         m, x, v = ics.plummer(65536, 2)
         run_blocksteps(binding, torch, "plummer65536", m, x, v, 0.125, binding.FP64, eps=1e-3,
                        level_min=6, chunks=8)

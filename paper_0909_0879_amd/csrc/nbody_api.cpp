@@ -579,38 +579,70 @@ int nbody_step_symplectic(nbody_ctx *c, int scheme, double h, int64_t n_steps,
   }
   const int mode = acc_mode_of(c);
   const nbk::Tuning t = device_tuning(c, c->K);
-  hipStream_t s = c->stream;
-  NB_HIP(nbk::launch_all_active(c->d, s));
-  auto evaluate = [&]() -> int {
+  NB_HIP(nbk::launch_all_active(c->d, c->stream));
+  auto evaluate = [&](hipStream_t s) -> int {
     NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, false, s));
     int r = force_launch(c, mode, nbk::kSrcState, c->K, nullptr, c->d.active, c->grid_acc_state,
                          s, nbk::kPlanState);
     if (r) return r;
     return sum_and_refine(c, c->d.active, -1, nullptr, s, /*acc_only=*/true);
   };
-  // the state's acceleration was taken at predicted positions: evaluate
-  // at the current ones first
-  if ((rc = evaluate())) return rc;
-  double pending = 0.0;
-  bool first = true;
-  int64_t evals = 1;
-  for (int64_t st = 0; st < n_steps; ++st) {
+  // one step: every stage kicks (merging the previous stage's half kick),
+  // drifts and evaluates; returns the half kick still owed
+  auto enqueue_step = [&](hipStream_t s, double pending, bool check, double *owed) -> int {
     for (double wk : w) {
       const double cw = wk * h;
-      NB_HIP(nbk::launch_sym_kick_drift(c->d, pending + 0.5 * cw, cw, first, s));
-      first = false;
-      if ((rc = evaluate())) return rc;
+      NB_HIP(nbk::launch_sym_kick_drift(c->d, pending + 0.5 * cw, cw, check, s));
+      check = false;
+      int r = evaluate(s);
+      if (r) return r;
       pending = 0.5 * cw;
-      ++evals;
     }
-    // bound the host's lead over the device on long runs
-    if ((st & 63) == 63) {
-      if ((rc = readback(c))) return rc;
-      if ((rc = take_error(c))) return rc;
+    *owed = pending;
+    return NBODY_OK;
+  };
+  // the state's acceleration was taken at predicted positions: evaluate
+  // at the current ones first
+  if ((rc = evaluate(c->stream))) return rc;
+  double pending = 0.0;
+  if ((rc = enqueue_step(c->stream, 0.0, true, &pending))) return rc;
+  const int64_t evals = 1 + n_steps * (int64_t)w.size();
+  // the remaining steps are identical: capture one as a HIP graph and
+  // replay it (eager launches when profiling, or for a few steps)
+  const int64_t rest = n_steps - 1;
+  if (rest >= 4 && !c->profiling) {
+    NB_HIP(hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+    double owed = 0.0;
+    rc = enqueue_step(c->cap, pending, false, &owed);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap, &g);
+    if (rc != NBODY_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc ? rc : fail(NBODY_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    hipGraphExec_t ge = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess)
+      return fail(NBODY_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    for (int64_t st = 0; st < rest && rc == NBODY_OK; ++st) {
+      const hipError_t el = hipGraphLaunch(ge, c->stream);
+      if (el != hipSuccess) rc = fail(NBODY_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(el));
+      // bound the host's lead over the device on long runs
+      if (rc == NBODY_OK && (st & 63) == 63) rc = readback(c);
+    }
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipGraphExecDestroy(ge);
+    if (rc) return rc;
+    pending = owed;
+  } else {
+    for (int64_t st = 0; st < rest; ++st) {
+      if ((rc = enqueue_step(c->stream, pending, false, &pending))) return rc;
+      if ((st & 63) == 63 && (rc = readback(c))) return rc;
     }
   }
-  NB_HIP(nbk::launch_sym_kick(c->d, pending, s));
-  NB_HIP(nbk::launch_sym_advance(c->d, span, s));
+  NB_HIP(nbk::launch_sym_kick(c->d, pending, c->stream));
+  NB_HIP(nbk::launch_sym_advance(c->d, span, c->stream));
   for (int k = 0; k < c->C; ++k) c->T_host[k] += span;
   // leave a consistent Hermite state: a, jerk and levels at the new positions
   if ((rc = full_evaluation_into_state(c))) return rc;

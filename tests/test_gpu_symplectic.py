@@ -175,3 +175,20 @@ def test_symplectic_rejects_bad_arguments():
     with pytest.raises(binding.NBodyError) as e:
         g.step_symplectic(binding.LEAPFROG, 1 / 64, 4)
     assert e.value.code == binding.EINVAL
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_symplectic_graph_replay_equals_eager_bitwise(prec):
+    # steps after the first replay one captured graph; with profiling on
+    # every launch is eager: both must give the same bits
+    require_gpu()
+    m, x, v = ics.plummer(700, 6)
+    out = []
+    for profile in (False, True):
+        g = binding.NBody(m, x, v, eps=1e-3, precision=prec, level_min=4, level_max=20)
+        g.profile(profile)
+        g.step_symplectic(binding.SYMPLECTIC6, 1 / 256, 16)
+        out.append({k: to_np(t) for k, t in g.get_state().items()})
+        g.close()
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
