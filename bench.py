@@ -233,10 +233,12 @@ def run_blocksteps(binding, torch, label, m, x, v, t_end, precision, cluster_off
         import oracle
         ref = oracle.System(m, x, v, eps, eta=0.01, eta_start=0.01, dt_shared=dt_shared,
                             level_min=level_min, level_max=level_max)
+        e_ref0 = oracle.energy(x, v, m, eps)["E"]
         t0 = time.perf_counter()
         ref.run(t_end)
         out["oracle_wall_s"] = time.perf_counter() - t0
         out["oracle_cores"] = oracle.threads()
+        out["oracle_dE_over_E"] = abs(oracle.energy(ref.x, ref.v, m, eps)["E"] - e_ref0) / abs(e_ref0)
     print(json.dumps(out), flush=True)
 
 

@@ -1488,9 +1488,9 @@ __device__ __forceinline__ void neu_add(double &s, double &c, double x) {
 // Wave-wide sum of NC compensated pairs over the 64 lanes (xor tree, same
 // order on every run); every lane ends with the total.
 template <int NC>
-__device__ __forceinline__ void wave_neu_reduce(double (&s)[NC], double (&c)[NC]) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
+__device__ __forceinline__ void wave_neu_reduce(double (&s)[NC], double (&c)[NC],
+                                                int top = 32) {
+  for (int off = top; off >= 1; off >>= 1) {
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
       const double os = __shfl_xor(s[q], off), oc = __shfl_xor(c[q], off);
@@ -1523,9 +1523,12 @@ __device__ __forceinline__ void wave_sum_rows(const Dev &d, const ClusterPlan &c
     tm = fmax(tm, row[6]);
   }
   if (cp.S > 1) {
-    wave_neu_reduce<6>(s, c);
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) tm = fmax(tm, __shfl_xor(tm, off));
+    // lanes >= S hold exact zeros, so the butterfly rounds that would only
+    // add them can be skipped without changing a bit of the result
+    int top = 32;
+    while (top > 1 && top >= cp.S) top >>= 1;
+    wave_neu_reduce<6>(s, c, top);
+    for (int off = top; off >= 1; off >>= 1) tm = fmax(tm, __shfl_xor(tm, off));
   }
 #pragma unroll
   for (int q = 0; q < 6; ++q) out[q] = s[q] + c[q];
