@@ -196,6 +196,7 @@ struct nbody_ctx {
   int grid_state = 0, grid_raw = 0, grid_pot = 0, grid_sb = 0;
   int grid_ref_state = 0, grid_ref_raw = 0;   // FP64 K = 1 re-evaluation
   int grid_small = 0;             // FP64, the context's K: small mixed block steps
+  int grid_rec = 0, grid_acc_rec = 0;   // record-only kernels
   // acceleration-only kernels (symplectic drivers, nbody_accel)
   int grid_acc_state = 0, grid_acc_raw = 0, grid_acc_sb = 0;
   int grid_ref_acc_state = 0, grid_ref_acc_raw = 0;
@@ -257,8 +258,11 @@ int refresh_grids(nbody_ctx *c) {
   c->grid_ref_state = nbk::force_grid_size(nbk::kModeFP64, nbk::kSrcState, 1, c->device);
   c->grid_ref_raw = nbk::force_grid_size(nbk::kModeFP64, nbk::kSrcRaw, 1, c->device);
   c->grid_small = nbk::force_grid_size(nbk::kModeFP64, nbk::kSrcState, c->K, c->device);
+  c->grid_rec = nbk::force_grid_size(mode_of(c), nbk::kSrcRec, c->K, c->device);
+  c->grid_acc_rec = nbk::force_grid_size(acc_mode_of(c), nbk::kSrcRec, c->K, c->device);
   if (c->grid_state < 1 || c->grid_raw < 1 || c->grid_pot < 1 || c->grid_ref_state < 1 ||
-      c->grid_ref_raw < 1 || c->grid_small < 1 || c->grid_sb < 1 || c->grid_acc_sb < 1 || c->grid_acc_state < 1 ||
+      c->grid_ref_raw < 1 || c->grid_small < 1 || c->grid_rec < 1 || c->grid_acc_rec < 1 ||
+      c->grid_sb < 1 || c->grid_acc_sb < 1 || c->grid_acc_state < 1 ||
       c->grid_acc_raw < 1 || c->grid_ref_acc_state < 1 || c->grid_ref_acc_raw < 1)
     return fail(NBODY_EHIP, "could not size the force kernel grid");
   return NBODY_OK;
@@ -275,14 +279,20 @@ int force_launch(nbody_ctx *c, int mode, int src, int K, const nbk::RawSrc *raw,
   const bool use_pred = rec_kind >= 0;
   // clusters of a mixed block step with few active particles run in FP64
   const bool small = rec_kind == nbk::kPlanStep && mode == nbk::kModeMixed;
-  if (use_pred) NB_HIP(nbk::launch_records(c->d, mode, rec_kind, raw, c->sb, s));
+  // evaluations whose records are always built (mixed block steps beyond
+  // the small ones, whole-state evaluations) use the record-only kernel
+  const bool rec_only = small || rec_kind == nbk::kPlanState;
+  if (use_pred) NB_HIP(nbk::launch_records(c->d, mode, rec_kind, raw, c->sb, rec_only, s));
   if (prof && c->ev_used == kEvPairs) {
     int rc = harvest_events(c);
     if (rc) return rc;
   }
   if (prof) NB_HIP(hipEventRecord(c->ev[2 * c->ev_used], s));
-  NB_HIP(nbk::launch_force(c->d, mode, src, K, raw, list,
-                            use_pred ? nbk::kRoleMain : nbk::kRoleAlways, grid, s));
+  NB_HIP(nbk::launch_force(c->d, mode, rec_only ? nbk::kSrcRec : src, K, raw, list,
+                            use_pred ? nbk::kRoleMain : nbk::kRoleAlways,
+                            rec_only ? (nbk::mode_acc_only(mode) ? c->grid_acc_rec : c->grid_rec)
+                                     : grid,
+                            s));
   if (use_pred && c->sb)
     NB_HIP(nbk::launch_force_sb(c->d, mode, K, raw, list,
                                 nbk::mode_acc_only(mode) ? c->grid_acc_sb : c->grid_sb, s));

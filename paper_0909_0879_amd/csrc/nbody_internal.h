@@ -121,8 +121,10 @@ struct Dev {
   double *eout;        // C * 9 energy output
 };
 
-// Where the force kernel takes j (and i) particles from.
-enum Source : int { kSrcState = 0, kSrcRaw = 1 };
+// Where the force kernel takes j (and i) particles from: the state
+// (predicted while the tile is filled, or the records when built), the
+// caller's arrays, or only the records (launches that always have them).
+enum Source : int { kSrcState = 0, kSrcRaw = 1, kSrcRec = 2 };
 // What the force kernel computes: acceleration and jerk, the potential, or
 // the acceleration alone (the symplectic drivers and nbody_accel).
 enum Mode : int {
@@ -179,7 +181,7 @@ hipError_t launch_force(const Dev &d, int mode, int src, int K,
 // with work for the main kernels).
 // kind: kPlanStep (predict to T_next), kPlanState (to T), kPlanApi (raw).
 hipError_t launch_records(const Dev &d, int mode, int kind, const RawSrc *raw,
-                          bool allow_sb, hipStream_t s);
+                          bool allow_sb, bool always, hipStream_t s);
 // The broadcast force kernel (j records in scalar registers); it does the
 // evaluation only when *d.pred_on == 2 and returns at once otherwise.
 hipError_t launch_force_sb(const Dev &d, int mode, int K, const RawSrc *raw,

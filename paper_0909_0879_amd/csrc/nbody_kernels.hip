@@ -404,8 +404,17 @@ __device__ __forceinline__ void rec_to_i(const JRecDS &r, IDS &s) {
 
 // ------------------------------------------------------------ force kernel
 
+// Waves per SIMD to aim for: the record-only mixed kernel with one i per
+// lane fits five waves (95 VGPRs, a few spills outside the j loop) and runs
+// ~4 % faster than at four (measured at N = 2^20); the others keep the
+// compiler's choice (1 = no minimum).
+template <int MODE, int SRC, int K> struct ForceOcc {
+  static constexpr int waves = (MODE == kModeMixed && SRC == kSrcRec && K == 1) ? 5 : 1;
+};
+
 template <int MODE, int SRC, int K>
-__global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
+__global__ __launch_bounds__(kWG)
+__attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force(ForceArgs A) {
   using Tr = Traits<MODE>;
   using T = typename Tr::T;
   using Rec = typename Tr::Rec;
@@ -420,12 +429,19 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
   // small-step FP64 launch (clusters of a mixed block step with few active
   // particles); records built once for this evaluation (large active sets)
   // or built here while the tile is filled (small active sets, other calls)
+  // SRC == kSrcRec: the caller guarantees records (flag 1 or 2) and the
+  // kernel carries no prediction or raw-load code (fewer registers)
+  constexpr bool REC = SRC == kSrcRec;
   int pred_flag = 0;
   int item_base = 0, n_items = d.work[2];
   int32_t *counter = d.work;
   if (A.role == kRoleMain) {
     pred_flag = *A.pred_on;
     if (pred_flag == 2) return;     // the broadcast kernel takes these items
+    if (REC && pred_flag != 1) {    // no records: a launch-order bug
+      if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(d.err, (int)kErrState);
+      return;
+    }
   } else if (A.role == kRoleSmall) {
     item_base = d.work[2];
     n_items = d.item_prefix[d.C];
@@ -434,7 +450,7 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
   // a launch with no items leaves before touching the shared counter (the
   // whole grid queueing on one atomic costs more than the launch itself)
   if (n_items <= item_base) return;
-  const bool use_pred = pred_flag == 1;
+  const bool use_pred = REC || pred_flag == 1;
   const Rec *pred = reinterpret_cast<const Rec *>(d.pred);
   for (;;) {
     if (tid == 0) s_g = item_base + atomicAdd(counter, 1);
@@ -478,9 +494,9 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
       } else if (use_pred) {
         rec_to_i(pred[iidx[k]], I[k]);
         continue;
-      } else if (SRC == kSrcState) {
+      } else if constexpr (SRC == kSrcState) {
         predict_state(d, iidx[k], cp.t_pred, xp, vp);
-      } else {
+      } else if constexpr (SRC == kSrcRaw) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           xp[c] = A.rx[3 * (int64_t)iidx[k] + c];
@@ -503,10 +519,10 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs A) {
       const int cnt = (int)((je - jt < kTJ) ? je - jt : kTJ);
       if (tid < cnt && use_pred) {
         tile[tid] = pred[jt + tid];
-      } else if (tid < cnt) {
+      } else if (!REC && tid < cnt) {
         const int64_t j = jt + tid;
         double xp[3], vp[3], m;
-        if (SRC == kSrcState) {
+        if constexpr (SRC == kSrcState) {
           predict_state(d, j, cp.t_pred, xp, vp);
           m = d.m[j];
         } else {
@@ -1186,13 +1202,17 @@ __global__ void k_api_finalize(Dev d, int64_t na, double *acc, double *jerk) {
 // *pred_on: 0 = records not built, 1 = built, 2 = built and every cluster
 // with work for the main kernels runs kWG i-slots per workgroup (the
 // broadcast kernel takes the evaluation; only with allow_sb).
+// always: build whatever the active count (the caller launches the
+// record-only kernel); particles of small-step clusters are skipped.
 template <int MODE>
-__global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, int allow_sb) {
+__global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, int allow_sb,
+                                                 int always) {
   using Rec = typename Traits<MODE>::Rec;
   const bool api = kind == kPlanApi;
   const int64_t nj = (api && raw.n_j > 0) ? raw.n_j : d.n;
   const int64_t total = api ? raw.n_active : (int64_t)d.act_off[d.C];
-  const bool on = total * 16 >= nj && nj <= d.n;     // the buffer holds d.n records
+  // the buffer holds d.n records
+  const bool on = (always || total * 16 >= nj) && nj <= d.n;
   if (blockIdx.x == 0) {
     int elig = (on && allow_sb) ? 1 : 0;
     if (elig) {
@@ -1218,7 +1238,8 @@ __global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, in
       m = raw.m[i];
     } else {
       const int c = d.cid[i];
-      if (kind == kPlanStep && d.Lthr[c] == kNoActive) continue;   // not stepping
+      if (kind == kPlanStep && (d.Lthr[c] == kNoActive || d.plan_c[c].small))
+        continue;                   // not stepping, or evaluated by the FP64 launch
       predict_state(d, i, kind == kPlanStep ? d.Tnext[c] : d.T[c], xp, vp);
       m = d.m[i];
     }
@@ -1913,6 +1934,14 @@ hipError_t launch_force(const Dev &d, int mode, int src, int K,
   NB_CASE(kModeMixedAcc, kSrcState, 2)
   NB_CASE(kModeMixedAcc, kSrcRaw, 1)
   NB_CASE(kModeMixedAcc, kSrcRaw, 2)
+  NB_CASE(kModeFP64, kSrcRec, 1)
+  NB_CASE(kModeFP64, kSrcRec, 2)
+  NB_CASE(kModeMixed, kSrcRec, 1)
+  NB_CASE(kModeMixed, kSrcRec, 2)
+  NB_CASE(kModeFP64Acc, kSrcRec, 1)
+  NB_CASE(kModeFP64Acc, kSrcRec, 2)
+  NB_CASE(kModeMixedAcc, kSrcRec, 1)
+  NB_CASE(kModeMixedAcc, kSrcRec, 2)
   NB_CASE(kModePot, kSrcState, 1)
 #undef NB_CASE
   return hipErrorInvalidValue;
@@ -1937,6 +1966,14 @@ int force_grid_size(int mode, int src, int K, int device) {
   NB_CASE(kModeMixedAcc, kSrcState, 2)
   NB_CASE(kModeMixedAcc, kSrcRaw, 1)
   NB_CASE(kModeMixedAcc, kSrcRaw, 2)
+  NB_CASE(kModeFP64, kSrcRec, 1)
+  NB_CASE(kModeFP64, kSrcRec, 2)
+  NB_CASE(kModeMixed, kSrcRec, 1)
+  NB_CASE(kModeMixed, kSrcRec, 2)
+  NB_CASE(kModeFP64Acc, kSrcRec, 1)
+  NB_CASE(kModeFP64Acc, kSrcRec, 2)
+  NB_CASE(kModeMixedAcc, kSrcRec, 1)
+  NB_CASE(kModeMixedAcc, kSrcRec, 2)
   NB_CASE(kModePot, kSrcState, 1)
 #undef NB_CASE
   return 0;
@@ -1962,16 +1999,16 @@ hipError_t launch_sym_advance(const Dev &d, int64_t dticks, hipStream_t s) {
 }
 
 hipError_t launch_records(const Dev &d, int mode, int kind, const RawSrc *raw,
-                          bool allow_sb, hipStream_t s) {
+                          bool allow_sb, bool always, hipStream_t s) {
   RawSrc r{};
   if (raw) r = *raw;
   const int64_t nj = (kind == kPlanApi && r.n_j > 0) ? r.n_j : d.n;
   const dim3 g(grid_for(nj, kWG, 1024)), b(kWG);
-  const int sb = allow_sb ? 1 : 0;
+  const int sb = allow_sb ? 1 : 0, al = always ? 1 : 0;
   if (mode_mixed(mode))
-    hipLaunchKernelGGL(k_records<kModeMixed>, g, b, 0, s, d, kind, r, sb);
+    hipLaunchKernelGGL(k_records<kModeMixed>, g, b, 0, s, d, kind, r, sb, al);
   else
-    hipLaunchKernelGGL(k_records<kModeFP64>, g, b, 0, s, d, kind, r, sb);
+    hipLaunchKernelGGL(k_records<kModeFP64>, g, b, 0, s, d, kind, r, sb, al);
   return hipGetLastError();
 }
 
