@@ -354,7 +354,7 @@ def main():
                    "n": n, "interactions_per_step": n * n},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": measured_traffic(), "kernel": "k_force<mixed,state,K>",
+                     "traffic": measured_traffic(), "kernel": "k_force<mixed,records,K=1> (LDS-staged j records)",
                      "kernel_ms": mixed["kernel_ms"],
                      "flops_per_launch": per_launch_flops},
         "fp64_reevaluation": {"ms_per_step": mixed["refine_ms_per_step"],
