@@ -123,6 +123,11 @@ def test_null_context_calls():
     assert lib.nbody_step(None, 1.0, None, None) == binding.EINVAL
     assert lib.nbody_energy(None, fake) == binding.EINVAL
     assert lib.nbody_sync(None) == binding.EINVAL
+    assert lib.nbody_accel(None, fake, 1, fake, fake, 1, fake) == binding.EINVAL
+    assert lib.nbody_step_symplectic(None, binding.LEAPFROG, 1 / 64, 4, None) == binding.EINVAL
+    assert lib.nbody_step_blocks(None, 1.0, 1, None, None) == binding.EINVAL
+    assert lib.nbody_get_state(None, fake, fake, fake, fake, fake, fake) == binding.EINVAL
+    assert lib.nbody_set_state(None, fake, fake, fake, fake, fake, fake) == binding.EINVAL
     lib.nbody_destroy(None)
 
 
