@@ -548,7 +548,7 @@ int nbody_init(nbody_ctx **out, const nbody_params *p, int64_t n, const double *
 
 int nbody_forces(nbody_ctx *c, const int32_t *i_active, int64_t n_active, const double *xj,
                  const double *vj, const double *mj, int64_t n_j, double *acc, double *jerk) {
-  if (!vj || !jerk) return fail(NBODY_EINVAL, "NULL array argument");
+  if (c && n_active > 0 && (!vj || !jerk)) return fail(NBODY_EINVAL, "NULL array argument");
   return api_forces(c, false, i_active, n_active, xj, vj, mj, n_j, acc, jerk);
 }
 

@@ -230,18 +230,19 @@ def test_mixed_refines_dominated_particles_in_fp64():
 
 @pytest.mark.parametrize("prec", PRECS)
 def test_more_clusters_than_plan_threads(prec):
-    # more than 1024 clusters: the plan's threads each own several clusters
+    # 4096 clusters (the maximum): the plan's threads each own four clusters
     require_gpu()
     rng = np.random.default_rng(77)
-    sizes = rng.integers(2, 24, 1500).tolist()
-    m, x, v, off = ics.ensemble(1500, sizes=sizes, seed=940)
-    eps = rng.uniform(1e-3, 1e-2, 1500)
+    nc = 4096                      # the largest cluster count a context takes
+    sizes = rng.integers(2, 12, nc).tolist()
+    m, x, v, off = ics.ensemble(nc, sizes=sizes, seed=940)
+    eps = rng.uniform(1e-3, 1e-2, nc)
     g = _ctx(m, x, v, list(eps), prec, cluster_offsets=off)
     acc, jerk = g.forces(x, v, m)
     g.sync()
     a, j = to_np(acc), to_np(jerk)
     worst_a = worst_j = 0.0
-    for c in range(1500):
+    for c in range(nc):
         sl = slice(off[c], off[c + 1])
         a_ref, j_ref = oracle.forces(x[sl], v[sl], m[sl], eps[c])
         worst_a = max(worst_a, rel_err(a[sl], a_ref).max())
@@ -255,3 +256,31 @@ def test_more_clusters_than_plan_threads(prec):
     e1 = g.energy()[:, 2]
     assert np.all(np.isfinite(e1))
     assert np.median(np.abs(e1 - e0) / np.abs(e0)) < 1e-5
+
+
+def test_empty_active_set_is_a_no_op():
+    require_gpu()
+    m, x, v = ics.plummer(64, 41)
+    g = _ctx(m, x, v, 1e-3, binding.MIXED)
+    acc, jerk = g.forces(x, v, m, i_active=np.zeros(0, np.int32))
+    g.sync()
+    assert acc.shape == (0, 3) and jerk.shape == (0, 3)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_massless_tracers(prec):
+    # zero-mass particles feel the field and exert none
+    require_gpu()
+    m, x, v = ics.plummer(1500, 42)
+    m = m.copy()
+    m[::3] = 0.0
+    g = _ctx(m, x, v, 1e-3, prec)
+    acc, jerk = g.forces(x, v, m)
+    g.sync()
+    a_ref, j_ref = oracle.forces(x, v, m, 1e-3)
+    check_parity(to_np(acc), to_np(jerk), a_ref, j_ref, prec == binding.MIXED, "tracers")
+    # the massive particles' forces do not depend on the tracers at all
+    heavy = np.nonzero(m > 0)[0]
+    a_h, j_h = oracle.forces(x[heavy], v[heavy], m[heavy], 1e-3)
+    check_parity(to_np(acc)[heavy], to_np(jerk)[heavy], a_h, j_h, prec == binding.MIXED,
+                 "tracers removed")

@@ -26,7 +26,11 @@ def test_full_size_sampled(king, prec):
     require_gpu()
     m, x, v = king
     print(f"full size prec={prec}", flush=True)
-    g = binding.NBody(m, x, v, eps=EPS, precision=prec, level_min=LEVEL, level_max=LEVEL)
+    # the benchmark's configuration: autotuned launch shapes (applied after
+    # the initial evaluation), one block step per launch
+    g = binding.NBody(m, x, v, eps=EPS, precision=prec, level_min=LEVEL, level_max=LEVEL,
+                      tuning="auto")
+    g.set_tuning({"steps_per_launch": 1})
     rng = np.random.default_rng(44)
     idx = np.sort(rng.choice(N, 2048, replace=False)).astype(np.int64)
     # the initial full evaluation (state source, all active)
