@@ -159,10 +159,29 @@ def cpu_baseline(m, x, v, seconds):
         if dt >= seconds or k >= n:
             break
         k = min(n, max(2 * k, int(k * seconds / max(dt, 1e-3))))
-    return {"value": k * n / dt, "unit": "interactions/s", "cores": oracle.threads(),
+    cores = oracle.threads()
+    # the single-thread rate on a smaller sample (the paper's serial version)
+    k1 = max(16, k // (4 * cores))
+    idx1 = np.sort(rng.choice(n, k1, replace=False)).astype(np.int64)
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.forces(x, v, m, EPS, idx=idx1)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(cores)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": k * n / dt, "unit": "interactions/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{k} random i x {n} j of the same King W0=7 evaluation (FP64, "
-                      f"compensated sums), {dt:.1f} s"}
+                      f"compensated sums), {dt:.1f} s",
+            "single_thread": k1 * n / dt1, "cpu_model": model}
 
 
 def sweep(binding, torch, ics, n):

@@ -61,6 +61,8 @@ def lib():
         L.oracle_init.argtypes = [C.c_int64, P, P, P, P, P, P, P, P, P]
         L.oracle_run.argtypes = [C.c_int64, P, P, P, P, P, P, P, P, C.c_int64, C.c_int64, P]
         L.oracle_threads.argtypes = []
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_set_threads.restype = None
         L.oracle_symplectic_weights.argtypes = [C.c_int, P]
         L.oracle_symplectic.argtypes = [C.c_int64, P, P, P, C.c_double, C.c_double, C.c_int64,
                                         C.c_int]
@@ -229,3 +231,8 @@ class System:
 
 def threads() -> int:
     return lib().oracle_threads()
+
+
+def set_threads(n: int):
+    """Threads for later oracle calls (results do not depend on it)."""
+    lib().oracle_set_threads(int(n))

@@ -503,6 +503,17 @@ int oracle_symplectic(int64_t n, const double *m, double *x, double *v,
   return err;
 }
 
+/* Set the number of OpenMP threads for later calls (no effect without
+ * OpenMP); results do not depend on it. */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* Number of OpenMP threads the oracle uses (1 when built without OpenMP). */
 int oracle_threads(void) {
 #ifdef _OPENMP
