@@ -306,6 +306,37 @@ def symplectic_scaling(binding, torch, ics, with_cpu):
                               "interactions_per_s": n * n / dt}), flush=True)
 
 
+def ensemble_vs_solo(binding, torch, m, x, v, off, k):
+    """The first k clusters of the ensemble to t = 1/4: once as one batched
+    context (one persistent kernel and graph per block step for all of
+    them), once as k separate contexts run one after another."""
+    sizes = off[1:k + 1] - off[:k]
+    sub_off = off[:k + 1] - off[0]
+    sl = slice(0, int(off[k]))
+    kw = dict(eps=1e-3, precision=binding.MIXED, eta=0.01, eta_start=0.01, level_min=5,
+              level_max=20, tuning="auto")
+    g = binding.NBody(m[sl], x[sl], v[sl], cluster_offsets=sub_off, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(0.25)
+    torch.cuda.synchronize()
+    batched = time.perf_counter() - t0
+    g.close()
+    solo = 0.0
+    for c in range(k):
+        cs = slice(int(off[c]), int(off[c + 1]))
+        g = binding.NBody(m[cs], x[cs], v[cs], **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(0.25)
+        torch.cuda.synchronize()
+        solo += time.perf_counter() - t0
+        g.close()
+    print(json.dumps({"workload": "ensemble-vs-solo", "clusters": k,
+                      "n": int(sizes.sum()), "batched_wall_s": batched,
+                      "solo_wall_s": solo, "speedup": solo / batched}), flush=True)
+
+
 def main():
     a = parse()
     if a.calibrate_copy:
@@ -327,6 +358,7 @@ def main():
         m, x, v, off = ics.ensemble(256, 256, 16384, seed=5000)
         run_blocksteps(binding, torch, "ensemble", m, x, v, 0.25, binding.MIXED,
                        cluster_offsets=off, eps=1e-3, level_min=5, chunks=8)
+        ensemble_vs_solo(binding, torch, m, x, v, off, 32)
         return
     if a.workload == "symplectic":
         symplectic_scaling(binding, torch, ics, not a.no_cpu)
