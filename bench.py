@@ -57,14 +57,26 @@ def parse():
     return ap.parse_args()
 
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_0909_0879_amd", "csrc", "nbody_kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0909_0879_amd", "csrc", f)
+                  for f in ("nbody_kernels.hip", "nbody_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_force_mixed_king1M.json")
 
 
 def kernel_hash() -> str:
+    """sha256 of the device code (the kernel source and the header it
+    shares with the runtime) with comments and blank space removed, so that
+    a comment edit does not retire the counter files but any code change
+    does."""
     import hashlib
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    import re
+    code = ""
+    for path in KERNEL_SOURCES:
+        with open(path) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        code += " ".join(src.split()) + "\n"
+    return hashlib.sha256(code.encode()).hexdigest()
 
 
 def measured_traffic():

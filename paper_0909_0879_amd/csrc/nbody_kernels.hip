@@ -11,24 +11,31 @@
 // criterion.
 //
 // Kernel layout on CDNA4:
-//  * the force kernel is persistent: each 256-thread workgroup pulls work
+//  * the force kernels are persistent: each 256-thread workgroup pulls work
 //    items (cluster, i-tile, j-split) from an atomic counter; items are
 //    ordered largest cost first (k_plan), so uneven clusters balance;
-//  * i-particles sit in registers, K per thread slot; j-particles are
-//    predicted while being copied, coalesced, from the SoA state in HBM into
-//    a 256-record LDS tile and are read back as broadcasts;
+//  * i-particles sit in registers, K per thread slot; j-particles reach the
+//    ALUs either through a 256-record LDS tile (k_force) — predicted while
+//    being copied from the SoA state for small active sets, or copied from
+//    records that k_records predicts once per evaluation for large ones —
+//    or, for large evaluations with full-width i-tiles, straight from the
+//    records through the scalar cache into SGPRs (k_force_sb);
 //  * FP32 arithmetic dual-issues on gfx950 while FP64 does not, so the mixed
 //    path keeps every per-pair operation in FP32: the FP64 predicted
 //    positions are stored as double-single (hi, lo) FP32 pairs and x_j - x_i
-//    is formed as (hi_j - hi_i) + (lo_j - lo_i);
+//    is formed as (hi_j - hi_i) + (lo_j - lo_i); particles dominated by one
+//    term are re-evaluated by the FP64 kernel, and mixed block steps with
+//    few active particles run in FP64 outright;
 //  * small active sets put several lanes on one i (P i-slots x Q j-lanes,
 //    P * Q = 256) and split j over workgroups; lanes are reduced with
-//    wavefront shuffles in a fixed tree and splits by the corrector in a
-//    fixed order, so every result is deterministic;
+//    wavefront shuffles in a fixed tree and splits by k_sum_flag in a fixed
+//    order, so every result is deterministic;
 //  * FP64 mode accumulates each tile in FP64 and folds it into a TwoSum
 //    (hi, lo) pair; mixed mode does rsqrt, r^-3 and the jerk products in
 //    FP32 and folds the FP32 sums of every 64 j into an FP32 TwoSum
-//    (hi, lo) pair.
+//    (hi, lo) pair;
+//  * the same kernels in acceleration-only modes serve the paper's
+//    symplectic drivers (kick / drift sweeps between evaluations).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
