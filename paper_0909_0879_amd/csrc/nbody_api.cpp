@@ -354,7 +354,6 @@ int sum_and_refine(nbody_ctx *c, const int32_t *list, int64_t na_host, const nbk
 // One Hermite block step for every cluster, enqueued on s.
 int enqueue_block_step(nbody_ctx *c, hipStream_t s) {
   const nbk::Tuning t = device_tuning(c, c->K);
-  NB_HIP(nbk::launch_sched(c->d, s));
   NB_HIP(nbk::launch_compact(c->d, s));
   NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanStep, 0, c->prec == NBODY_MIXED, s));
   int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->d.active,

@@ -15,6 +15,8 @@ constexpr int kTickBits = 20;       // one time unit = 2^20 ticks
 constexpr int kLevels = 21;         // levels 0..20, step 2^-level
 constexpr int kMaxClusters = 4096;
 constexpr int kScanBlock = 1024;    // particles per block of the compaction
+constexpr int kFusedScan = 1024;    // compaction grids up to this many blocks
+                                    // (N <= 2^20) skip the separate scan
 constexpr int kBuckets = 25;        // tuning buckets floor(log2(n_active))
 constexpr int kNoActive = 99;       // threshold level meaning "nothing due"
 constexpr int kSmallStep = 256;     // mixed block steps up to this many active
@@ -151,7 +153,8 @@ struct RawSrc {                 // caller arrays for nbody_forces
 hipError_t launch_init_state(const Dev &d, const double *m, const double *x,
                              const double *v, hipStream_t s);
 hipError_t launch_all_active(const Dev &d, hipStream_t s);
-hipError_t launch_sched(const Dev &d, hipStream_t s);
+// Scheduler (per-cluster T_next and threshold level) and ordered compaction
+// of the due particles into the active list.
 hipError_t launch_compact(const Dev &d, hipStream_t s);
 // allow_small: clusters of a block step with at most kSmallStep active
 // particles are planned for the small-step FP64 launch (mixed contexts).

@@ -744,45 +744,70 @@ __global__ void k_all_active(Dev d) {
   if (gt <= d.C) d.act_off[gt] = (int32_t)d.coff[gt];
 }
 
-// Per cluster: T_next = next multiple of the finest present step after T,
-// threshold level L = 20 - ctz(T_next) (particles on levels >= L are due).
-__global__ void k_sched(Dev d) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= d.C) return;
+// Next block-step time and threshold level of cluster c: T_next is the next
+// multiple of the finest present step after T; with power-of-two steps and
+// commensurate times, the particles due at T_next are exactly those with
+// level >= L = 20 - ctz(T_next).  Clusters at t_end (or after an error) get
+// L = kNoActive.
+__device__ __forceinline__ void cluster_threshold(const Dev &d, int c, int64_t tend, int err,
+                                                  int64_t *tn_out, int *L_out) {
   const int64_t T = d.T[c];
-  const int64_t tend = d.ctr[kCtrTend];
-  if (T >= tend || *d.err != 0) {
-    d.Tnext[c] = T;
-    d.Lthr[c] = kNoActive;
-    return;
-  }
+  *tn_out = T;
+  *L_out = kNoActive;
+  if (T >= tend || err != 0) return;
   int lmax = -1;
   for (int l = kLevels - 1; l >= 0; --l)
     if (d.hist[c * kLevels + l] > 0) { lmax = l; break; }
-  if (lmax < 0) {
-    d.Tnext[c] = T;
-    d.Lthr[c] = kNoActive;
-    return;
-  }
+  if (lmax < 0) return;
   const int64_t dtl = (int64_t)1 << (kTickBits - lmax);
   const int64_t tn = (T / dtl + 1) * dtl;
   int L = kTickBits - __builtin_ctzll((unsigned long long)tn);
   if (L < 0) L = 0;
-  d.Tnext[c] = tn;
-  d.Lthr[c] = L;
+  *tn_out = tn;
+  *L_out = L;
 }
 
+// Scheduler and count in one pass: each block of kScanBlock particles
+// computes the threshold of the (at most kScanBlock) clusters its particles
+// belong to, the block holding a cluster's first particle publishes that
+// cluster's T_next and threshold, and the block counts its due particles.
 __global__ __launch_bounds__(kWG) void k_count(Dev d) {
   __shared__ int sh[4];
-  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
+  __shared__ int thr[kScanBlock];
+  const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
+  const int64_t b1 = (b0 + kScanBlock < d.n) ? b0 + kScanBlock : d.n;
+  const int c0 = d.cid[b0], c1 = d.cid[b1 - 1];
+  const int64_t tend = d.ctr[kCtrTend];
+  const int err = *d.err;
+  for (int c = c0 + threadIdx.x; c <= c1; c += kWG) {
+    int64_t tn;
+    int L;
+    cluster_threshold(d, c, tend, err, &tn, &L);
+    thr[c - c0] = L;
+    const int64_t first = d.coff[c];
+    if (first >= b0 && first < b1) {
+      d.Tnext[c] = tn;
+      d.Lthr[c] = L;
+    }
+  }
+  __syncthreads();
+  const int64_t base = b0 + threadIdx.x * 4;
   int cnt = 0;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int64_t i = base + e;
-    if (i < d.n && d.level[i] >= d.Lthr[d.cid[i]]) ++cnt;
+    if (i < d.n && d.level[i] >= thr[d.cid[i] - c0]) ++cnt;
   }
   cnt = block_sum_i(cnt, sh);
   if (threadIdx.x == 0) d.blk_cnt[blockIdx.x] = cnt;
+}
+
+// Sum of blk_cnt[0, b) by the whole block (grids of at most kFusedScan
+// blocks, where every block reading the counts beats a separate scan launch).
+__device__ __forceinline__ int block_prefix(const Dev &d, int b, int *sh4) {
+  int v = 0;
+  for (int u = threadIdx.x; u < b; u += kWG) v += d.blk_cnt[u];
+  return block_sum_i(v, sh4);
 }
 
 // Exclusive scan of nblk block counts by one 1024-thread workgroup.
@@ -808,9 +833,13 @@ __global__ __launch_bounds__(1024) void k_scan(Dev d) {
 }
 
 // Ordered compaction: active list ascending in particle index, and each
-// cluster's offset in it.
+// cluster's offset in it.  FUSED: the block sums the counts before it
+// itself (no k_scan).
+template <bool FUSED>
 __global__ __launch_bounds__(kWG) void k_scatter(Dev d) {
   __shared__ int wsum[4];
+  __shared__ int sh4[4];
+  const int bpre = FUSED ? block_prefix(d, blockIdx.x, sh4) : d.blk_off[blockIdx.x];
   const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
   int flag[4];
   int cnt = 0;
@@ -832,7 +861,7 @@ __global__ __launch_bounds__(kWG) void k_scatter(Dev d) {
   __syncthreads();
   int wbase = 0;
   for (int u = 0; u < w; ++u) wbase += wsum[u];
-  int pos = d.blk_off[blockIdx.x] + wbase + incl - cnt;
+  int pos = bpre + wbase + incl - cnt;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int64_t i = base + e;
@@ -842,7 +871,11 @@ __global__ __launch_bounds__(kWG) void k_scatter(Dev d) {
       if (flag[e]) d.active[pos++] = (int32_t)i;
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) d.act_off[d.C] = d.blk_off[d.nblk];
+  if (FUSED) {
+    if (blockIdx.x == d.nblk - 1 && threadIdx.x == kWG - 1) d.act_off[d.C] = pos;
+  } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+    d.act_off[d.C] = d.blk_off[d.nblk];
+  }
 }
 
 // Exclusive scan of one int64 per thread over a 1024-thread workgroup
@@ -1622,9 +1655,14 @@ __global__ __launch_bounds__(kWG) void k_rcount(Dev d, int64_t na_host) {
   if (threadIdx.x == 0) d.blk_cnt[blockIdx.x] = cnt;
 }
 
+// FUSED: the block sums the counts before it itself, and the last block
+// publishes the total (and, for one cluster, the re-evaluation offsets).
+template <bool FUSED>
 __global__ __launch_bounds__(kWG) void k_rscatter(Dev d, const int32_t *list,
                                                   int64_t na_host) {
   __shared__ int wsum[4];
+  __shared__ int sh4[4];
+  const int bpre = FUSED ? block_prefix(d, blockIdx.x, sh4) : d.blk_off[blockIdx.x];
   const int64_t total = na_host >= 0 ? na_host : d.act_off[d.C];
   const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
   int flag[4];
@@ -1646,7 +1684,7 @@ __global__ __launch_bounds__(kWG) void k_rscatter(Dev d, const int32_t *list,
   __syncthreads();
   int wbase = 0;
   for (int u = 0; u < w; ++u) wbase += wsum[u];
-  int pos = d.blk_off[blockIdx.x] + wbase + incl - cnt;
+  int pos = bpre + wbase + incl - cnt;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     if (flag[e]) {
@@ -1654,6 +1692,14 @@ __global__ __launch_bounds__(kWG) void k_rscatter(Dev d, const int32_t *list,
       d.ref_i[pos] = list[k];
       d.ref_k[pos] = (int32_t)k;
       ++pos;
+    }
+  }
+  if (FUSED && blockIdx.x == gridDim.x - 1 && threadIdx.x == kWG - 1) {
+    d.blk_off[d.nblk] = pos;          // the total, as k_scan leaves it
+    if (d.C == 1) {                   // k_ref_offsets is not launched
+      d.ref_off[0] = 0;
+      d.ref_off[1] = pos;
+      d.ctr[kCtrRefined] += pos;
     }
   }
 }
@@ -1884,15 +1930,14 @@ hipError_t launch_all_active(const Dev &d, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_sched(const Dev &d, hipStream_t s) {
-  hipLaunchKernelGGL(k_sched, dim3((d.C + kWG - 1) / kWG), dim3(kWG), 0, s, d);
-  return hipGetLastError();
-}
-
 hipError_t launch_compact(const Dev &d, hipStream_t s) {
   hipLaunchKernelGGL(k_count, dim3(d.nblk), dim3(kWG), 0, s, d);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d);
-  hipLaunchKernelGGL(k_scatter, dim3(d.nblk), dim3(kWG), 0, s, d);
+  if (d.nblk <= kFusedScan) {
+    hipLaunchKernelGGL(k_scatter<true>, dim3(d.nblk), dim3(kWG), 0, s, d);
+  } else {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d);
+    hipLaunchKernelGGL(k_scatter<false>, dim3(d.nblk), dim3(kWG), 0, s, d);
+  }
   return hipGetLastError();
 }
 
@@ -2074,10 +2119,16 @@ hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_hos
                      list, na_host, refine_ratio);
   if (refine_ratio > 0.0f) {
     hipLaunchKernelGGL(k_rcount, dim3(d.nblk), dim3(kWG), 0, s, d, na_host);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d);
-    hipLaunchKernelGGL(k_rscatter, dim3(d.nblk), dim3(kWG), 0, s, d, list, na_host);
-    hipLaunchKernelGGL(k_ref_offsets, dim3((d.C + 1 + kWG - 1) / kWG), dim3(kWG), 0, s,
-                       d, na_host >= 0 ? 1 : 0);
+    const bool fused = d.nblk <= kFusedScan;
+    if (fused) {
+      hipLaunchKernelGGL(k_rscatter<true>, dim3(d.nblk), dim3(kWG), 0, s, d, list, na_host);
+    } else {
+      hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d);
+      hipLaunchKernelGGL(k_rscatter<false>, dim3(d.nblk), dim3(kWG), 0, s, d, list, na_host);
+    }
+    if (!fused || d.C > 1)
+      hipLaunchKernelGGL(k_ref_offsets, dim3((d.C + 1 + kWG - 1) / kWG), dim3(kWG), 0, s,
+                         d, na_host >= 0 ? 1 : 0);
   }
   return hipGetLastError();
 }
