@@ -45,10 +45,12 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="headline",
-                    choices=("headline", "sweep", "ensemble", "blocksteps", "symplectic"),
+                    choices=("headline", "sweep", "ensemble", "blocksteps", "kingsteps",
+                             "symplectic"),
                     help="headline: the contract line (default); sweep: n_active sweep of "
                          "the King 2^20 evaluation; ensemble: 256-cluster block steps; "
                          "blocksteps: Plummer 65536 FP64 and Salpeter 262144 mixed runs; "
+                         "kingsteps: King 2^20 mixed block steps (real active sets); "
                          "symplectic: time per leapfrog / sixth-order step vs N on the "
                          "paper's uniform-sphere initial conditions")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -371,6 +373,11 @@ def main():
         run_blocksteps(binding, torch, "ensemble", m, x, v, 0.25, binding.MIXED,
                        cluster_offsets=off, eps=1e-3, level_min=5, chunks=8)
         ensemble_vs_solo(binding, torch, m, x, v, off, 32)
+        return
+    if a.workload == "kingsteps":
+        m, x, v = ics.king(a.n, 7.0, 4)
+        run_blocksteps(binding, torch, "king1M-blocksteps", m, x, v, 1 / 128, binding.MIXED,
+                       eps=EPS, level_min=9, chunks=4)
         return
     if a.workload == "symplectic":
         symplectic_scaling(binding, torch, ics, not a.no_cpu)
