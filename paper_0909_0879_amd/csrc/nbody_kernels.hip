@@ -282,11 +282,22 @@ __device__ __forceinline__ void pair_mixed_acc(const IDS &I, int iidx, const JRe
   t[2] = fmaf(mr3, dz, t[2]);
 }
 
+// Potential -m_j / sqrt(s) (energy diagnostics).  The i's own pair is
+// skipped: by s == 0 when unsoftened (MASK, as for the forces), else by
+// index in the tiles that can hold i (SELF).
+template <bool MASK, bool SELF>
 __device__ __forceinline__ void pair_pot(const I64 &I, int iidx, const JRec64 &r,
-                                         double eps2, double *t) {
+                                         double eps2, double *t, int &dom) {
   const double dx = r.x - I.x[0], dy = r.y - I.x[1], dz = r.z - I.x[2];
   const double s = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-  const double rinv = (r.idx == iidx) ? 0.0 : 1.0 / sqrt(s);
+  double rinv = rsq64(s);
+  if (MASK) {
+    if (s == 0.0) {
+      rinv = 0.0;
+      dom |= (r.idx != iidx);
+    }
+  }
+  if (SELF && r.idx == iidx) rinv = 0.0;
   t[0] = fma(-r.m, rinv, t[0]);
 }
 
@@ -357,7 +368,7 @@ __device__ __forceinline__ void pair_k(const typename Traits<MODE>::Rec &r,
     else if constexpr (MODE == kModeFP64Acc)
       pair_fp64_acc<MASK>(I[k], iidx[k], r, eps2, t[k], dom[k]);
     else
-      pair_pot(I[k], iidx[k], r, eps2, t[k]);
+      pair_pot<MASK, SELF>(I[k], iidx[k], r, eps2, t[k], dom[k]);
   }
 }
 
@@ -550,18 +561,20 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
 #pragma unroll
       for (int k = 0; k < K; ++k) mine |= (iidx[k] >= jt && iidx[k] < jt + cnt);
       const bool self_tile = __syncthreads_or(mine) != 0;
-      const bool msk = mask || MODE == kModePot;
+      // the FP64 force terms of the i's own pair are exactly zero; the
+      // mixed bound and the potential must skip it
+      constexpr bool has_self = mode_mixed(MODE) || MODE == kModePot;
       if (Q == 1) {
-        if (msk)
+        if (mask)
           tile_loop<MODE, K, true, true, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
-        else if (mode_mixed(MODE) && self_tile)
+        else if (has_self && self_tile)
           tile_loop<MODE, K, true, false, true>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
         else
           tile_loop<MODE, K, true, false, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
       } else {
-        if (msk)
+        if (mask)
           tile_loop<MODE, K, false, true, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
-        else if (mode_mixed(MODE) && self_tile)
+        else if (has_self && self_tile)
           tile_loop<MODE, K, false, false, true>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
         else
           tile_loop<MODE, K, false, false, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);

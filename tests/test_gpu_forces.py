@@ -71,6 +71,25 @@ def test_j_set_larger_than_context(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_j_set_of_2_23(prec):
+    # one cluster of 2^23 j, eight times the largest benchmark system: 64-bit
+    # j offsets and long split ranges; sampled i, the last index among them
+    require_gpu()
+    n = 1 << 23
+    m0, x0, v0 = ics.plummer(64, 1)
+    g = _ctx(m0, x0, v0, 1e-4, prec)
+    m, x, v = ics.plummer(n, 23)
+    rng = np.random.default_rng(23)
+    idx = np.sort(rng.choice(n - 1, 255, replace=False))
+    idx = np.append(idx, n - 1).astype(np.int32)
+    print(f"n_j 2^23 prec={prec}", flush=True)
+    acc, jerk = g.forces(x, v, m, i_active=idx)
+    g.sync()
+    a_ref, j_ref = oracle.forces(x, v, m, 1e-4, idx=idx.astype(np.int64))
+    check_parity(to_np(acc), to_np(jerk), a_ref, j_ref, prec == binding.MIXED, "n_j 2^23")
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_zero_softening(prec):
     require_gpu()
     rng = np.random.default_rng(3)
