@@ -27,10 +27,34 @@ class OracleError(RuntimeError):
         self.code = code
 
 
+FIELD_KEYS = ("bulge_m", "bulge_b", "disk_m", "disk_a", "disk_b", "halo_m", "halo_a",
+              "halo_gamma", "halo_rc")
+
+
+class Field(C.Structure):
+    """External (Galactic) field parameters; see oracle_field_eval."""
+    _fields_ = [(k, C.c_double) for k in FIELD_KEYS]
+
+
+def make_field(field):
+    """A Field from a dict of FIELD_KEYS (missing components are off), or None."""
+    if field is None:
+        return None
+    unknown = set(field) - set(FIELD_KEYS)
+    if unknown:
+        raise ValueError(f"unknown field keys {sorted(unknown)}")
+    return Field(*[float(field.get(k, 0.0)) for k in FIELD_KEYS])
+
+
+def _fp(f):
+    return C.byref(f) if f is not None else None
+
+
 class Params(C.Structure):
     _fields_ = [("eps", C.c_double), ("eta", C.c_double),
                 ("eta_start", C.c_double), ("dt_shared", C.c_double),
-                ("level_min", C.c_int32), ("level_max", C.c_int32)]
+                ("level_min", C.c_int32), ("level_max", C.c_int32),
+                ("field", C.POINTER(Field))]
 
 
 class Stats(C.Structure):
@@ -47,7 +71,11 @@ def lib():
         L = C.CDLL(_LIB_PATH)
         P = C.c_void_p
         L.oracle_forces.argtypes = [C.c_int64, P, C.c_int64, P, P, P, C.c_double, P, P, P]
-        L.oracle_energy.argtypes = [C.c_int64, P, P, P, C.c_double, P]
+        L.oracle_energy.argtypes = [C.c_int64, P, P, P, C.c_double, P, P]
+        L.oracle_field_eval.argtypes = [P, P, P, P, P, P]
+        L.oracle_field_eval.restype = None
+        L.oracle_field_all.argtypes = [P, C.c_int64, P, P, P, P, P]
+        L.oracle_field_all.restype = None
         L.oracle_predict_one.argtypes = [P, P, P, P, C.c_double, P, P]
         L.oracle_predict_one.restype = None
         L.oracle_predict.argtypes = [C.c_int64, P, P, P, P, P, P, P]
@@ -64,8 +92,8 @@ def lib():
         L.oracle_set_threads.argtypes = [C.c_int]
         L.oracle_set_threads.restype = None
         L.oracle_symplectic_weights.argtypes = [C.c_int, P]
-        L.oracle_symplectic.argtypes = [C.c_int64, P, P, P, C.c_double, C.c_double, C.c_int64,
-                                        C.c_int]
+        L.oracle_symplectic.argtypes = [C.c_int64, P, P, P, C.c_double, P, C.c_double,
+                                        C.c_int64, C.c_int]
         _lib = L
     return _lib
 
@@ -112,31 +140,51 @@ def symplectic_weights(scheme):
     return w[:k].copy()
 
 
-def symplectic(x, v, m, eps, h, n_steps, scheme):
-    """n_steps steps of size h of a symplectic driver; returns new (x, v)."""
+def symplectic(x, v, m, eps, h, n_steps, scheme, field=None):
+    """n_steps steps of size h of a symplectic driver (with the external
+    field given as a dict of FIELD_KEYS, or none); returns new (x, v)."""
     m = _f64(m)
     n = m.shape[0]
     x = _f64(x, (n, 3)).copy()
     v = _f64(v, (n, 3)).copy()
-    rc = lib().oracle_symplectic(n, _p(m), _p(x), _p(v), float(eps), float(h), int(n_steps),
-                                 int(scheme))
+    f = make_field(field)
+    rc = lib().oracle_symplectic(n, _p(m), _p(x), _p(v), float(eps), _fp(f), float(h),
+                                 int(n_steps), int(scheme))
     if rc:
         raise OracleError(rc, "symplectic")
     return x, v
 
 
-def energy(x, v, m, eps):
-    """{K, W, E, L(3), P(3)} of one isolated system."""
+def energy(x, v, m, eps, field=None):
+    """{K, W, E, L(3), P(3)} of one system; E includes the external field's
+    potential energy when a field is given."""
     m = _f64(m)
     n = m.shape[0]
     x = _f64(x, (n, 3))
     v = _f64(v, (n, 3))
     out = np.empty(9)
-    rc = lib().oracle_energy(n, _p(x), _p(v), _p(m), float(eps), _p(out))
+    f = make_field(field)
+    rc = lib().oracle_energy(n, _p(x), _p(v), _p(m), float(eps), _fp(f), _p(out))
     if rc:
         raise OracleError(rc, "energy")
     return {"K": out[0], "W": out[1], "E": out[2], "L": out[3:6].copy(),
             "P": out[6:9].copy()}
+
+
+def field_eval(field, x, v):
+    """External field on points x with velocities v ((n, 3) or (3,)):
+    returns (acc, jerk, pot) of matching shapes."""
+    f = make_field(field)
+    x = np.asarray(x, np.float64)
+    single = x.ndim == 1
+    x = _f64(x.reshape(-1, 3))
+    n = x.shape[0]
+    v = _f64(np.asarray(v, np.float64).reshape(-1, 3), (n, 3))
+    acc, jerk, pot = np.empty((n, 3)), np.empty((n, 3)), np.empty(n)
+    lib().oracle_field_all(C.byref(f), n, _p(x), _p(v), _p(acc), _p(jerk), _p(pot))
+    if single:
+        return acc[0], jerk[0], pot[0]
+    return acc, jerk, pot
 
 
 def predict_one(x, v, a, j, dt):
@@ -187,7 +235,7 @@ class System:
     """Hermite-4 block-step state of one isolated system (oracle side)."""
 
     def __init__(self, m, x, v, eps, eta=0.01, eta_start=0.01, dt_shared=0.0,
-                 level_min=3, level_max=20):
+                 level_min=3, level_max=20, field=None):
         self.m = _f64(m).copy()
         n = self.m.shape[0]
         self.x = _f64(x, (n, 3)).copy()
@@ -196,8 +244,11 @@ class System:
         self.j = np.empty((n, 3))
         self.tick = np.zeros(n, np.int64)
         self.level = np.zeros(n, np.int8)
+        self.field_dict = dict(field) if field is not None else None
+        self._field = make_field(field)          # kept alive for the params pointer
         self.params = Params(float(eps), float(eta), float(eta_start), float(dt_shared),
-                             int(level_min), int(level_max))
+                             int(level_min), int(level_max),
+                             C.pointer(self._field) if self._field is not None else None)
         self.stats = Stats()
         rc = lib().oracle_init(n, _p(self.m), _p(self.x), _p(self.v), C.byref(self.params),
                                _p(self.a), _p(self.j), _p(self.tick), _p(self.level),
@@ -226,7 +277,7 @@ class System:
         return self
 
     def energy(self):
-        return energy(self.x, self.v, self.m, self.params.eps)
+        return energy(self.x, self.v, self.m, self.params.eps, self.field_dict)
 
 
 def threads() -> int:

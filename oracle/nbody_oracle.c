@@ -16,6 +16,13 @@
  * the Plummer form phi = -m / sqrt(r^2 + eps^2).  The jerk is the time
  * derivative of a_i along the current velocities (not in the paper).
  *
+ * External field (Sect. 4): the pairwise forces are added to the force of
+ * an analytic Galactic potential, the three-component model of Allen &
+ * Santillan (1991) the paper names (spherical bulge, axisymmetric disk,
+ * spherical halo).  The paper prints neither the formulas nor the
+ * parameters; the forms used are given at oracle_field_eval, and the
+ * published parameters are supplied by the caller.
+ *
  * Time integration: the paper's symplectic drivers (leapfrog and a
  * sixth-order composition of leapfrog stages, Sect. 4) for shared steps,
  * and a fourth-order Hermite predictor-corrector (Makino &
@@ -134,15 +141,139 @@ int oracle_forces(int64_t n_i, const int64_t *idx, int64_t n_j,
   return err;
 }
 
+/* --------------------------------------------------------- external field */
+
+/* Parameters of the three components, G = 1 in the caller's units; a zero
+ * mass switches a component off. */
+typedef struct {
+  double bulge_m, bulge_b;            /* bulge mass and scale length */
+  double disk_m, disk_a, disk_b;      /* disk mass, radial and vertical scales */
+  double halo_m, halo_a, halo_gamma;  /* halo mass scale, radius, exponent */
+  double halo_rc;                     /* halo cut-off radius */
+} oracle_field;
+
+/* Spherical component: acc = -g(r) x, jerk = -(g v + (g'(r) / r) (x.v) x),
+ * the time derivative of the acceleration along v. */
+static void sph_add(double g, double gp_over_r, const double x[3],
+                    const double v[3], double acc[3], double jerk[3]) {
+  const double xv = x[0] * v[0] + x[1] * v[1] + x[2] * v[2];
+  for (int c = 0; c < 3; ++c) {
+    acc[c] -= g * x[c];
+    jerk[c] -= g * v[c] + gp_over_r * xv * x[c];
+  }
+}
+
+/* The external field at position x moving with velocity v:
+ *   bulge (Plummer sphere): Phi = -M / sqrt(r^2 + b^2), so
+ *     g = M (r^2 + b^2)^(-3/2), g'/r = -3 M (r^2 + b^2)^(-5/2).
+ *   disk (Miyamoto & Nagai 1975): zeta = sqrt(z^2 + b^2), u = a + zeta,
+ *     D = sqrt(R^2 + u^2), Phi = -M / D;
+ *     acc = -M (x, y, z u / zeta) / D^3; with q = x vx + y vy + u z vz / zeta
+ *     (= D dD/dt) and d(z u / zeta)/dt = vz (u b^2 / zeta^3 + z^2 / zeta^2),
+ *     jerk = -M [ (vx, vy, vz (u b^2 / zeta^3 + z^2 / zeta^2)) / D^3
+ *                 - 3 q (x, y, z u / zeta) / D^5 ].
+ *   halo: enclosed mass M(r) = M_h s^(g+1) / (1 + s^g), s = r / a, up to
+ *     r_c and M(r_c) beyond; force -M(r) / r^2 radially, i.e.
+ *     g(r) = M(r) / r^3, g'/r = M'(r) / r^4 - 3 M(r) / r^5 with
+ *     M'(r) = (M_h / a) s^g (g + 1 + s^g) / (1 + s^g)^2 inside, 0 beyond;
+ *     potential the integral of that force from infinity:
+ *     Phi = -M(r_c) / r beyond r_c,
+ *     Phi = -M(r_c) / r_c - (M_h / (g a)) [ln(1 + s_c^g) - ln(1 + s^g)] inside.
+ *     At r = 0 the halo adds nothing (its acceleration tends to zero there).
+ * pot receives Phi (per unit mass).  Pins: the published circular velocity
+ * at the Sun and total mass of the model, acc = -grad Phi and jerk = d acc /
+ * dt by central differences, the disk with a = 0 equal to the Plummer
+ * bulge, the halo continuous at r_c and a point mass beyond, a circular
+ * orbit kept by the Hermite driver. */
+void oracle_field_eval(const oracle_field *f, const double x[3], const double v[3],
+                       double acc[3], double jerk[3], double *pot) {
+  double phi = 0.0;
+  for (int c = 0; c < 3; ++c) acc[c] = jerk[c] = 0.0;
+  const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+  if (f->bulge_m != 0.0) {
+    const double d2 = r2 + f->bulge_b * f->bulge_b;
+    const double d = sqrt(d2);
+    const double g = f->bulge_m / (d2 * d);
+    sph_add(g, -3.0 * g / d2, x, v, acc, jerk);
+    phi -= f->bulge_m / d;
+  }
+  if (f->disk_m != 0.0) {
+    const double M = f->disk_m, b = f->disk_b;
+    const double z = x[2];
+    const double zeta = sqrt(z * z + b * b);
+    const double u = f->disk_a + zeta;
+    const double D2 = x[0] * x[0] + x[1] * x[1] + u * u;
+    const double D = sqrt(D2);
+    const double D3 = D2 * D, D5 = D3 * D2;
+    const double zf = z * u / zeta;
+    const double q = x[0] * v[0] + x[1] * v[1] + v[2] * zf;
+    const double dzf = v[2] * (u * b * b / (zeta * zeta * zeta) + z * z / (zeta * zeta));
+    acc[0] -= M * x[0] / D3;
+    acc[1] -= M * x[1] / D3;
+    acc[2] -= M * zf / D3;
+    jerk[0] -= M * (v[0] / D3 - 3.0 * q * x[0] / D5);
+    jerk[1] -= M * (v[1] / D3 - 3.0 * q * x[1] / D5);
+    jerk[2] -= M * (dzf / D3 - 3.0 * q * zf / D5);
+    phi -= M / D;
+  }
+  if (f->halo_m != 0.0 && r2 > 0.0) {
+    const double a = f->halo_a, gm = f->halo_gamma, Mh = f->halo_m;
+    const double r = sqrt(r2);
+    const double sc = f->halo_rc / a;
+    const double scg = pow(sc, gm);
+    const double Mc = Mh * sc * scg / (1.0 + scg);    /* M(r_c) */
+    double Mr, Mp;
+    if (r < f->halo_rc) {
+      const double s = r / a, sg = pow(s, gm);
+      Mr = Mh * s * sg / (1.0 + sg);
+      Mp = (Mh / a) * sg * (gm + 1.0 + sg) / ((1.0 + sg) * (1.0 + sg));
+      phi += -Mc / f->halo_rc - (Mh / (gm * a)) * (log(1.0 + scg) - log(1.0 + sg));
+    } else {
+      Mr = Mc;
+      Mp = 0.0;
+      phi -= Mc / r;
+    }
+    const double r3 = r2 * r;
+    sph_add(Mr / r3, Mp / (r3 * r) - 3.0 * Mr / (r3 * r2), x, v, acc, jerk);
+  }
+  if (pot) *pot = phi;
+}
+
+/* The field on n particles ((n, 3) arrays; pot may be NULL). */
+void oracle_field_all(const oracle_field *f, int64_t n, const double *x,
+                      const double *v, double *acc, double *jerk, double *pot) {
+  for (int64_t i = 0; i < n; ++i)
+    oracle_field_eval(f, &x[3 * i], &v[3 * i], &acc[3 * i], &jerk[3 * i],
+                      pot ? &pot[i] : NULL);
+}
+
+/* Add the field (if any) to the pair sums of particles idx[0..n_i) whose
+ * positions and velocities are x, v. */
+static void add_field(const oracle_field *f, int64_t n_i, const int64_t *idx,
+                      const double *x, const double *v, double *acc, double *jerk) {
+  if (!f) return;
+  for (int64_t k = 0; k < n_i; ++k) {
+    const int64_t i = idx[k];
+    double fa[3], fj[3];
+    oracle_field_eval(f, &x[3 * i], &v[3 * i], fa, fj, NULL);
+    for (int c = 0; c < 3; ++c) {
+      acc[3 * k + c] += fa[c];
+      if (jerk) jerk[3 * k + c] += fj[c];
+    }
+  }
+}
+
 /* ---------------------------------------------------------------- energy */
 
-/* Diagnostics of one isolated system (Sect. 4: virial ratio Q = 2K/|W|):
+/* Diagnostics of one system (Sect. 4: virial ratio Q = 2K/|W|):
  * out = {K, W, E, Lx, Ly, Lz, Px, Py, Pz} with K = 1/2 sum m v^2,
- * W = -sum_{i<j} m_i m_j / sqrt(r^2 + eps^2), E = K + W, L = sum m x cross v,
- * P = sum m v.  Pins: Plummer-sphere virial equilibrium (W -> -1/2,
- * K -> 1/4 in Henon units), two-body closed form. */
+ * W = -sum_{i<j} m_i m_j / sqrt(r^2 + eps^2), E = K + W + sum_i m_i Phi(x_i)
+ * (Phi the external field's potential, none when field is NULL),
+ * L = sum m x cross v, P = sum m v.  Pins: Plummer-sphere virial equilibrium
+ * (W -> -1/2, K -> 1/4 in Henon units), two-body closed form. */
 int oracle_energy(int64_t n, const double *x, const double *v,
-                  const double *m, double eps, double *out) {
+                  const double *m, double eps, const oracle_field *field,
+                  double *out) {
   if (n < 0 || eps < 0.0) return OR_EINVAL;
   nsum k = {0, 0}, w = {0, 0}, L[3], P[3];
   memset(L, 0, sizeof L);
@@ -178,9 +309,15 @@ int oracle_energy(int64_t n, const double *x, const double *v,
   }
   for (int64_t i = 0; i < n; ++i) nsum_add(&w, wi[i]);
   free(wi);
+  nsum we = {0, 0};
+  for (int64_t i = 0; field && i < n; ++i) {
+    double fa[3], fj[3], phi;
+    oracle_field_eval(field, &x[3 * i], &v[3 * i], fa, fj, &phi);
+    nsum_add(&we, m[i] * phi);
+  }
   out[0] = nsum_val(&k);
   out[1] = nsum_val(&w);
-  out[2] = out[0] + out[1];
+  out[2] = out[0] + out[1] + nsum_val(&we);
   for (int c = 0; c < 3; ++c) {
     out[3 + c] = nsum_val(&L[c]);
     out[6 + c] = nsum_val(&P[c]);
@@ -296,6 +433,7 @@ int oracle_initial_level(const double a[3], const double j[3], double eta_s,
 typedef struct {
   double eps, eta, eta_start, dt_shared;
   int32_t level_min, level_max;
+  const oracle_field *field;      /* external field, NULL: none */
 } oracle_params;
 
 typedef struct {
@@ -320,6 +458,7 @@ int oracle_init(int64_t n, const double *m, const double *x, const double *v,
   if (!idx) return OR_EINVAL;
   for (int64_t i = 0; i < n; ++i) idx[i] = i;
   int err = oracle_forces(n, idx, n, x, v, m, p->eps, a, jk, NULL);
+  if (!err) add_field(p->field, n, idx, x, v, a, jk);
   free(idx);
   if (err) return err;
   memset(st, 0, sizeof *st);
@@ -350,7 +489,8 @@ int oracle_init(int64_t n, const double *m, const double *x, const double *v,
  *   1. T_next = min_i (tick_i + 2^(20 - level_i));
  *      active set A = {i : tick_i + 2^(20 - level_i) == T_next}
  *   2. predict every particle to T_next
- *   3. acceleration and jerk on each i in A from all predicted particles
+ *   3. acceleration and jerk on each i in A from all predicted particles,
+ *      plus the external field at i's predicted position and velocity
  *   4. correct each i in A, then choose its next level (block mode) or keep
  *      it (dt_shared > 0)
  * max_steps bounds the number of block steps (0 = no bound). */
@@ -389,6 +529,7 @@ int oracle_run(int64_t n, const double *m, double *x, double *v, double *a,
                          (double)(t_next - tick[i]) * tick_dt, &xp[3 * i], &vp[3 * i]);
     err = oracle_forces(na, act, n, xp, vp, m, p->eps, a1, j1, NULL);
     if (err) goto done;
+    add_field(p->field, na, act, xp, vp, a1, j1);
     for (int64_t k = 0; k < na; ++k) {
       const int64_t i = act[k];
       const double h = (double)(t_next - tick[i]) * tick_dt;
@@ -452,9 +593,11 @@ int oracle_symplectic_weights(int scheme, double *w) {
 }
 
 /* Accelerations of all n particles at positions x (acc-only use of the
- * pair sum above; velocities do not enter the acceleration). */
+ * pair sum above; velocities do not enter the acceleration), plus the
+ * external field's. */
 static int accel_all(int64_t n, const double *x, const double *m, double eps,
-                     double *acc, double *tmp_v, double *tmp_j) {
+                     const oracle_field *field, double *acc, double *tmp_v,
+                     double *tmp_j) {
   int err = OR_OK;
   (void)tmp_v;
 #pragma omp parallel for schedule(dynamic, 16)
@@ -467,6 +610,11 @@ static int accel_all(int64_t n, const double *x, const double *m, double eps,
 #pragma omp atomic write
       err = e;
     }
+    if (field) {
+      double fa[3], fj[3];
+      oracle_field_eval(field, &x[3 * i], zero, fa, fj, NULL);
+      for (int c = 0; c < 3; ++c) acc[3 * i + c] += fa[c];
+    }
   }
   return err;
 }
@@ -476,10 +624,12 @@ static int accel_all(int64_t n, const double *x, const double *m, double eps,
  * in place.  Each stage of weight w is the kick-drift-kick leapfrog of step
  * w h: v += (w h / 2) a(x); x += w h v; v += (w h / 2) a(x).  The
  * acceleration at the current positions is kept between stages, so a stage
- * costs one evaluation.  Pins: Kepler period and convergence order, time
+ * costs one evaluation.  field: external field added to every evaluation
+ * (NULL: isolated system).  Pins: Kepler period and convergence order, time
  * reversibility, bounded energy error. */
 int oracle_symplectic(int64_t n, const double *m, double *x, double *v,
-                      double eps, double h, int64_t n_steps, int scheme) {
+                      double eps, const oracle_field *field, double h,
+                      int64_t n_steps, int scheme) {
   double w[7];
   const int ns = oracle_symplectic_weights(scheme, w);
   if (ns == 0 || n < 1 || n_steps < 0 || !(h > 0.0)) return OR_EINVAL;
@@ -487,13 +637,13 @@ int oracle_symplectic(int64_t n, const double *m, double *x, double *v,
   double *zv = (double *)calloc((size_t)(3 * n), sizeof(double));
   double *jk = (double *)calloc((size_t)(3 * n), sizeof(double));
   int err = (a && zv && jk) ? OR_OK : OR_EINVAL;
-  if (!err) err = accel_all(n, x, m, eps, a, zv, jk);
+  if (!err) err = accel_all(n, x, m, eps, field, a, zv, jk);
   for (int64_t st = 0; st < n_steps && !err; ++st) {
     for (int k = 0; k < ns && !err; ++k) {
       const double c = w[k] * h;
       for (int64_t q = 0; q < 3 * n; ++q) v[q] += 0.5 * c * a[q];
       for (int64_t q = 0; q < 3 * n; ++q) x[q] += c * v[q];
-      err = accel_all(n, x, m, eps, a, zv, jk);
+      err = accel_all(n, x, m, eps, field, a, zv, jk);
       for (int64_t q = 0; q < 3 * n; ++q) v[q] += 0.5 * c * a[q];
     }
   }
