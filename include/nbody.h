@@ -72,6 +72,29 @@ typedef enum nbody_precision {
   NBODY_MIXED = 1
 } nbody_precision;
 
+/* External Galactic field added to the pairwise forces (Sect. 4: the paper
+ * sums the star-star forces with an analytic Galactic potential, the model
+ * of Allen & Santillan (1991) with a spherical bulge, an axisymmetric disk
+ * and a spherical halo; the paper gives neither formulas nor parameters).
+ * Positions are taken about the Galactic centre, z along the disk axis;
+ * every value in the context's units with G = 1:
+ *   bulge  Phi = -bulge_m / sqrt(r^2 + bulge_b^2)                (Plummer)
+ *   disk   Phi = -disk_m / sqrt(R^2 + (disk_a + sqrt(z^2 + disk_b^2))^2)
+ *                                                     (Miyamoto & Nagai)
+ *   halo   enclosed mass M(r) = halo_m s^(g + 1) / (1 + s^g), s = r / halo_a,
+ *          g = halo_gamma, up to r = halo_rc and M(halo_rc) beyond; radial
+ *          pull M(r) / r^2 and the potential that integrates it from
+ *          infinity (no pull at r = 0).
+ * A zero mass switches a component off; the other values of an active
+ * component must be finite, lengths > 0 (disk_a >= 0), halo_gamma > 0.
+ * Allen & Santillan's model in units of 1 kpc and 2.32e7 M_sun: bulge
+ * 606, 0.3873; disk 3690, 5.3178, 0.25; halo 4615, 12, 1.02, 100. */
+typedef struct nbody_field {
+  double bulge_m, bulge_b;
+  double disk_m, disk_a, disk_b;
+  double halo_m, halo_a, halo_gamma, halo_rc;
+} nbody_field;
+
 typedef struct nbody_params {
   int32_t n_clusters;              /* >= 1, <= 4096 */
   int32_t precision;               /* nbody_precision */
@@ -88,6 +111,14 @@ typedef struct nbody_params {
   void *stream;                    /* hipStream_t for all work; NULL = null stream */
   void *workspace;                 /* device buffer, 256-byte aligned */
   size_t workspace_bytes;          /* >= nbody_workspace_bytes(params, n) */
+  const nbody_field *field;        /* host, read at nbody_init; NULL: no
+                                      external field.  When set, its
+                                      acceleration and jerk are added to the
+                                      pairwise ones wherever the integrators
+                                      use them (the stored a and jerk, block
+                                      and symplectic steps) and its potential
+                                      energy to E; nbody_forces and
+                                      nbody_accel stay pairwise. */
 } nbody_params;
 
 /* Bytes of device workspace a context for n particles needs (0 if the
@@ -172,8 +203,9 @@ int nbody_step_blocks(nbody_ctx *c, double t_end, int64_t max_block_steps,
 /* Diagnostics per cluster, computed in FP64 at each cluster's current time
  * (every particle predicted to it): out (host) receives 9 doubles per
  * cluster: K, W, E, Lx, Ly, Lz, Px, Py, Pz, with K = 1/2 sum m v^2,
- * W = -sum_{i<j} m_i m_j / sqrt(r^2 + eps^2), E = K + W, L = sum m x cross
- * v, P = sum m v (virial ratio Q = 2K/|W|, Sect. 4).  Syncs. */
+ * W = -sum_{i<j} m_i m_j / sqrt(r^2 + eps^2), E = K + W (+ sum m Phi_ext(x)
+ * with an external field), L = sum m x cross v, P = sum m v (virial ratio
+ * Q = 2K/|W|, Sect. 4).  Syncs. */
 int nbody_energy(nbody_ctx *c, double *out);
 
 /* Copy the state out: x, v, a, jerk ((n, 3), device, FP64), tick (n, int64,

@@ -38,6 +38,15 @@ class NBodyError(RuntimeError):
         self.code = code
 
 
+FIELD_KEYS = ("bulge_m", "bulge_b", "disk_m", "disk_a", "disk_b", "halo_m", "halo_a",
+              "halo_gamma", "halo_rc")
+
+
+class Field(C.Structure):
+    """nbody_field: the external Galactic field (G = 1, context units)."""
+    _fields_ = [(k, C.c_double) for k in FIELD_KEYS]
+
+
 class Params(C.Structure):
     _fields_ = [
         ("n_clusters", C.c_int32), ("precision", C.c_int32),
@@ -45,7 +54,31 @@ class Params(C.Structure):
         ("eta", C.c_double), ("eta_start", C.c_double), ("dt_shared", C.c_double),
         ("level_min", C.c_int32), ("level_max", C.c_int32),
         ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+        ("field", C.POINTER(Field)),
     ]
+
+
+# The Galactic model of Allen & Santillan (1991) in its own units (1 kpc,
+# 2.32e7 M_sun, G = 1), the external field the paper adds (Sect. 4).
+ALLEN_SANTILLAN_1991 = {"bulge_m": 606.0, "bulge_b": 0.3873,
+                        "disk_m": 3690.0, "disk_a": 5.3178, "disk_b": 0.25,
+                        "halo_m": 4615.0, "halo_a": 12.0, "halo_gamma": 1.02,
+                        "halo_rc": 100.0}
+AS91_MASS_UNIT_MSUN = 2.32e7
+
+
+def allen_santillan(length_unit_kpc: float = 1.0, mass_unit_msun: float = AS91_MASS_UNIT_MSUN):
+    """The Allen & Santillan field in units where the length unit is
+    length_unit_kpc and the mass unit mass_unit_msun (G = 1 in both)."""
+    out = {}
+    for k, val in ALLEN_SANTILLAN_1991.items():
+        if k.endswith("_m"):
+            out[k] = val * AS91_MASS_UNIT_MSUN / mass_unit_msun
+        elif k == "halo_gamma":
+            out[k] = val
+        else:
+            out[k] = val / length_unit_kpc
+    return out
 
 
 class Tuning(C.Structure):
@@ -133,8 +166,9 @@ def _stream_handle(stream):
 
 
 def make_params(n, n_clusters=1, cluster_offsets=None, eps=1e-3, precision=FP64, eta=0.01,
-                eta_start=0.01, dt_shared=0.0, level_min=3, level_max=20):
-    """Host-side parameter block (keeps the numpy arrays it points to alive)."""
+                eta_start=0.01, dt_shared=0.0, level_min=3, level_max=20, field=None):
+    """Host-side parameter block (keeps the numpy arrays it points to alive).
+    field: dict of FIELD_KEYS (missing components off) or None."""
     eps_arr = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, np.float64), (n_clusters,)))
     p = Params()
     p.n_clusters = n_clusters
@@ -149,6 +183,13 @@ def make_params(n, n_clusters=1, cluster_offsets=None, eps=1e-3, precision=FP64,
     p.eps = eps_arr.ctypes.data
     p.eta, p.eta_start, p.dt_shared = float(eta), float(eta_start), float(dt_shared)
     p.level_min, p.level_max = int(level_min), int(level_max)
+    if field is not None:
+        unknown = set(field) - set(FIELD_KEYS)
+        if unknown:
+            raise ValueError(f"unknown field keys {sorted(unknown)}")
+        f = Field(*[float(field.get(k, 0.0)) for k in FIELD_KEYS])
+        keep.append(f)
+        p.field = C.pointer(f)
     p._keep = keep
     return p
 
@@ -163,7 +204,7 @@ class NBody:
 
     def __init__(self, m, x, v, *, cluster_offsets=None, eps=1e-3, precision=FP64, eta=0.01,
                  eta_start=0.01, dt_shared=0.0, level_min=3, level_max=20, stream=None,
-                 device="cuda", tuning=None):
+                 device="cuda", tuning=None, field=None):
         import torch
         self._torch = torch
         m = torch.as_tensor(m, dtype=torch.float64, device=device).contiguous()
@@ -174,7 +215,7 @@ class NBody:
             raise ValueError("x and v must have shape (n, 3)")
         n_clusters = 1 if cluster_offsets is None else len(cluster_offsets) - 1
         self.params = make_params(n, n_clusters, cluster_offsets, eps, precision, eta, eta_start,
-                                  dt_shared, level_min, level_max)
+                                  dt_shared, level_min, level_max, field)
         self.n = n
         self.n_clusters = n_clusters
         self.precision = precision

@@ -130,7 +130,45 @@ int validate_params(const nbody_params *p, int64_t n) {
     return fail(NBODY_EINVAL, "need 0 <= level_min <= level_max <= 20");
   if (p->dt_shared != 0.0 && !is_pow2_step(p->dt_shared, p->level_min, p->level_max, nullptr))
     return fail(NBODY_EINVAL, "dt_shared must be 0 or a power of two within the level range");
+  if (p->field) {
+    const nbody_field &f = *p->field;
+    const double all[] = {f.bulge_m, f.bulge_b, f.disk_m, f.disk_a, f.disk_b,
+                          f.halo_m, f.halo_a, f.halo_gamma, f.halo_rc};
+    for (double q : all)
+      if (!std::isfinite(q)) return fail(NBODY_EINVAL, "field parameters must be finite");
+    if (f.bulge_m < 0.0 || f.disk_m < 0.0 || f.halo_m < 0.0)
+      return fail(NBODY_EINVAL, "field masses must be >= 0");
+    if (f.bulge_m > 0.0 && !(f.bulge_b > 0.0))
+      return fail(NBODY_EINVAL, "field bulge_b must be > 0");
+    if (f.disk_m > 0.0 && (!(f.disk_a >= 0.0) || !(f.disk_b > 0.0)))
+      return fail(NBODY_EINVAL, "field disk needs disk_a >= 0 and disk_b > 0");
+    if (f.halo_m > 0.0 && (!(f.halo_a > 0.0) || !(f.halo_gamma > 0.0) || !(f.halo_rc > 0.0)))
+      return fail(NBODY_EINVAL, "field halo needs halo_a, halo_gamma, halo_rc > 0");
+  }
   return NBODY_OK;
+}
+
+// Device copy of the external field, with the halo's mass inside the
+// cut-off and the constant of its inner potential.
+nbk::Field make_field(const nbody_field *f) {
+  nbk::Field d{};
+  if (!f || (f->bulge_m == 0.0 && f->disk_m == 0.0 && f->halo_m == 0.0)) return d;
+  d.on = 1;
+  d.bm = f->bulge_m;
+  d.bb = f->bulge_b;
+  d.dm = f->disk_m;
+  d.da = f->disk_a;
+  d.db = f->disk_b;
+  d.hm = f->halo_m;
+  d.ha = f->halo_a;
+  d.hg = f->halo_gamma;
+  d.hrc = f->halo_rc;
+  if (d.hm != 0.0) {
+    const double sc = d.hrc / d.ha, scg = std::pow(sc, d.hg);
+    d.hmc = d.hm * sc * scg / (1.0 + scg);
+    d.hpc = -d.hmc / d.hrc - d.hm / (d.hg * d.ha) * std::log1p(scg);
+  }
+  return d;
 }
 
 int device_present(int *dev) {
@@ -518,6 +556,7 @@ int nbody_init(nbody_ctx **out, const nbody_params *p, int64_t n, const double *
   }
   c->T_host.assign(c->C, 0);
   carve(n, c->C, (char *)p->workspace, &c->d);
+  c->d.fld = make_field(p->field);
   c->tune = default_tuning(c->prec);
   auto bail = [&](int code) {
     nbody_destroy(c);

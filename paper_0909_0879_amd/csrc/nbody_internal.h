@@ -77,6 +77,17 @@ enum PlanKind : int {
 };
 
 // Device pointers carved from the caller's workspace.
+// External field (see nbody_field), with the halo constants the host
+// derives: mass inside the cut-off and the potential's inner offset.
+struct Field {
+  double bm, bb;             // bulge mass, scale
+  double dm, da, db;         // disk mass, radial and vertical scales
+  double hm, ha, hg, hrc;    // halo mass scale, radius, exponent, cut-off
+  double hmc;                // M(hrc)
+  double hpc;                // inner potential: hpc + hm / (hg ha) ln(1 + s^hg)
+  int32_t on, pad_;
+};
+
 struct Dev {
   int64_t n;
   int32_t C;
@@ -121,6 +132,7 @@ struct Dev {
   int32_t *err;        // sticky error bits
   int64_t *ctr;        // kCtrCount counters
   double *eout;        // C * 9 energy output
+  Field fld;           // external field (fld.on == 0: none)
 };
 
 // Where the force kernel takes j (and i) particles from: the state

@@ -1090,7 +1090,79 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
   }
 }
 
+// ------------------------------------------------------------ external field
+//
+// The analytic Galactic field that is added to the pairwise forces (Sect. 4):
+// Plummer bulge, Miyamoto-Nagai disk, and a halo whose enclosed mass
+// M(r) = hm s^(hg+1) / (1 + s^hg), s = r / ha, stops growing at hrc.  FP64,
+// a few dozen operations per particle, evaluated where the integrators use
+// a and jerk.  Spherical parts act as a = -G x, jerk = -(G v + H (x.v) x)
+// with G = |a| / r and H = G'(r) / r; the disk term is differentiated along
+// v directly.
+__device__ void ext_field(const Field &f, const double x[3], const double v[3],
+                          double a[3], double jk[3]) {
+  const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+  const double xv = x[0] * v[0] + x[1] * v[1] + x[2] * v[2];
+  double G = 0.0, H = 0.0;
+  if (f.bm != 0.0) {
+    const double q = 1.0 / (r2 + f.bb * f.bb);           // (r^2 + b^2)^-1
+    const double gb = f.bm * q * sqrt(q);
+    G += gb;
+    H -= 3.0 * gb * q;
+  }
+  if (f.hm != 0.0 && r2 > 0.0) {
+    const double r = sqrt(r2);
+    double mr = f.hmc, mp = 0.0;                        // M(r), dM/dr
+    if (r < f.hrc) {
+      const double s = r / f.ha, sg = pow(s, f.hg), w = 1.0 / (1.0 + sg);
+      mr = f.hm * s * sg * w;
+      mp = (f.hm / f.ha) * sg * (f.hg + 1.0 + sg) * w * w;
+    }
+    const double ir3 = 1.0 / (r2 * r);
+    G += mr * ir3;
+    H += (mp - 3.0 * mr / r) * ir3 / r;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    a[c] = -G * x[c];
+    jk[c] = -(G * v[c] + H * xv * x[c]);
+  }
+  if (f.dm != 0.0) {
+    const double z = x[2];
+    const double zeta = sqrt(z * z + f.db * f.db), u = f.da + zeta;
+    const double iD2 = 1.0 / (x[0] * x[0] + x[1] * x[1] + u * u);
+    const double k3 = f.dm * iD2 * sqrt(iD2);           // M / D^3
+    const double w = z * u / zeta;                      // z-component of grad D^2 / 2
+    const double q3 = 3.0 * (x[0] * v[0] + x[1] * v[1] + w * v[2]) * iD2;
+    const double dw = v[2] * (u * f.db * f.db / (zeta * zeta * zeta) + (z * z) / (zeta * zeta));
+    a[0] -= k3 * x[0];
+    a[1] -= k3 * x[1];
+    a[2] -= k3 * w;
+    jk[0] -= k3 * (v[0] - q3 * x[0]);
+    jk[1] -= k3 * (v[1] - q3 * x[1]);
+    jk[2] -= k3 * (dw - q3 * w);
+  }
+}
+
+// Potential of the field per unit mass.
+__device__ double ext_pot(const Field &f, const double x[3]) {
+  const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+  double p = 0.0;
+  if (f.bm != 0.0) p -= f.bm / sqrt(r2 + f.bb * f.bb);
+  if (f.dm != 0.0) {
+    const double u = f.da + sqrt(x[2] * x[2] + f.db * f.db);
+    p -= f.dm / sqrt(x[0] * x[0] + x[1] * x[1] + u * u);
+  }
+  if (f.hm != 0.0) {
+    const double r = sqrt(r2);
+    p += (r < f.hrc) ? f.hpc + f.hm / (f.hg * f.ha) * log1p(pow(r / f.ha, f.hg))
+                     : -f.hmc / r;
+  }
+  return p;
+}
+
 // Hermite-4 correction of every active particle, new level, bookkeeping.
+template <bool FIELD>
 __global__ __launch_bounds__(kWG) void k_correct(Dev d, double eta,
                                                  double dt_shared, int lmin,
                                                  int lmax) {
@@ -1106,19 +1178,30 @@ __global__ __launch_bounds__(kWG) void k_correct(Dev d, double eta,
     const int64_t tn = d.Tnext[c];
     const double h = (double)(tn - d.tick[i]) * kTick;
     const double h2 = h * h, h3 = h2 * h;
-    double x1[3], v1[3], a2e[3], a3v[3], a1[3], j1[3];
+    double x1[3], v1[3], a2e[3], a3v[3], a1[3], j1[3], xp[3], vp[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      predict(d.x[q * n + i], d.v[q * n + i], d.a[q * n + i], d.j[q * n + i], h, xp[q], vp[q]);
+    if (FIELD) {
+      // the external field at the predicted position joins the pair sums
+      double fa[3], fj[3];
+      ext_field(d.fld, xp, vp, fa, fj);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        f[q] += fa[q];
+        f[3 + q] += fj[q];
+      }
+    }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      double xp, vp;
       const double a0 = d.a[q * n + i], j0 = d.j[q * n + i];
-      predict(d.x[q * n + i], d.v[q * n + i], a0, j0, h, xp, vp);
       a1[q] = f[q];
       j1[q] = f[3 + q];
       const double da = a0 - a1[q];
       const double a2 = (-6.0 * da - h * (4.0 * j0 + 2.0 * j1[q])) / h2;
       const double a3 = (12.0 * da + 6.0 * h * (j0 + j1[q])) / h3;
-      x1[q] = xp + a2 * (h2 * h2 / 24.0) + a3 * (h2 * h3 / 120.0);
-      v1[q] = vp + a2 * (h3 / 6.0) + a3 * (h2 * h2 / 24.0);
+      x1[q] = xp[q] + a2 * (h2 * h2 / 24.0) + a3 * (h2 * h3 / 120.0);
+      v1[q] = vp[q] + a2 * (h3 / 6.0) + a3 * (h2 * h2 / 24.0);
       a2e[q] = a2 + h * a3;
       a3v[q] = a3;
     }
@@ -1151,6 +1234,7 @@ __global__ __launch_bounds__(kWG) void k_correct(Dev d, double eta,
 
 // After the initial force evaluation: store a, jerk, choose levels, build
 // the level histograms.
+template <bool FIELD>
 __global__ __launch_bounds__(kWG) void k_init_levels(Dev d, double eta_s,
                                                      double dt_shared,
                                                      int lmin, int lmax) {
@@ -1170,6 +1254,21 @@ __global__ __launch_bounds__(kWG) void k_init_levels(Dev d, double eta_s,
     double f[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) f[q] = d.fsum[6 * i + q];
+    if (FIELD) {
+      // every particle sits at its cluster's time: the field at the state
+      double xs[3], vs[3], fa[3], fj[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        xs[q] = d.x[q * n + i];
+        vs[q] = d.v[q * n + i];
+      }
+      ext_field(d.fld, xs, vs, fa, fj);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        f[q] += fa[q];
+        f[3 + q] += fj[q];
+      }
+    }
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       d.a[q * n + i] = f[q];
@@ -1503,20 +1602,42 @@ __global__ __launch_bounds__(kWG) void k_force_sb(ForceArgs A) {
 // state, with the accelerations of the last evaluation in fsum (entry k =
 // particle k: every particle is active).  A stage of step c = w h is
 //   v += (pending + c / 2) a;  x += c v;  a = F(x);  pending = c / 2,
-// so consecutive half kicks merge and each stage costs one evaluation.
+// so consecutive half kicks merge and each stage costs one evaluation.  The
+// external field's acceleration at the current positions (those fsum was
+// evaluated at) is added in the kick itself.
+
+// Pairwise plus external acceleration of particle i at its current position.
+template <bool FIELD>
+__device__ __forceinline__ void sym_acc(const Dev &d, int64_t i, double acc[3]) {
+  const int64_t n = d.n;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) acc[c] = d.fsum[6 * i + c];
+  if (FIELD) {
+    double xs[3], fa[3], fj[3];
+    const double zero[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xs[c] = d.x[c * n + i];
+    ext_field(d.fld, xs, zero, fa, fj);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] += fa[c];
+  }
+}
 
 // Kick by ck, then drift by cd.  check: every particle must sit at its
 // cluster's time (no particle in the middle of a block step).
+template <bool FIELD>
 __global__ void k_sym_kick_drift(Dev d, double ck, double cd, int check) {
   const int64_t n = d.n;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     if (check && d.tick[i] != d.T[d.cid[i]]) atomicOr(d.err, kErrState);
     bool fin = true;
+    double acc[3];
+    sym_acc<FIELD>(d, i, acc);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       double v = d.v[c * n + i];
-      if (ck != 0.0) v = fma(ck, d.fsum[6 * i + c], v);
+      if (ck != 0.0) v = fma(ck, acc[c], v);
       const double x = fma(cd, v, d.x[c * n + i]);
       d.v[c * n + i] = v;
       d.x[c * n + i] = x;
@@ -1526,14 +1647,17 @@ __global__ void k_sym_kick_drift(Dev d, double ck, double cd, int check) {
   }
 }
 
+template <bool FIELD>
 __global__ void k_sym_kick(Dev d, double ck) {
   const int64_t n = d.n;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     bool fin = true;
+    double acc[3];
+    sym_acc<FIELD>(d, i, acc);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double v = fma(ck, d.fsum[6 * i + c], d.v[c * n + i]);
+      const double v = fma(ck, acc[c], d.v[c * n + i]);
       d.v[c * n + i] = v;
       fin = fin && isfinite(v);
     }
@@ -1768,15 +1892,16 @@ __global__ __launch_bounds__(kWG) void k_ref_final(Dev d) {
 }
 
 // Per-cluster diagnostics: one workgroup per cluster, fixed-order sums.
+template <bool FIELD>
 __global__ __launch_bounds__(kWG) void k_energy_reduce(Dev d) {
   __shared__ double sh[kWG][2];
   const int c = blockIdx.x;
   const ClusterPlan cp = d.plan_c[c];
   const int64_t b = d.coff[c], e = d.coff[c + 1];
   const int64_t T = d.T[c];
-  // quantities: K, W, Lx, Ly, Lz, Px, Py, Pz
-  double s[8], cc[8];
-  for (int q = 0; q < 8; ++q) s[q] = cc[q] = 0.0;
+  // quantities: K, W, Lx, Ly, Lz, Px, Py, Pz, external potential energy
+  double s[9], cc[9];
+  for (int q = 0; q < 9; ++q) s[q] = cc[q] = 0.0;
   auto add = [&](int q, double x) {
     const double u = s[q] + x;
     cc[q] += (fabs(s[q]) >= fabs(x)) ? (s[q] - u) + x : (x - u) + s[q];
@@ -1796,9 +1921,10 @@ __global__ __launch_bounds__(kWG) void k_energy_reduce(Dev d) {
     add(5, m * vp[0]);
     add(6, m * vp[1]);
     add(7, m * vp[2]);
+    if (FIELD) add(8, m * ext_pot(d.fld, xp));
   }
-  double out[8];
-  for (int q = 0; q < 8; ++q) {
+  double out[9];
+  for (int q = 0; q < 9; ++q) {
     sh[threadIdx.x][0] = s[q];
     sh[threadIdx.x][1] = cc[q];
     __syncthreads();
@@ -1820,7 +1946,7 @@ __global__ __launch_bounds__(kWG) void k_energy_reduce(Dev d) {
     double *o = d.eout + 9 * (int64_t)c;
     o[0] = out[0];
     o[1] = out[1];
-    o[2] = out[0] + out[1];
+    o[2] = out[0] + out[1] + out[8];
     for (int q = 0; q < 6; ++q) o[3 + q] = out[2 + q];
   }
 }
@@ -2046,13 +2172,20 @@ int force_grid_size(int mode, int src, int K, int device) {
 
 hipError_t launch_sym_kick_drift(const Dev &d, double ck, double cd, bool check,
                                  hipStream_t s) {
-  hipLaunchKernelGGL(k_sym_kick_drift, dim3(grid_for(d.n)), dim3(kWG), 0, s, d, ck, cd,
-                     check ? 1 : 0);
+  if (d.fld.on)
+    hipLaunchKernelGGL(k_sym_kick_drift<true>, dim3(grid_for(d.n)), dim3(kWG), 0, s, d, ck,
+                       cd, check ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_sym_kick_drift<false>, dim3(grid_for(d.n)), dim3(kWG), 0, s, d, ck,
+                       cd, check ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_sym_kick(const Dev &d, double ck, hipStream_t s) {
-  hipLaunchKernelGGL(k_sym_kick, dim3(grid_for(d.n)), dim3(kWG), 0, s, d, ck);
+  if (d.fld.on)
+    hipLaunchKernelGGL(k_sym_kick<true>, dim3(grid_for(d.n)), dim3(kWG), 0, s, d, ck);
+  else
+    hipLaunchKernelGGL(k_sym_kick<false>, dim3(grid_for(d.n)), dim3(kWG), 0, s, d, ck);
   return hipGetLastError();
 }
 
@@ -2154,16 +2287,24 @@ hipError_t launch_refine_finalize(const Dev &d, hipStream_t s) {
 
 hipError_t launch_correct(const Dev &d, double eta, double dt_shared,
                           int level_min, int level_max, hipStream_t s) {
-  hipLaunchKernelGGL(k_correct, dim3(grid_for(d.n, kWG, 2048)), dim3(kWG), 0, s,
-                     d, eta, dt_shared, level_min, level_max);
+  if (d.fld.on)
+    hipLaunchKernelGGL(k_correct<true>, dim3(grid_for(d.n, kWG, 2048)), dim3(kWG), 0, s,
+                       d, eta, dt_shared, level_min, level_max);
+  else
+    hipLaunchKernelGGL(k_correct<false>, dim3(grid_for(d.n, kWG, 2048)), dim3(kWG), 0, s,
+                       d, eta, dt_shared, level_min, level_max);
   return hipGetLastError();
 }
 
 hipError_t launch_init_levels(const Dev &d, double eta_start, double dt_shared,
                               int level_min, int level_max, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_levels, dim3((unsigned)((d.n + kWG - 1) / kWG)),
-                     dim3(kWG), 0, s, d, eta_start, dt_shared, level_min,
-                     level_max);
+  const dim3 g((unsigned)((d.n + kWG - 1) / kWG));
+  if (d.fld.on)
+    hipLaunchKernelGGL(k_init_levels<true>, g, dim3(kWG), 0, s, d, eta_start, dt_shared,
+                       level_min, level_max);
+  else
+    hipLaunchKernelGGL(k_init_levels<false>, g, dim3(kWG), 0, s, d, eta_start, dt_shared,
+                       level_min, level_max);
   return hipGetLastError();
 }
 
@@ -2181,7 +2322,10 @@ hipError_t launch_api_finalize(const Dev &d, const RawSrc &r, hipStream_t s) {
 }
 
 hipError_t launch_energy_reduce(const Dev &d, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy_reduce, dim3(d.C), dim3(kWG), 0, s, d);
+  if (d.fld.on)
+    hipLaunchKernelGGL(k_energy_reduce<true>, dim3(d.C), dim3(kWG), 0, s, d);
+  else
+    hipLaunchKernelGGL(k_energy_reduce<false>, dim3(d.C), dim3(kWG), 0, s, d);
   return hipGetLastError();
 }
 

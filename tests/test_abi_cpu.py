@@ -76,6 +76,32 @@ def test_invalid_params_rejected_on_host(bad):
     assert lib.nbody_last_error().decode()
 
 
+def test_field_parameters_checked_on_host():
+    lib = binding.lib()
+    good = binding.allen_santillan()
+    p = _params(field=good)
+    assert lib.nbody_workspace_bytes(C.byref(p), 16) > 0
+    # scaling to other units keeps the model's dimensionless shape
+    f = binding.allen_santillan(length_unit_kpc=1e-3, mass_unit_msun=1e5)
+    assert f["halo_gamma"] == good["halo_gamma"]
+    assert f["disk_a"] / f["disk_b"] == good["disk_a"] / good["disk_b"]
+    assert abs(f["bulge_m"] / good["bulge_m"] - 2.32e7 / 1e5) < 1e-9
+    for bad in (dict(disk_b=0.0), dict(bulge_b=0.0), dict(halo_a=0.0), dict(halo_rc=-1.0),
+                dict(halo_gamma=0.0), dict(disk_a=-1.0), dict(bulge_m=-1.0),
+                dict(halo_m=float("nan")), dict(disk_a=float("inf"))):
+        p = _params(field={**good, **bad})
+        assert lib.nbody_workspace_bytes(C.byref(p), 16) == 0, bad
+    # a switched-off component needs no valid scales
+    p = _params(field={"bulge_m": 0.0, "bulge_b": 0.0, "halo_m": 1.0, "halo_a": 2.0,
+                       "halo_gamma": 1.0, "halo_rc": 10.0})
+    assert lib.nbody_workspace_bytes(C.byref(p), 16) > 0
+    try:
+        binding.make_params(16, field={"bulge_mass": 1.0})
+        raise AssertionError("unknown key accepted")
+    except ValueError:
+        pass
+
+
 def test_bad_cluster_offsets_rejected():
     lib = binding.lib()
     for off in ([0, 10, 10, 16], [1, 10, 16], [0, 10, 15]):
