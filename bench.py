@@ -46,13 +46,14 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="headline",
                     choices=("headline", "sweep", "ensemble", "blocksteps", "kingsteps",
-                             "symplectic"),
+                             "symplectic", "galactic"),
                     help="headline: the contract line (default); sweep: n_active sweep of "
                          "the King 2^20 evaluation; ensemble: 256-cluster block steps; "
                          "blocksteps: Plummer 65536 FP64 and Salpeter 262144 mixed runs; "
                          "kingsteps: King 2^20 mixed block steps (real active sets); "
                          "symplectic: time per leapfrog / sixth-order step vs N on the "
-                         "paper's uniform-sphere initial conditions")
+                         "paper's uniform-sphere initial conditions; galactic: a cluster on "
+                         "a Galactic orbit with and without the external field")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (to scale the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -229,13 +230,13 @@ def sweep(binding, torch, ics, n):
 
 def run_blocksteps(binding, torch, label, m, x, v, t_end, precision, cluster_offsets=None,
                    eps=1e-3, level_min=3, chunks=8, dt_shared=0.0, level_max=20,
-                   oracle_time=False):
+                   oracle_time=False, field=None):
     """Hermite-4 block steps to t_end in `chunks` equal calls (the largest
     step 2^-level_min divides each chunk); progress to stderr per chunk.
     oracle_time: also run the CPU oracle over the same steps (small N)."""
     g = binding.NBody(m, x, v, eps=eps, precision=precision, eta=0.01, eta_start=0.01,
                       dt_shared=dt_shared, level_min=level_min, level_max=level_max,
-                      cluster_offsets=cluster_offsets, tuning="auto")
+                      cluster_offsets=cluster_offsets, tuning="auto", field=field)
     e0 = g.energy()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -251,6 +252,7 @@ def run_blocksteps(binding, torch, label, m, x, v, t_end, precision, cluster_off
     e1 = g.energy()
     st = g.stats()
     de = abs(e1[:, 2] - e0[:, 2]) / abs(e0[:, 2])
+    de_w = abs(e1[:, 2] - e0[:, 2]) / abs(e0[:, 1])     # against the clusters' own |W|
     lz = abs(e1[:, 5] - e0[:, 5])
     q_vir = 2 * e1[:, 0] / abs(e1[:, 1])
     dp = (e1[:, 6:9] - e0[:, 6:9])
@@ -258,6 +260,7 @@ def run_blocksteps(binding, torch, label, m, x, v, t_end, precision, cluster_off
            "clusters": int(e0.shape[0]), "t_end": t_end, "block_steps": steps,
            "interactions": inter, "wall_s": wall, "interactions_per_s": inter / wall,
            "dE_over_E_max": float(de.max()), "dE_over_E_median": float(sorted(de)[len(de) // 2]),
+           "dE_over_W_max": float(de_w.max()), "external_field": field is not None,
            "dLz_max": float(lz.max()), "dP_max": float(abs(dp).max()),
            "virial_Q_median": float(sorted(q_vir)[len(q_vir) // 2]),
            "floor_clamps": st["floor_clamps"]}
@@ -273,6 +276,26 @@ def run_blocksteps(binding, torch, label, m, x, v, t_end, precision, cluster_off
         out["oracle_cores"] = oracle.threads()
         out["oracle_dE_over_E"] = abs(oracle.energy(ref.x, ref.v, m, eps)["E"] - e_ref0) / abs(e_ref0)
     print(json.dumps(out), flush=True)
+
+
+def galactic(binding, torch, ics):
+    """A Plummer cluster of 65536 stars (units 1e5 M_sun, 1 pc) on a circular
+    orbit at 8.5 kpc in the Allen & Santillan field, mixed block steps to
+    t = 1/16 with the field and, for the cost of the field, without it."""
+    import numpy as np
+    f = binding.allen_santillan(length_unit_kpc=1e-3, mass_unit_msun=1e5)
+    R = 8.5e3
+    # circular speed from the field's pull on one star (its stored acceleration)
+    probe = binding.NBody([1e-12], [[R, 0.0, 0.0]], [[0.0, 0.0, 0.0]], eps=0.0, field=f,
+                          level_min=0, level_max=20)
+    vc = float(np.sqrt(R * -probe.get_state()["a"][0, 0].item()))
+    probe.close()
+    m, x, v = ics.plummer(65536, 6)
+    x = x + np.array([R, 0.0, 0.0])
+    v = v + np.array([0.0, vc, 0.0])
+    for fld, label in ((f, "galactic65536"), (None, "galactic65536-nofield")):
+        run_blocksteps(binding, torch, label, m, x, v, 1 / 16, binding.MIXED, eps=1e-3,
+                       level_min=7, chunks=8, field=fld)
 
 
 def symplectic_scaling(binding, torch, ics, with_cpu):
@@ -381,6 +404,9 @@ def main():
         return
     if a.workload == "symplectic":
         symplectic_scaling(binding, torch, ics, not a.no_cpu)
+        return
+    if a.workload == "galactic":
+        galactic(binding, torch, ics)
         return
     if a.workload == "blocksteps":
         m, x, v = ics.plummer(1024, 1)

@@ -35,7 +35,10 @@
 //    FP32 and folds the FP32 sums of every 64 j into an FP32 TwoSum
 //    (hi, lo) pair;
 //  * the same kernels in acceleration-only modes serve the paper's
-//    symplectic drivers (kick / drift sweeps between evaluations).
+//    symplectic drivers (kick / drift sweeps between evaluations);
+//  * the external Galactic field (Sect. 4) is O(N) and rides in the kernels
+//    that use the acceleration (corrector, initial store, symplectic kicks,
+//    energy), as compile-time variants launched only when a field is set.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
