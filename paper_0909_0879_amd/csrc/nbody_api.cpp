@@ -374,12 +374,14 @@ float refine_ratio(const nbody_ctx *c) {
 int sum_and_refine(nbody_ctx *c, const int32_t *list, int64_t na_host, const nbk::RawSrc *raw,
                    hipStream_t s, bool acc_only = false) {
   const float ratio = refine_ratio(c);
-  NB_HIP(nbk::launch_sum_and_flag(c->d, list, na_host, ratio, s));
-  if (ratio <= 0.0f) return NBODY_OK;
   const nbk::Tuning t1 = device_tuning(c, 1);
   const bool api = raw != nullptr;
-  NB_HIP(nbk::launch_plan(c->d, t1, api ? nbk::kPlanApiRefine : nbk::kPlanRefine,
-                          api ? raw->n_j : 0, false, s));
+  const int ref_kind = api ? nbk::kPlanApiRefine : nbk::kPlanRefine;
+  const int64_t api_nj = api ? raw->n_j : 0;
+  NB_HIP(nbk::launch_sum_and_flag(c->d, list, na_host, ratio, t1, ref_kind, api_nj, s));
+  if (ratio <= 0.0f) return NBODY_OK;
+  if (!nbk::plan_fused(c->d))
+    NB_HIP(nbk::launch_plan(c->d, t1, ref_kind, api_nj, false, s));
   const int grid = acc_only ? (api ? c->grid_ref_acc_raw : c->grid_ref_acc_state)
                             : (api ? c->grid_ref_raw : c->grid_ref_state);
   int rc = force_launch(c, acc_only ? nbk::kModeFP64Acc : nbk::kModeFP64,
@@ -392,8 +394,10 @@ int sum_and_refine(nbody_ctx *c, const int32_t *list, int64_t na_host, const nbk
 // One Hermite block step for every cluster, enqueued on s.
 int enqueue_block_step(nbody_ctx *c, hipStream_t s) {
   const nbk::Tuning t = device_tuning(c, c->K);
-  NB_HIP(nbk::launch_compact(c->d, s));
-  NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanStep, 0, c->prec == NBODY_MIXED, s));
+  const bool allow_small = c->prec == NBODY_MIXED;
+  NB_HIP(nbk::launch_compact(c->d, t, allow_small, s));
+  if (!nbk::plan_fused(c->d))
+    NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanStep, 0, allow_small, s));
   int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->d.active,
                         c->grid_state, s, nbk::kPlanStep);
   if (rc) return rc;
@@ -444,8 +448,8 @@ int take_error(nbody_ctx *c) {
 int full_evaluation_into_state(nbody_ctx *c) {
   // initial forces: every particle active, predicted to its own time
   const nbk::Tuning t = device_tuning(c, c->K);
-  NB_HIP(nbk::launch_all_active(c->d, c->stream));
-  NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, false, c->stream));
+  NB_HIP(nbk::launch_all_active(c->d, t, c->stream));
+  if (c->C > 1) NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, false, c->stream));
   int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->d.active,
                         c->grid_state, c->stream, nbk::kPlanState);
   if (rc) return rc;
@@ -627,9 +631,11 @@ int nbody_step_symplectic(nbody_ctx *c, int scheme, double h, int64_t n_steps,
   }
   const int mode = acc_mode_of(c);
   const nbk::Tuning t = device_tuning(c, c->K);
-  NB_HIP(nbk::launch_all_active(c->d, c->stream));
+  // with one cluster the kernel before each evaluation (the all-active
+  // setup, then every kick-drift) writes its plan
+  NB_HIP(nbk::launch_all_active(c->d, t, c->stream));
   auto evaluate = [&](hipStream_t s) -> int {
-    NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, false, s));
+    if (c->C > 1) NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, false, s));
     int r = force_launch(c, mode, nbk::kSrcState, c->K, nullptr, c->d.active, c->grid_acc_state,
                          s, nbk::kPlanState);
     if (r) return r;
@@ -640,7 +646,7 @@ int nbody_step_symplectic(nbody_ctx *c, int scheme, double h, int64_t n_steps,
   auto enqueue_step = [&](hipStream_t s, double pending, bool check, double *owed) -> int {
     for (double wk : w) {
       const double cw = wk * h;
-      NB_HIP(nbk::launch_sym_kick_drift(c->d, pending + 0.5 * cw, cw, check, s));
+      NB_HIP(nbk::launch_sym_kick_drift(c->d, pending + 0.5 * cw, cw, check, t, s));
       check = false;
       int r = evaluate(s);
       if (r) return r;
@@ -775,8 +781,8 @@ int nbody_step_blocks(nbody_ctx *c, double t_end, int64_t max_block_steps,
 int nbody_energy(nbody_ctx *c, double *out) {
   if (!c || !out) return fail(NBODY_EINVAL, "NULL argument");
   const nbk::Tuning t = device_tuning(c, 1);
-  NB_HIP(nbk::launch_all_active(c->d, c->stream));
-  NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, false, c->stream));
+  NB_HIP(nbk::launch_all_active(c->d, t, c->stream));
+  if (c->C > 1) NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, false, c->stream));
   int rc0 = force_launch(c, nbk::kModePot, nbk::kSrcState, 1, nullptr, c->d.active, c->grid_pot,
                          c->stream);
   if (rc0) return rc0;

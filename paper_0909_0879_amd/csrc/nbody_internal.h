@@ -164,10 +164,16 @@ struct RawSrc {                 // caller arrays for nbody_forces
 
 hipError_t launch_init_state(const Dev &d, const double *m, const double *x,
                              const double *v, hipStream_t s);
-hipError_t launch_all_active(const Dev &d, hipStream_t s);
+// Every particle active; with one cluster also the kPlanState plan (tuning t).
+hipError_t launch_all_active(const Dev &d, const Tuning &t, hipStream_t s);
+// One-cluster contexts whose compaction takes its block prefixes itself:
+// the compaction kernels also write the plan that follows (launch_compact
+// the block step's, launch_sum_and_flag the re-evaluation's), and the
+// separate launch_plan is skipped.
+bool plan_fused(const Dev &d);
 // Scheduler (per-cluster T_next and threshold level) and ordered compaction
-// of the due particles into the active list.
-hipError_t launch_compact(const Dev &d, hipStream_t s);
+// of the due particles into the active list (plan: see plan_fused).
+hipError_t launch_compact(const Dev &d, const Tuning &t, bool allow_small, hipStream_t s);
 // allow_small: clusters of a block step with at most kSmallStep active
 // particles are planned for the small-step FP64 launch (mixed contexts).
 hipError_t launch_plan(const Dev &d, const Tuning &t, int kind,
@@ -176,7 +182,8 @@ hipError_t launch_plan(const Dev &d, const Tuning &t, int kind,
 // flag entries whose largest acceleration term exceeds refine_ratio times
 // their net acceleration, and build the grouped re-evaluation list.
 hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_host,
-                               float refine_ratio, hipStream_t s);
+                               float refine_ratio, const Tuning &t1, int ref_kind,
+                               int64_t api_nj, hipStream_t s);
 hipError_t launch_refine_finalize(const Dev &d, hipStream_t s);
 // Which work a force launch takes.  The plan splits the items in two:
 // [0, work[2]) for the main launches, [work[2], total) for the small-step
@@ -202,10 +209,11 @@ hipError_t launch_records(const Dev &d, int mode, int kind, const RawSrc *raw,
 hipError_t launch_force_sb(const Dev &d, int mode, int K, const RawSrc *raw,
                            const int32_t *list, int grid, hipStream_t s);
 int force_sb_grid_size(int mode, int K, int device);
-// Symplectic drivers: kick (v += ck a, a from fsum) then drift (x += cd v);
+// Symplectic drivers: kick (v += ck a, a from fsum) then drift (x += cd v)
+// (with one cluster also the next evaluation's kPlanState plan, tuning t);
 // final kick; advance all times by dticks.
 hipError_t launch_sym_kick_drift(const Dev &d, double ck, double cd, bool check,
-                                 hipStream_t s);
+                                 const Tuning &t, hipStream_t s);
 hipError_t launch_sym_kick(const Dev &d, double ck, hipStream_t s);
 hipError_t launch_sym_advance(const Dev &d, int64_t dticks, hipStream_t s);
 hipError_t launch_correct(const Dev &d, double eta, double dt_shared,

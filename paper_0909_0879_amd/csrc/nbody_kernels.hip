@@ -752,12 +752,104 @@ __global__ void k_init_state(Dev d, const double *m, const double *x,
   if (gt == 0) *d.err = 0;
 }
 
-__global__ void k_all_active(Dev d) {
+// Launch plan of cluster c whose active entries are [act_off, act_off + na):
+// i-slots per workgroup from the tuning bucket of na, j-splits from the
+// target item count (bounded by the split size and the partial rows), the
+// items, and whether the FP64 small-step launch takes it.  row_off is left
+// to the caller.
+__device__ ClusterPlan plan_cluster(const Dev &d, const Tuning &tu, int kind, int64_t api_nj,
+                                    int allow_small, int c, int32_t act_off, int32_t na) {
+  const bool api = (kind == kPlanApi || kind == kPlanApiRefine);
+  const int K = tu.K;
+  ClusterPlan p;
+  p.c = c;
+  p.P = 256;
+  p.Qlog = 0;
+  p.S = 0;
+  p.na = na;
+  p.act_off = act_off;
+  p.tiles = 0;
+  p.items = 0;
+  p.row_off = 0;
+  p.chunk = kTJ;
+  p.small = 0;
+  p.pad_ = 0;
+  if (api && d.C == 1 && api_nj > 0) {
+    p.jb = 0;
+    p.je = api_nj;
+  } else {
+    p.jb = d.coff[c];
+    p.je = d.coff[c + 1];
+  }
+  const int64_t nc = p.je - p.jb;
+  p.t_pred = (kind == kPlanStep || kind == kPlanRefine) ? d.Tnext[c] : d.T[c];
+  if (p.na > 0 && nc > 0) {
+    int b = 31 - __builtin_clz((unsigned)p.na);
+    if (b >= kBuckets) b = kBuckets - 1;
+    int P = tu.i_slots[b];
+    if (P < 1) P = 1;
+    if (P > 256) P = 256;
+    P = 1 << (31 - __builtin_clz((unsigned)P));      // power of two
+    p.P = P;
+    p.Qlog = 8 - (31 - __builtin_clz((unsigned)P));
+    const int64_t ipt = (int64_t)P * K;
+    const int64_t tiles = (p.na + ipt - 1) / ipt;
+    int64_t target = tu.target_items[b] > 0 ? tu.target_items[b] : 1;
+    int64_t S = (target + tiles - 1) / tiles;
+    const int64_t mj = tu.min_split_j > 0 ? tu.min_split_j : 64;
+    const int64_t s_j = (nc + mj - 1) / mj;
+    if (S > s_j) S = s_j;
+    // partial rows of a cluster: at most 4 per j-particle (so an ensemble
+    // needs at most 4 n rows, and a cluster splits the same way alone or
+    // in an ensemble), and never more than the workspace holds
+    int64_t rowcap = 4 * nc;
+    if (rowcap > d.rows_cap) rowcap = d.rows_cap;
+    const int64_t s_r = rowcap / p.na;
+    if (S > s_r) S = s_r;
+    if (S < 1) S = 1;
+    int64_t chunk = (nc + S - 1) / S;
+    chunk = ((chunk + kTJ - 1) / kTJ) * kTJ;
+    S = (nc + chunk - 1) / chunk;
+    p.S = (int32_t)S;
+    p.chunk = chunk;
+    p.tiles = (int32_t)tiles;
+    p.items = (int32_t)(tiles * S);
+    p.small = (allow_small && kind == kPlanStep && p.na <= kSmallStep) ? 1 : 0;
+  }
+  return p;
+}
+
+// The whole plan of a one-cluster context, by one thread: what k_plan
+// writes for C = 1 (the only cluster is first in every order).  Run by the
+// compaction that produced the active count, which saves a launch.
+__device__ void plan_single(const Dev &d, const Tuning &tu, int kind, int64_t api_nj,
+                            int allow_small, int32_t na) {
+  const ClusterPlan p = plan_cluster(d, tu, kind, api_nj, allow_small, 0, 0, na);
+  d.plan_c[0] = p;
+  d.plan_lpt[0] = p;
+  d.item_prefix[0] = 0;
+  d.item_prefix[1] = p.items;
+  d.work[0] = 0;
+  d.work[1] = 0;
+  d.work[2] = p.small ? 0 : p.items;
+  if (kind == kPlanStep) {
+    d.T[0] = d.Tnext[0];
+    if (p.items > 0) {
+      d.ctr[kCtrInter] += (int64_t)p.na * (p.je - p.jb);
+      d.ctr[kCtrSteps] += 1;
+    }
+    d.ctr[kCtrNotDone] = (d.Tnext[0] < d.ctr[kCtrTend]) ? 1 : 0;
+  }
+}
+
+__global__ void k_all_active(Dev d, Tuning tu, int plan_kind) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < d.n;
        i += (int64_t)gridDim.x * blockDim.x)
     d.active[i] = (int32_t)i;
   const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (gt <= d.C) d.act_off[gt] = (int32_t)d.coff[gt];
+  // one cluster: every particle is active, so the plan needs nothing more
+  if (gt == 0 && plan_kind >= 0) plan_single(d, tu, plan_kind, 0, 0, (int32_t)d.n);
 }
 
 // Next block-step time and threshold level of cluster c: T_next is the next
@@ -852,7 +944,8 @@ __global__ __launch_bounds__(1024) void k_scan(Dev d) {
 // cluster's offset in it.  FUSED: the block sums the counts before it
 // itself (no k_scan).
 template <bool FUSED>
-__global__ __launch_bounds__(kWG) void k_scatter(Dev d) {
+__global__ __launch_bounds__(kWG) void k_scatter(Dev d, Tuning tu, int plan_kind,
+                                                 int allow_small) {
   __shared__ int wsum[4];
   __shared__ int sh4[4];
   const int bpre = FUSED ? block_prefix(d, blockIdx.x, sh4) : d.blk_off[blockIdx.x];
@@ -888,7 +981,11 @@ __global__ __launch_bounds__(kWG) void k_scatter(Dev d) {
     }
   }
   if (FUSED) {
-    if (blockIdx.x == d.nblk - 1 && threadIdx.x == kWG - 1) d.act_off[d.C] = pos;
+    if (blockIdx.x == d.nblk - 1 && threadIdx.x == kWG - 1) {
+      d.act_off[d.C] = pos;
+      // one cluster: the active count is known here, so plan here
+      if (plan_kind >= 0) plan_single(d, tu, plan_kind, 0, allow_small, pos);
+    }
   } else if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.act_off[d.C] = d.blk_off[d.nblk];
   }
@@ -926,7 +1023,6 @@ template <int QN>
 __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
                                                 int64_t api_nj, int allow_small) {
   const bool refine = (kind == kPlanRefine || kind == kPlanApiRefine);
-  const bool api = (kind == kPlanApi || kind == kPlanApiRefine);
   const int32_t *offs = refine ? d.ref_off : d.act_off;
   __shared__ uint64_t key[QN * 1024];           // LPT order key per cluster
   __shared__ int32_t items_by_rank[QN * 1024];
@@ -941,65 +1037,16 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
   for (int q = 0; q < QN; ++q) {
     const int c = tid + 1024 * q;
     ClusterPlan &p = cp[q];
-    p.c = c;
-    p.P = 256;
-    p.Qlog = 0;
-    p.S = 0;
-    p.na = 0;
-    p.act_off = 0;
-    p.tiles = 0;
-    p.items = 0;
-    p.row_off = 0;
-    p.jb = p.je = 0;
-    p.chunk = kTJ;
-    p.t_pred = 0;
-    p.small = 0;
-    p.pad_ = 0;
-    if (c >= C) continue;
-    p.act_off = offs[c];
-    p.na = offs[c + 1] - p.act_off;
-    if (api && C == 1 && api_nj > 0) {
-      p.jb = 0;
-      p.je = api_nj;
-    } else {
-      p.jb = d.coff[c];
-      p.je = d.coff[c + 1];
+    if (c >= C) {
+      p = ClusterPlan{};
+      p.c = c;
+      p.P = 256;
+      p.chunk = kTJ;
+      continue;
     }
-    const int64_t nc = p.je - p.jb;
-    p.t_pred = (kind == kPlanStep || kind == kPlanRefine) ? d.Tnext[c] : d.T[c];
-    if (p.na > 0 && nc > 0) {
-      int b = 31 - __builtin_clz((unsigned)p.na);
-      if (b >= kBuckets) b = kBuckets - 1;
-      int P = tu.i_slots[b];
-      if (P < 1) P = 1;
-      if (P > 256) P = 256;
-      P = 1 << (31 - __builtin_clz((unsigned)P));      // power of two
-      p.P = P;
-      p.Qlog = 8 - (31 - __builtin_clz((unsigned)P));
-      const int64_t ipt = (int64_t)P * K;
-      const int64_t tiles = (p.na + ipt - 1) / ipt;
-      int64_t target = tu.target_items[b] > 0 ? tu.target_items[b] : 1;
-      int64_t S = (target + tiles - 1) / tiles;
-      const int64_t mj = tu.min_split_j > 0 ? tu.min_split_j : 64;
-      const int64_t s_j = (nc + mj - 1) / mj;
-      if (S > s_j) S = s_j;
-      // partial rows of a cluster: at most 4 per j-particle (so an ensemble
-      // needs at most 4 n rows, and a cluster splits the same way alone or
-      // in an ensemble), and never more than the workspace holds
-      int64_t rowcap = 4 * nc;
-      if (rowcap > d.rows_cap) rowcap = d.rows_cap;
-      const int64_t s_r = rowcap / p.na;
-      if (S > s_r) S = s_r;
-      if (S < 1) S = 1;
-      int64_t chunk = (nc + S - 1) / S;
-      chunk = ((chunk + kTJ - 1) / kTJ) * kTJ;
-      S = (nc + chunk - 1) / chunk;
-      p.S = (int32_t)S;
-      p.chunk = chunk;
-      p.tiles = (int32_t)tiles;
-      p.items = (int32_t)(tiles * S);
-      p.small = (allow_small && kind == kPlanStep && p.na <= kSmallStep) ? 1 : 0;
-      my_inter += (int64_t)p.na * nc;
+    p = plan_cluster(d, tu, kind, api_nj, allow_small, c, offs[c], offs[c + 1] - offs[c]);
+    if (p.items > 0) {
+      my_inter += (int64_t)p.na * (p.je - p.jb);
       my_active += p.na;
     }
     if (kind == kPlanStep && d.Tnext[c] < d.ctr[kCtrTend]) ++my_notdone;
@@ -1629,8 +1676,12 @@ __device__ __forceinline__ void sym_acc(const Dev &d, int64_t i, double acc[3]) 
 // Kick by ck, then drift by cd.  check: every particle must sit at its
 // cluster's time (no particle in the middle of a block step).
 template <bool FIELD>
-__global__ void k_sym_kick_drift(Dev d, double ck, double cd, int check) {
+__global__ void k_sym_kick_drift(Dev d, double ck, double cd, int check, Tuning tu,
+                                 int plan_kind) {
   const int64_t n = d.n;
+  // one cluster: plan the evaluation that follows (every particle active)
+  if (blockIdx.x == 0 && threadIdx.x == 0 && plan_kind >= 0)
+    plan_single(d, tu, plan_kind, 0, 0, (int32_t)n);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     if (check && d.tick[i] != d.T[d.cid[i]]) atomicOr(d.err, kErrState);
@@ -1799,7 +1850,8 @@ __global__ __launch_bounds__(kWG) void k_rcount(Dev d, int64_t na_host) {
 // publishes the total (and, for one cluster, the re-evaluation offsets).
 template <bool FUSED>
 __global__ __launch_bounds__(kWG) void k_rscatter(Dev d, const int32_t *list,
-                                                  int64_t na_host) {
+                                                  int64_t na_host, Tuning tu, int plan_kind,
+                                                  int64_t api_nj) {
   __shared__ int wsum[4];
   __shared__ int sh4[4];
   const int bpre = FUSED ? block_prefix(d, blockIdx.x, sh4) : d.blk_off[blockIdx.x];
@@ -1840,6 +1892,8 @@ __global__ __launch_bounds__(kWG) void k_rscatter(Dev d, const int32_t *list,
       d.ref_off[0] = 0;
       d.ref_off[1] = pos;
       d.ctr[kCtrRefined] += pos;
+      // nor the re-evaluation's k_plan
+      if (plan_kind >= 0) plan_single(d, tu, plan_kind, api_nj, 0, pos);
     }
   }
 }
@@ -2065,20 +2119,24 @@ hipError_t launch_init_state(const Dev &d, const double *m, const double *x,
   return hipGetLastError();
 }
 
-hipError_t launch_all_active(const Dev &d, hipStream_t s) {
+hipError_t launch_all_active(const Dev &d, const Tuning &t, hipStream_t s) {
   int64_t need = d.n > d.C + 1 ? d.n : d.C + 1;
   hipLaunchKernelGGL(k_all_active, dim3((unsigned)((need + kWG - 1) / kWG)),
-                     dim3(kWG), 0, s, d);
+                     dim3(kWG), 0, s, d, t, d.C == 1 ? (int)kPlanState : -1);
   return hipGetLastError();
 }
 
-hipError_t launch_compact(const Dev &d, hipStream_t s) {
+bool plan_fused(const Dev &d) { return d.C == 1 && d.nblk <= kFusedScan; }
+
+hipError_t launch_compact(const Dev &d, const Tuning &t, bool allow_small, hipStream_t s) {
   hipLaunchKernelGGL(k_count, dim3(d.nblk), dim3(kWG), 0, s, d);
+  const int al = allow_small ? 1 : 0;
   if (d.nblk <= kFusedScan) {
-    hipLaunchKernelGGL(k_scatter<true>, dim3(d.nblk), dim3(kWG), 0, s, d);
+    hipLaunchKernelGGL(k_scatter<true>, dim3(d.nblk), dim3(kWG), 0, s, d, t,
+                       plan_fused(d) ? (int)kPlanStep : -1, al);
   } else {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d);
-    hipLaunchKernelGGL(k_scatter<false>, dim3(d.nblk), dim3(kWG), 0, s, d);
+    hipLaunchKernelGGL(k_scatter<false>, dim3(d.nblk), dim3(kWG), 0, s, d, t, -1, al);
   }
   return hipGetLastError();
 }
@@ -2174,13 +2232,14 @@ int force_grid_size(int mode, int src, int K, int device) {
 }
 
 hipError_t launch_sym_kick_drift(const Dev &d, double ck, double cd, bool check,
-                                 hipStream_t s) {
+                                 const Tuning &t, hipStream_t s) {
+  const int pk = d.C == 1 ? (int)kPlanState : -1;
   if (d.fld.on)
     hipLaunchKernelGGL(k_sym_kick_drift<true>, dim3(grid_for(d.n)), dim3(kWG), 0, s, d, ck,
-                       cd, check ? 1 : 0);
+                       cd, check ? 1 : 0, t, pk);
   else
     hipLaunchKernelGGL(k_sym_kick_drift<false>, dim3(grid_for(d.n)), dim3(kWG), 0, s, d, ck,
-                       cd, check ? 1 : 0);
+                       cd, check ? 1 : 0, t, pk);
   return hipGetLastError();
 }
 
@@ -2261,7 +2320,8 @@ int force_sb_grid_size(int mode, int K, int device) {
 }
 
 hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_host,
-                               float refine_ratio, hipStream_t s) {
+                               float refine_ratio, const Tuning &t1, int ref_kind,
+                               int64_t api_nj, hipStream_t s) {
   const int64_t cap = na_host >= 0 ? na_host : d.cap_active;
   // one wave (64 lanes) per entry, grid-stride
   hipLaunchKernelGGL(k_sum_flag, dim3(grid_for(cap * 64, kWG, 4096)), dim3(kWG), 0, s, d,
@@ -2270,10 +2330,12 @@ hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_hos
     hipLaunchKernelGGL(k_rcount, dim3(d.nblk), dim3(kWG), 0, s, d, na_host);
     const bool fused = d.nblk <= kFusedScan;
     if (fused) {
-      hipLaunchKernelGGL(k_rscatter<true>, dim3(d.nblk), dim3(kWG), 0, s, d, list, na_host);
+      hipLaunchKernelGGL(k_rscatter<true>, dim3(d.nblk), dim3(kWG), 0, s, d, list, na_host, t1,
+                         plan_fused(d) ? ref_kind : -1, api_nj);
     } else {
       hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d);
-      hipLaunchKernelGGL(k_rscatter<false>, dim3(d.nblk), dim3(kWG), 0, s, d, list, na_host);
+      hipLaunchKernelGGL(k_rscatter<false>, dim3(d.nblk), dim3(kWG), 0, s, d, list, na_host,
+                         t1, -1, api_nj);
     }
     if (!fused || d.C > 1)
       hipLaunchKernelGGL(k_ref_offsets, dim3((d.C + 1 + kWG - 1) / kWG), dim3(kWG), 0, s,
