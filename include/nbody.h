@@ -286,6 +286,12 @@ typedef struct nbody_tuning {
                                kernel (default 1; < 0 disables) */
   int32_t i_slots[NBODY_TUNE_BUCKETS];
   int32_t target_items[NBODY_TUNE_BUCKETS];
+  int32_t acc_variant;      /* variant of the acceleration-only evaluations
+                               (nbody_accel, the symplectic drivers), whose
+                               lighter kernels may prefer another one;
+                               0: the same as variant.  In nbody_set_tuning
+                               0 keeps the current value and -1 resets it
+                               to 0. */
 } nbody_tuning;
 
 /* Read or replace the tuning of a context (host only, no device work). */

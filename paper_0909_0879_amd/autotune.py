@@ -40,13 +40,15 @@ def cache_key(precision: int, n: int) -> str:
     return f"{arch_name()}/{'mixed' if precision == binding.MIXED else 'fp64'}/{int(round(math.log2(max(n, 1))))}"
 
 
-def _time_forces(g, xt, vt, mt, ia, reps):
+def _time_forces(g, xt, vt, mt, ia, reps, acc_only=False):
     import torch
-    g.forces(xt, vt, mt, i_active=ia)
+    call = (lambda: g.accel(xt, mt, i_active=ia)) if acc_only else \
+        (lambda: g.forces(xt, vt, mt, i_active=ia))
+    call()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        g.forces(xt, vt, mt, i_active=ia)
+        call()
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
@@ -79,6 +81,19 @@ def tune(n: int, precision: int, eps: float = 1e-3, seed: int = 77, buckets=None
         if verbose:
             print(f"variant {var}: full evaluation {times[var]:.2f} ms", flush=True)
     best_var = min(variants, key=lambda var: times[var])
+    # the acceleration-only kernels (symplectic drivers, nbody_accel) carry
+    # fewer registers and may prefer another variant
+    acc_times = {var: math.inf for var in variants}
+    for _ in range(2):
+        for var in variants:
+            g.set_tuning({"acc_variant": var})
+            acc_times[var] = min(acc_times[var], _time_forces(g, xt, vt, mt, full, 2, True))
+    for var in variants:
+        if verbose:
+            print(f"acc_variant {var}: full acceleration-only evaluation {acc_times[var]:.2f} ms",
+                  flush=True)
+    best_acc = min(variants, key=lambda var: acc_times[var])
+    g.set_tuning({"acc_variant": -1})
     K = 2 if best_var in (binding.VARIANT_K2, binding.VARIANT_S2) else 1
     slots = list(base["i_slots"])
     targets = list(base["target_items"])
@@ -92,9 +107,11 @@ def tune(n: int, precision: int, eps: float = 1e-3, seed: int = 77, buckets=None
         for s in SLOT_CHOICES:
             if s * K > 2 * na and s > 1:
                 continue
-            # thousands of active particles fill the chip with full-width
-            # i-tiles; narrower ones only cost time to try
-            if na >= 4096 and s < 256:
+            # on large systems thousands of active particles fill the chip
+            # with full-width i-tiles and narrower ones only cost time to
+            # try; on smaller ones the partial-row bound caps the j-splits
+            # and narrower tiles are how the items reach the target
+            if na >= 4096 and n >= (1 << 19) and s < 256:
                 continue
             for tg in TARGET_CHOICES:
                 tr = {"variant": best_var, "i_slots": [s] * binding.TUNE_BUCKETS,
@@ -111,7 +128,8 @@ def tune(n: int, precision: int, eps: float = 1e-3, seed: int = 77, buckets=None
             print(f"bucket {b:2d} (n_active {na}): slots {best[1]:3d} target {best[2]:5d} "
                   f"{best[0]:.3f} ms  {rate:.3e} int/s", flush=True)
     g.close()
-    return {"variant": best_var, "use_graph": binding.GRAPH_ON, "steps_per_launch": 16,
+    return {"variant": best_var, "acc_variant": best_acc, "use_graph": binding.GRAPH_ON,
+            "steps_per_launch": 16,
             "min_split_j": 256, "i_slots": slots, "target_items": targets,
             "measured": time.strftime("%Y-%m-%dT%H:%M:%S")}
 

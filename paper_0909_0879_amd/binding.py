@@ -86,13 +86,15 @@ class Tuning(C.Structure):
         ("variant", C.c_int32), ("use_graph", C.c_int32), ("steps_per_launch", C.c_int32),
         ("min_split_j", C.c_int32), ("refine_ratio", C.c_float),
         ("i_slots", C.c_int32 * TUNE_BUCKETS), ("target_items", C.c_int32 * TUNE_BUCKETS),
+        ("acc_variant", C.c_int32),
     ]
 
     def as_dict(self):
         return {"variant": self.variant, "use_graph": self.use_graph,
                 "steps_per_launch": self.steps_per_launch, "min_split_j": self.min_split_j,
                 "refine_ratio": self.refine_ratio,
-                "i_slots": list(self.i_slots), "target_items": list(self.target_items)}
+                "i_slots": list(self.i_slots), "target_items": list(self.target_items),
+                "acc_variant": self.acc_variant}
 
     @classmethod
     def from_dict(cls, d):
@@ -106,6 +108,7 @@ class Tuning(C.Structure):
             t.i_slots[b] = int(v)
         for b, v in enumerate(d.get("target_items", [0] * TUNE_BUCKETS)):
             t.target_items[b] = int(v)
+        t.acc_variant = int(d.get("acc_variant", 0))
         return t
 
 

@@ -231,6 +231,8 @@ struct nbody_ctx {
   nbody_tuning tune{};
   int K = 1;
   bool sb = false;                // broadcast kernel for large evaluations
+  int Ka = 1;                     // the same two for the acceleration-only
+  bool sba = false;               // evaluations (tuning acc_variant)
   int grid_state = 0, grid_raw = 0, grid_pot = 0, grid_sb = 0;
   int grid_ref_state = 0, grid_ref_raw = 0;   // FP64 K = 1 re-evaluation
   int grid_small = 0;             // FP64, the context's K: small mixed block steps
@@ -284,10 +286,13 @@ int refresh_grids(nbody_ctx *c) {
   const int v = c->tune.variant;
   c->K = (v == NBODY_VARIANT_K2 || v == NBODY_VARIANT_S2) ? 2 : 1;
   c->sb = (v == NBODY_VARIANT_S1 || v == NBODY_VARIANT_S2);
+  const int va = c->tune.acc_variant ? c->tune.acc_variant : v;
+  c->Ka = (va == NBODY_VARIANT_K2 || va == NBODY_VARIANT_S2) ? 2 : 1;
+  c->sba = (va == NBODY_VARIANT_S1 || va == NBODY_VARIANT_S2);
   c->grid_sb = c->sb ? nbk::force_sb_grid_size(mode_of(c), c->K, c->device) : 1;
-  c->grid_acc_sb = c->sb ? nbk::force_sb_grid_size(acc_mode_of(c), c->K, c->device) : 1;
-  c->grid_acc_state = nbk::force_grid_size(acc_mode_of(c), nbk::kSrcState, c->K, c->device);
-  c->grid_acc_raw = nbk::force_grid_size(acc_mode_of(c), nbk::kSrcRaw, c->K, c->device);
+  c->grid_acc_sb = c->sba ? nbk::force_sb_grid_size(acc_mode_of(c), c->Ka, c->device) : 1;
+  c->grid_acc_state = nbk::force_grid_size(acc_mode_of(c), nbk::kSrcState, c->Ka, c->device);
+  c->grid_acc_raw = nbk::force_grid_size(acc_mode_of(c), nbk::kSrcRaw, c->Ka, c->device);
   c->grid_ref_acc_state = nbk::force_grid_size(nbk::kModeFP64Acc, nbk::kSrcState, 1, c->device);
   c->grid_ref_acc_raw = nbk::force_grid_size(nbk::kModeFP64Acc, nbk::kSrcRaw, 1, c->device);
   c->grid_state = nbk::force_grid_size(mode_of(c), nbk::kSrcState, c->K, c->device);
@@ -297,7 +302,7 @@ int refresh_grids(nbody_ctx *c) {
   c->grid_ref_raw = nbk::force_grid_size(nbk::kModeFP64, nbk::kSrcRaw, 1, c->device);
   c->grid_small = nbk::force_grid_size(nbk::kModeFP64, nbk::kSrcState, c->K, c->device);
   c->grid_rec = nbk::force_grid_size(mode_of(c), nbk::kSrcRec, c->K, c->device);
-  c->grid_acc_rec = nbk::force_grid_size(acc_mode_of(c), nbk::kSrcRec, c->K, c->device);
+  c->grid_acc_rec = nbk::force_grid_size(acc_mode_of(c), nbk::kSrcRec, c->Ka, c->device);
   if (c->grid_state < 1 || c->grid_raw < 1 || c->grid_pot < 1 || c->grid_ref_state < 1 ||
       c->grid_ref_raw < 1 || c->grid_small < 1 || c->grid_rec < 1 || c->grid_acc_rec < 1 ||
       c->grid_sb < 1 || c->grid_acc_sb < 1 || c->grid_acc_state < 1 ||
@@ -320,7 +325,8 @@ int force_launch(nbody_ctx *c, int mode, int src, int K, const nbk::RawSrc *raw,
   // evaluations whose records are always built (mixed block steps beyond
   // the small ones, whole-state evaluations) use the record-only kernel
   const bool rec_only = small || rec_kind == nbk::kPlanState;
-  if (use_pred) NB_HIP(nbk::launch_records(c->d, mode, rec_kind, raw, c->sb, rec_only, s));
+  const bool sb = nbk::mode_acc_only(mode) ? c->sba : c->sb;
+  if (use_pred) NB_HIP(nbk::launch_records(c->d, mode, rec_kind, raw, sb, rec_only, s));
   if (prof && c->ev_used == kEvPairs) {
     int rc = harvest_events(c);
     if (rc) return rc;
@@ -331,7 +337,7 @@ int force_launch(nbody_ctx *c, int mode, int src, int K, const nbk::RawSrc *raw,
                             rec_only ? (nbk::mode_acc_only(mode) ? c->grid_acc_rec : c->grid_rec)
                                      : grid,
                             s));
-  if (use_pred && c->sb)
+  if (use_pred && sb)
     NB_HIP(nbk::launch_force_sb(c->d, mode, K, raw, list,
                                 nbk::mode_acc_only(mode) ? c->grid_acc_sb : c->grid_sb, s));
   if (small)
@@ -490,7 +496,8 @@ int api_forces(nbody_ctx *c, bool acc_only, const int32_t *i_active, int64_t n_a
     return fail(NBODY_EINVAL, "with several clusters n_j must equal the context's n");
   const int mode = acc_only ? acc_mode_of(c) : mode_of(c);
   const int grid = acc_only ? c->grid_acc_raw : c->grid_raw;
-  const nbk::Tuning t = device_tuning(c, c->K);
+  const int K = acc_only ? c->Ka : c->K;
+  const nbk::Tuning t = device_tuning(c, K);
   const int64_t cap = c->d.cap_active;
   for (int64_t k0 = 0; k0 < n_active; k0 += cap) {
     nbk::RawSrc r;
@@ -504,7 +511,7 @@ int api_forces(nbody_ctx *c, bool acc_only, const int32_t *i_active, int64_t n_a
     r.jerk = jerk ? jerk + 3 * k0 : nullptr;
     NB_HIP(nbk::launch_api_group(c->d, r, c->stream));
     NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanApi, r.n_j, false, c->stream));
-    int rc = force_launch(c, mode, nbk::kSrcRaw, c->K, &r, r.i_active, grid, c->stream,
+    int rc = force_launch(c, mode, nbk::kSrcRaw, K, &r, r.i_active, grid, c->stream,
                           nbk::kPlanApi);
     if (rc) return rc;
     if ((rc = sum_and_refine(c, r.i_active, r.n_active, &r, c->stream, acc_only))) return rc;
@@ -630,13 +637,13 @@ int nbody_step_symplectic(nbody_ctx *c, int scheme, double h, int64_t n_steps,
     w = {w3, w2, w1, w0, w1, w2, w3};
   }
   const int mode = acc_mode_of(c);
-  const nbk::Tuning t = device_tuning(c, c->K);
+  const nbk::Tuning t = device_tuning(c, c->Ka);
   // with one cluster the kernel before each evaluation (the all-active
   // setup, then every kick-drift) writes its plan
   NB_HIP(nbk::launch_all_active(c->d, t, c->stream));
   auto evaluate = [&](hipStream_t s) -> int {
     if (c->C > 1) NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, false, s));
-    int r = force_launch(c, mode, nbk::kSrcState, c->K, nullptr, c->d.active, c->grid_acc_state,
+    int r = force_launch(c, mode, nbk::kSrcState, c->Ka, nullptr, c->d.active, c->grid_acc_state,
                          s, nbk::kPlanState);
     if (r) return r;
     return sum_and_refine(c, c->d.active, -1, nullptr, s, /*acc_only=*/true);
@@ -908,6 +915,13 @@ int nbody_set_tuning(nbody_ctx *c, const nbody_tuning *t) {
         t->variant != NBODY_VARIANT_S1 && t->variant != NBODY_VARIANT_S2)
       return fail(NBODY_EINVAL, "unknown variant");
     n.variant = t->variant;
+  }
+  if (t->acc_variant) {
+    if (t->acc_variant != -1 && t->acc_variant != NBODY_VARIANT_K1 &&
+        t->acc_variant != NBODY_VARIANT_K2 && t->acc_variant != NBODY_VARIANT_S1 &&
+        t->acc_variant != NBODY_VARIANT_S2)
+      return fail(NBODY_EINVAL, "unknown acc_variant");
+    n.acc_variant = t->acc_variant == -1 ? 0 : t->acc_variant;
   }
   if (t->use_graph) {
     if (t->use_graph != NBODY_GRAPH_ON && t->use_graph != NBODY_GRAPH_OFF)

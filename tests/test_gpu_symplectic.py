@@ -192,3 +192,47 @@ def test_symplectic_graph_replay_equals_eager_bitwise(prec):
         g.close()
     for k in out[0]:
         assert np.array_equal(out[0][k], out[1][k]), k
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_acc_variant_is_independent_of_variant(prec):
+    # the acceleration-only evaluations take their own kernel variant; each
+    # combination stays within the oracle's tolerance, block steps keep
+    # theirs, and -1 returns the field to "the same as variant"
+    require_gpu()
+    n = 3000
+    m, x, v = ics.plummer(n, 73)
+    a_ref, j_ref = oracle.forces(x, v, m, 1e-4)
+    g = binding.NBody(m, x, v, eps=1e-4, precision=prec)
+    for var, acc_var in ((binding.VARIANT_K1, binding.VARIANT_K2),
+                         (binding.VARIANT_K2, binding.VARIANT_S1),
+                         (binding.VARIANT_S2, binding.VARIANT_K1)):
+        g.set_tuning({"variant": var, "acc_variant": acc_var})
+        t = g.get_tuning()
+        assert t["variant"] == var and t["acc_variant"] == acc_var
+        acc = to_np(g.accel(x, m))
+        a_full, j_full = g.forces(x, v, m)
+        g.sync()
+        assert rel_err(acc, a_ref).max() <= _tol(prec)
+        assert rel_err(to_np(a_full), a_ref).max() <= _tol(prec)
+    g.set_tuning({"acc_variant": -1})
+    assert g.get_tuning()["acc_variant"] == 0
+    with pytest.raises(binding.NBodyError) as e:
+        g.set_tuning({"acc_variant": 7})
+    assert e.value.code == binding.EINVAL
+
+
+def test_symplectic_with_other_acc_variant_matches_oracle():
+    require_gpu()
+    n, h, steps = 1024, 1 / 256, 16
+    m, x, v = ics.plummer(n, 1)
+    g = binding.NBody(m, x, v, eps=1e-3, precision=binding.FP64, level_min=4, level_max=20)
+    g.set_tuning({"variant": binding.VARIANT_K1, "acc_variant": binding.VARIANT_S2})
+    g.step_symplectic(binding.SYMPLECTIC6, h, steps)
+    s = {k: to_np(t) for k, t in g.get_state().items()}
+    xr, vr = oracle.symplectic(x, v, m, 1e-3, h, steps, binding.SYMPLECTIC6)
+    assert _positions_close(s["x"], xr, 1e-12)
+    assert _positions_close(s["v"], vr, 1e-11)
+    a_ref, j_ref = oracle.forces(s["x"], s["v"], m, 1e-3)
+    assert rel_err(s["a"], a_ref).max() <= FP64_TOL
+    assert rel_err(s["j"], j_ref).max() <= FP64_TOL
