@@ -8,10 +8,18 @@ or two i-particles per slot, j staged through LDS or broadcast from scalar
 registers) is chosen on the full evaluation.  Results are
 cached as JSON keyed by device architecture, precision and log2(N).
 
+Ensembles of many clusters are tuned apart (--ensemble C): a block step of
+an ensemble spreads over every cluster, so its time is set by the longest
+work items, and narrower i-tiles than a single system of the same total N
+wants pay off.  The ensemble tuner starts from the single-system entry of
+the same size, caps the i-slots of the larger buckets, and times real block
+steps of a seeded ensemble of Plummer clusters for each cap.
+
 Every candidate computes the same sums in a different order, so tuning only
 changes rounding (the split-invariance GPU test bounds the difference).
 
 Usage: python -m paper_0909_0879_amd.autotune --n 1048576 --precision mixed
+       python -m paper_0909_0879_amd.autotune --ensemble 256 --precision mixed
 """
 from __future__ import annotations
 
@@ -36,8 +44,9 @@ def arch_name() -> str:
     return getattr(props, "gcnArchName", "unknown").split(":")[0]
 
 
-def cache_key(precision: int, n: int) -> str:
-    return f"{arch_name()}/{'mixed' if precision == binding.MIXED else 'fp64'}/{int(round(math.log2(max(n, 1))))}"
+def cache_key(precision: int, n: int, ensemble: bool = False) -> str:
+    key = f"{arch_name()}/{'mixed' if precision == binding.MIXED else 'fp64'}/{int(round(math.log2(max(n, 1))))}"
+    return key + "/ensemble" if ensemble else key
 
 
 def _time_forces(g, xt, vt, mt, ia, reps, acc_only=False):
@@ -134,23 +143,80 @@ def tune(n: int, precision: int, eps: float = 1e-3, seed: int = 77, buckets=None
             "measured": time.strftime("%Y-%m-%dT%H:%M:%S")}
 
 
-def load(precision: int, n: int, path: str = DEFAULT_CACHE):
-    """Cached tuning for (arch, precision, log2 n), or None."""
+def load(precision: int, n: int, path: str = DEFAULT_CACHE, n_clusters: int = 1):
+    """Cached tuning for (arch, precision, log2 n), or None; contexts of
+    several clusters take the ensemble entry of that size when there is one."""
     if not os.path.exists(path):
         return None
     with open(path) as f:
         cache = json.load(f)
+    if n_clusters > 1 and cache_key(precision, n, True) in cache:
+        return cache[cache_key(precision, n, True)]
     return cache.get(cache_key(precision, n))
 
 
-def store(precision: int, n: int, tuning: dict, path: str = DEFAULT_CACHE):
+def store(precision: int, n: int, tuning: dict, path: str = DEFAULT_CACHE,
+          ensemble: bool = False):
     cache = {}
     if os.path.exists(path):
         with open(path) as f:
             cache = json.load(f)
-    cache[cache_key(precision, n)] = tuning
+    cache[cache_key(precision, n, ensemble)] = tuning
     with open(path, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
+
+
+def tune_ensemble(n_clusters: int, precision: int, n_min: int = 256, n_max: int = 16384,
+                  seed: int = 5000, t_end: float = 1 / 32, verbose: bool = True,
+                  path: str = DEFAULT_CACHE) -> tuple[int, dict]:
+    """Tune block steps of an ensemble of n_clusters Plummer clusters with
+    log-uniform sizes in [n_min, n_max]; returns (total N, tuning)."""
+    import torch
+    m, x, v, off = ics.ensemble(n_clusters, n_min, n_max, seed=seed)
+    n = int(m.shape[0])
+    base = load(precision, n, path)
+    if base is None:
+        g = binding.NBody(m[:64], x[:64], v[:64], precision=precision)
+        base = g.get_tuning()
+        g.close()
+    base = {k: val for k, val in base.items() if k != "measured"}
+
+    def run(tr):
+        best = math.inf
+        for _ in range(2):
+            g = binding.NBody(m, x, v, eps=1e-3, precision=precision, eta=0.01, eta_start=0.01,
+                              level_min=5, level_max=20, cluster_offsets=off, tuning=tr)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.step(t_end)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+            g.close()
+        return best
+
+    best = (run(base), 256, 0)
+    if verbose:
+        print(f"ensemble n={n}: single-system tuning {best[0]:.3f} s", flush=True)
+    for cap in (128, 64, 32):
+        for first in (6, 8, 10):
+            tr = dict(base)
+            tr["i_slots"] = [min(s, cap) if b >= first else s
+                             for b, s in enumerate(base["i_slots"])]
+            t = run(tr)
+            if verbose:
+                print(f"  i-slots <= {cap:3d} from bucket {first:2d}: {t:.3f} s", flush=True)
+            if t < best[0]:
+                best = (t, cap, first)
+    out = dict(base)
+    out["i_slots"] = [min(s, best[1]) if b >= best[2] else s
+                      for b, s in enumerate(base["i_slots"])]
+    out["ensemble"] = {"clusters": n_clusters, "n_min": n_min, "n_max": n_max,
+                       "slot_cap": best[1], "from_bucket": best[2], "seconds": best[0]}
+    out["measured"] = time.strftime("%Y-%m-%dT%H:%M:%S")
+    if verbose:
+        print(f"ensemble n={n}: i-slots <= {best[1]} from bucket {best[2]}, {best[0]:.3f} s",
+              flush=True)
+    return n, out
 
 
 def main():
@@ -158,11 +224,18 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="mixed")
     ap.add_argument("--cache", default=DEFAULT_CACHE)
+    ap.add_argument("--ensemble", type=int, default=0, metavar="C",
+                    help="tune block steps of an ensemble of C Plummer clusters instead")
     ap.add_argument("--buckets", default="",
                     help="comma list of log2(n_active) buckets, or 'none' to choose only the "
                          "kernel variant (other buckets keep their cached values)")
     a = ap.parse_args()
     prec = binding.MIXED if a.precision == "mixed" else binding.FP64
+    if a.ensemble > 1:
+        n, t = tune_ensemble(a.ensemble, prec, path=a.cache)
+        store(prec, n, t, a.cache, ensemble=True)
+        print(json.dumps({"key": cache_key(prec, n, True), **t}))
+        return
     if a.buckets == "none":
         buckets = []
     else:

@@ -236,7 +236,7 @@ class NBody:
                                _ptr(v)), "nbody_init")
         if tuning == "auto":
             from . import autotune
-            tuning = autotune.load(precision, n)
+            tuning = autotune.load(precision, n, n_clusters=n_clusters)
         if tuning:
             self.set_tuning(tuning)
 
