@@ -509,8 +509,8 @@ int api_forces(nbody_ctx *c, bool acc_only, const int32_t *i_active, int64_t n_a
     r.n_active = (n_active - k0 < cap) ? n_active - k0 : cap;
     r.acc = acc + 3 * k0;
     r.jerk = jerk ? jerk + 3 * k0 : nullptr;
-    NB_HIP(nbk::launch_api_group(c->d, r, c->stream));
-    NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanApi, r.n_j, false, c->stream));
+    NB_HIP(nbk::launch_api_group(c->d, r, t, c->stream));
+    if (c->C > 1) NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanApi, r.n_j, false, c->stream));
     int rc = force_launch(c, mode, nbk::kSrcRaw, K, &r, r.i_active, grid, c->stream,
                           nbk::kPlanApi);
     if (rc) return rc;

@@ -221,7 +221,9 @@ hipError_t launch_correct(const Dev &d, double eta, double dt_shared,
 hipError_t launch_init_levels(const Dev &d, double eta_start,
                               double dt_shared, int level_min, int level_max,
                               hipStream_t s);
-hipError_t launch_api_group(const Dev &d, const RawSrc &r, hipStream_t s);
+// nbody_forces / nbody_accel: per-cluster offsets of the caller's active list
+// (and its index checks); with one cluster also the kPlanApi plan (tuning t).
+hipError_t launch_api_group(const Dev &d, const RawSrc &r, const Tuning &t, hipStream_t s);
 hipError_t launch_api_finalize(const Dev &d, const RawSrc &r, hipStream_t s);
 hipError_t launch_energy_reduce(const Dev &d, hipStream_t s);
 hipError_t launch_set_word64(int64_t *p, int64_t v, hipStream_t s);

@@ -1348,9 +1348,11 @@ __global__ __launch_bounds__(kWG) void k_init_levels(Dev d, double eta_s,
 
 // nbody_forces with several clusters: offsets of each cluster's group in
 // i_active (which must be grouped by non-decreasing cluster id).
-__global__ void k_api_group(Dev d, const int32_t *ia, int64_t na) {
+__global__ void k_api_group(Dev d, const int32_t *ia, int64_t na, Tuning tu, int64_t api_nj) {
   const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int C = d.C;
+  // one cluster: the active count is the caller's, so plan here
+  if (C == 1 && gt == 0) plan_single(d, tu, kPlanApi, api_nj, 0, (int32_t)na);
   auto key = [&](int64_t k) -> int {
     const int32_t i = ia[k];
     if (i < 0 || i >= d.n) return C;     // invalid: sorts last
@@ -2373,10 +2375,10 @@ hipError_t launch_init_levels(const Dev &d, double eta_start, double dt_shared,
   return hipGetLastError();
 }
 
-hipError_t launch_api_group(const Dev &d, const RawSrc &r, hipStream_t s) {
+hipError_t launch_api_group(const Dev &d, const RawSrc &r, const Tuning &t, hipStream_t s) {
   int64_t need = r.n_active > d.C + 1 ? r.n_active : d.C + 1;
   hipLaunchKernelGGL(k_api_group, dim3((unsigned)((need + kWG - 1) / kWG)),
-                     dim3(kWG), 0, s, d, r.i_active, r.n_active);
+                     dim3(kWG), 0, s, d, r.i_active, r.n_active, t, r.n_j);
   return hipGetLastError();
 }
 
