@@ -1,0 +1,56 @@
+"""The autotuner's cache (host logic only): keys by architecture, precision
+and log2 N; contexts of several clusters take the ensemble entry of their
+size when there is one and the single-system entry otherwise; the shipped
+cache parses and holds valid tunings."""
+import json
+import os
+
+import pytest
+
+from paper_0909_0879_amd import autotune, binding
+
+
+@pytest.fixture
+def arch(monkeypatch):
+    monkeypatch.setattr(autotune, "arch_name", lambda: "gfx950")
+
+
+def test_keys(arch):
+    assert autotune.cache_key(binding.MIXED, 1 << 20) == "gfx950/mixed/20"
+    assert autotune.cache_key(binding.FP64, 979217) == "gfx950/fp64/20"      # log2 rounded
+    assert autotune.cache_key(binding.MIXED, 979217, True) == "gfx950/mixed/20/ensemble"
+
+
+def test_store_and_load_with_ensemble_fallback(arch, tmp_path):
+    path = str(tmp_path / "cache.json")
+    assert autotune.load(binding.MIXED, 4096, path) is None
+    autotune.store(binding.MIXED, 4096, {"variant": 1}, path)
+    assert autotune.load(binding.MIXED, 4096, path) == {"variant": 1}
+    # several clusters, no ensemble entry yet: the single-system one
+    assert autotune.load(binding.MIXED, 4096, path, n_clusters=8) == {"variant": 1}
+    autotune.store(binding.MIXED, 4096, {"variant": 2}, path, ensemble=True)
+    assert autotune.load(binding.MIXED, 4096, path, n_clusters=8) == {"variant": 2}
+    assert autotune.load(binding.MIXED, 4096, path, n_clusters=1) == {"variant": 1}
+    assert autotune.load(binding.FP64, 4096, path) is None
+    with open(path) as f:
+        assert set(json.load(f)) == {"gfx950/mixed/12", "gfx950/mixed/12/ensemble"}
+
+
+def test_shipped_cache_is_valid():
+    with open(autotune.DEFAULT_CACHE) as f:
+        cache = json.load(f)
+    assert cache
+    for key, t in cache.items():
+        parts = key.split("/")
+        assert parts[1] in ("mixed", "fp64") and parts[2].isdigit(), key
+        assert t["variant"] in (1, 2, 3, 4)
+        assert t.get("acc_variant", 0) in (0, 1, 2, 3, 4)
+        assert len(t["i_slots"]) == binding.TUNE_BUCKETS
+        assert len(t["target_items"]) == binding.TUNE_BUCKETS
+        for p in t["i_slots"]:
+            assert 1 <= p <= 256 and p & (p - 1) == 0, key
+        for q in t["target_items"]:
+            assert 1 <= q <= 65536, key
+        # the binding turns every entry into the ABI struct
+        tt = binding.Tuning.from_dict(t)
+        assert tt.variant == t["variant"]
