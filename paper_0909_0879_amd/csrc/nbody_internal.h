@@ -20,7 +20,9 @@ constexpr int kFusedScan = 1024;    // compaction grids up to this many blocks
 constexpr int kBuckets = 25;        // tuning buckets floor(log2(n_active))
 constexpr int kNoActive = 99;       // threshold level meaning "nothing due"
 constexpr int kSmallStep = 256;     // mixed block steps up to this many active
-                                    // particles are evaluated by the FP64 kernel
+                                    // particles are evaluated by the FP64 kernel,
+constexpr int64_t kSmallWork = (int64_t)1 << 27;   // and so are those of up to
+                                    // this many interactions (n_active x N_c)
 constexpr int kRowStride = 8;       // doubles per partial row: a(3), jerk(3),
                                     // bound on the largest acc term, pad
 
@@ -54,7 +56,7 @@ struct ClusterPlan {
   int64_t jb, je;   // j range [jb, je)
   int64_t chunk;    // j per split (multiple of kTJ)
   int64_t t_pred;   // tick every particle of the cluster is predicted to
-  int32_t small;    // mixed block step with <= kSmallStep active particles:
+  int32_t small;    // small mixed block step (kSmallStep, kSmallWork):
                     // evaluated by the FP64 kernel, never re-evaluated
   int32_t pad_;
 };
@@ -174,8 +176,9 @@ bool plan_fused(const Dev &d);
 // Scheduler (per-cluster T_next and threshold level) and ordered compaction
 // of the due particles into the active list (plan: see plan_fused).
 hipError_t launch_compact(const Dev &d, const Tuning &t, bool allow_small, hipStream_t s);
-// allow_small: clusters of a block step with at most kSmallStep active
-// particles are planned for the small-step FP64 launch (mixed contexts).
+// allow_small: clusters of a small block step (at most kSmallStep active
+// particles, or at most kSmallWork interactions) are planned for the
+// small-step FP64 launch (mixed contexts).
 hipError_t launch_plan(const Dev &d, const Tuning &t, int kind,
                        int64_t api_nj, bool allow_small, hipStream_t s);
 // Sum each active entry's partial rows into fsum; with refine_ratio > 0 also
@@ -191,8 +194,8 @@ hipError_t launch_refine_finalize(const Dev &d, hipStream_t s);
 // (re-evaluation, potential); kRoleMain: the main items unless the record
 // flag (*d.pred_on, set by launch_records) is 2 — then the broadcast kernel
 // takes them — reading records when it is 1; kRoleSmall: the small-step
-// items (clusters of a mixed block step with <= kSmallStep active), in FP64
-// with the prediction fused into the tile fill.
+// items (clusters of a small mixed block step), in FP64 with the prediction
+// fused into the tile fill.
 enum Role : int { kRoleAlways = 0, kRoleMain = 1, kRoleSmall = 2 };
 hipError_t launch_force(const Dev &d, int mode, int src, int K,
                         const RawSrc *raw, const int32_t *list, int role,

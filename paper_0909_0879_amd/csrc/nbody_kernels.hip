@@ -814,7 +814,8 @@ __device__ ClusterPlan plan_cluster(const Dev &d, const Tuning &tu, int kind, in
     p.chunk = chunk;
     p.tiles = (int32_t)tiles;
     p.items = (int32_t)(tiles * S);
-    p.small = (allow_small && kind == kPlanStep && p.na <= kSmallStep) ? 1 : 0;
+    p.small = (allow_small && kind == kPlanStep &&
+               (p.na <= kSmallStep || (int64_t)p.na * nc <= kSmallWork)) ? 1 : 0;
   }
   return p;
 }

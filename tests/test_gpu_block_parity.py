@@ -16,7 +16,8 @@ from tests.gpu_util import FP64_TOL, check_parity, require_gpu, to_np
 pytestmark = pytest.mark.gpu
 
 TICK = 2.0 ** -20
-SMALL_STEP = 256      # mixed block steps with at most this many active run in FP64
+SMALL_STEP = 256      # mixed block steps with at most this many active run in FP64,
+SMALL_WORK = 1 << 27  # and so do those of at most this many interactions
 
 
 def _state(g):
@@ -44,7 +45,7 @@ def _check_block_steps(g, m, eps, t_end, checks, every, sample, mixed, label):
         a_ref, j_ref = oracle.forces(xp, vp, m, eps, idx=idx.astype(np.int64))
         print(f"  {label} check {c}: n_active {active.size} of {n}", flush=True)
         st = check_parity(s1["a"][idx], s1["j"][idx], a_ref, j_ref, mixed, f"{label} {c}")
-        if mixed and active.size <= SMALL_STEP:
+        if mixed and (active.size <= SMALL_STEP or active.size * n <= SMALL_WORK):
             # a mixed block step this small is evaluated by the FP64 kernel
             assert st["acc_max"] <= FP64_TOL and st["jerk_max"] <= FP64_TOL, st
         sizes.append(active.size)
