@@ -143,16 +143,37 @@ def tune(n: int, precision: int, eps: float = 1e-3, seed: int = 77, buckets=None
             "measured": time.strftime("%Y-%m-%dT%H:%M:%S")}
 
 
+def _nearest(cache: dict, key: str):
+    """The entry of key, else the one of the nearest size with the same
+    architecture, precision and kind (the smaller size on a tie), or None."""
+    if key in cache:
+        return cache[key]
+    parts = key.split("/")
+    size, suffix = int(parts[2]), parts[3:]
+    best = None
+    for k, entry in cache.items():
+        q = k.split("/")
+        if q[:2] != parts[:2] or q[3:] != suffix or not q[2].isdigit():
+            continue
+        d = (abs(int(q[2]) - size), int(q[2]))
+        if best is None or d < best[0]:
+            best = (d, entry)
+    return best[1] if best else None
+
+
 def load(precision: int, n: int, path: str = DEFAULT_CACHE, n_clusters: int = 1):
-    """Cached tuning for (arch, precision, log2 n), or None; contexts of
-    several clusters take the ensemble entry of that size when there is one."""
+    """Cached tuning for (arch, precision, log2 n) — the nearest tuned size
+    when n itself was not tuned — or None.  Contexts of several clusters
+    take the ensemble entry of exactly their size when there is one (an
+    ensemble entry is tuned to its kind of ensemble and is not stretched to
+    other sizes)."""
     if not os.path.exists(path):
         return None
     with open(path) as f:
         cache = json.load(f)
     if n_clusters > 1 and cache_key(precision, n, True) in cache:
         return cache[cache_key(precision, n, True)]
-    return cache.get(cache_key(precision, n))
+    return _nearest(cache, cache_key(precision, n))
 
 
 def store(precision: int, n: int, tuning: dict, path: str = DEFAULT_CACHE,

@@ -1,7 +1,8 @@
 """The autotuner's cache (host logic only): keys by architecture, precision
-and log2 N; contexts of several clusters take the ensemble entry of their
-size when there is one and the single-system entry otherwise; the shipped
-cache parses and holds valid tunings."""
+and log2 N; an untuned size takes the nearest tuned one; contexts of
+several clusters take the ensemble entry of their size when there is one
+and a single-system entry otherwise; the shipped cache parses and holds
+valid tunings."""
 import json
 import os
 
@@ -34,6 +35,23 @@ def test_store_and_load_with_ensemble_fallback(arch, tmp_path):
     assert autotune.load(binding.FP64, 4096, path) is None
     with open(path) as f:
         assert set(json.load(f)) == {"gfx950/mixed/12", "gfx950/mixed/12/ensemble"}
+
+
+def test_nearest_tuned_size(arch, tmp_path):
+    path = str(tmp_path / "cache.json")
+    for b in (12, 16, 20):
+        autotune.store(binding.MIXED, 1 << b, {"variant": b}, path)
+    autotune.store(binding.MIXED, 1 << 20, {"variant": 99}, path, ensemble=True)
+    assert autotune.load(binding.MIXED, 1 << 16, path)["variant"] == 16   # exact
+    assert autotune.load(binding.MIXED, 1 << 17, path)["variant"] == 16   # tie: smaller
+    assert autotune.load(binding.MIXED, 1 << 19, path)["variant"] == 20
+    assert autotune.load(binding.MIXED, 1 << 8, path)["variant"] == 12
+    assert autotune.load(binding.MIXED, 1 << 24, path)["variant"] == 20
+    # ensembles: the ensemble entry of exactly their size, else the nearest
+    # single-system one
+    assert autotune.load(binding.MIXED, 1 << 20, path, n_clusters=4)["variant"] == 99
+    assert autotune.load(binding.MIXED, 1 << 17, path, n_clusters=4)["variant"] == 16
+    assert autotune.load(binding.FP64, 1 << 17, path) is None
 
 
 def test_shipped_cache_is_valid():
