@@ -18,14 +18,15 @@ CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
           "-Wno-unused-parameter"]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = OUT + ".tmp"
-    cmd = ["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"]
+def build(verbose: bool = False, src: str = SRC, out: str = OUT) -> str:
+    """Compile src (default: the oracle) into the shared library out."""
+    tmp = out + ".tmp"
+    cmd = ["gcc", *CFLAGS, src, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
