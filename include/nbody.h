@@ -8,9 +8,12 @@
  * phi = -m / sqrt(r^2 + eps^2)), together with its time derivative (the
  * jerk).  It advances systems with a fourth-order Hermite predictor-corrector
  * on individual power-of-two block time steps chosen by Aarseth's criterion
- * (the paper's individual per-particle time steps, Sect. 3).  Many
- * independent systems ("clusters") can share one context; each cluster only
- * feels its own particles.
+ * (the paper's individual per-particle time steps, Sect. 3), or with the
+ * paper's symplectic drivers (leapfrog and a sixth-order composition,
+ * Sect. 4) over an acceleration-only form of the same evaluation.  An
+ * optional external Galactic field (Sect. 4; nbody_field) adds to the
+ * pairwise forces.  Many independent systems ("clusters") can share one
+ * context; each cluster only feels its own particles (and the field).
  *
  * Conventions
  *  - Arrays of vectors are (n, 3) row-major FP64: x[3*i + c].
