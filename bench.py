@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=N_DEFAULT, help="particles (default 2^20)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the FP64 and FP64-difference comparison runs")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="headline",
                     choices=("headline", "sweep", "ensemble", "blocksteps", "kingsteps",
@@ -424,10 +425,12 @@ def main():
 
     m, x, v = ics.king(a.n, 7.0, 4)
     mixed = time_path(binding, torch, m, x, v, binding.MIXED, a.steps, a.warmup)
-    fp64 = None
+    fp64 = mixed_ds = None
     if not a.no_fp64:
         fp64 = time_path(binding, torch, m, x, v, binding.FP64, max(1, a.steps // 2 + 1),
                          a.warmup)
+        mixed_ds = time_path(binding, torch, m, x, v, binding.MIXED_DS,
+                             max(1, a.steps // 2 + 1), a.warmup)
     n = a.n
     per_launch_flops = FLOPS_PER_INTERACTION * float(n) * n
     achieved = per_launch_flops / (mixed["kernel_ms"] * 1e-3) / 1e12
@@ -446,11 +449,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"King W0=7 N={n} equal-mass Henon units eps=1e-4, Hermite-4 "
                                f"block step with all particles active (level {LEVEL}), "
-                               "mixed-precision force path",
+                               "mixed-precision force path (FP64 coordinate and velocity "
+                               "differences, FP32 rsqrt, r^-3 and jerk products)",
                    "n": n, "interactions_per_step": n * n},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": measured_traffic(), "kernel": "k_force<mixed,records,K=1> (LDS-staged j records)",
+                     "traffic": measured_traffic(),
+                     "kernel": "k_force_sb<mixed,K=1> (FP64 j records through the scalar cache)",
                      "kernel_ms": mixed["kernel_ms"],
                      "flops_per_launch": per_launch_flops},
         "fp64_reevaluation": {"ms_per_step": mixed["refine_ms_per_step"],
@@ -463,6 +468,15 @@ def main():
                        "kernel_ms": fp64["kernel_ms"], "achieved_tflops": f_ach,
                        "frac_fp64_peak": f_ach / FP64_VECTOR_PEAK_TFLOPS}
         out["mixed_over_fp64"] = mixed["rate"] / fp64["rate"]
+    if mixed_ds:
+        # the other mixed form: x_j - x_i from double-single pairs and FP32
+        # velocity differences (the paper's software double precision)
+        d_ach = per_launch_flops / (mixed_ds["kernel_ms"] * 1e-3) / 1e12
+        out["mixed_double_single"] = {
+            "value": mixed_ds["rate"], "ms_per_step": mixed_ds["ms_per_step"],
+            "kernel_ms": mixed_ds["kernel_ms"], "achieved_tflops": d_ach,
+            "frac_fp32_peak": d_ach / FP32_VECTOR_PEAK_TFLOPS,
+            "over_fp64": mixed_ds["rate"] / fp64["rate"] if fp64 else None}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(m, x, v, a.cpu_seconds)
     print(json.dumps(out), flush=True)

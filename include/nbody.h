@@ -65,14 +65,18 @@ typedef enum nbody_status {
 typedef enum nbody_precision {
   /* plain FP64 arithmetic throughout */
   NBODY_FP64 = 0,
-  /* FP64 state, predictor and corrector; x_j - x_i formed from the FP64
-     predicted positions split into double-single FP32 pairs (the paper's
-     software double precision, Sect. 5); FP32 v_j - v_i, rsqrt, r^-3 and
-     jerk products; FP32 sums of every 64 j folded into a compensated
-     (TwoSum) FP32 hi/lo pair.  Particles whose acceleration is dominated
-     by a single term (see nbody_tuning.refine_ratio) are re-evaluated in
-     FP64. */
-  NBODY_MIXED = 1
+  /* FP64 state, predictor and corrector; x_j - x_i and v_j - v_i are FP64
+     subtractions of the FP64 predicted positions and velocities, rounded to
+     FP32 for the FP32 r^2, r.v, rsqrt, r^-3 and jerk products; FP32 sums of
+     every 64 j folded into a compensated (TwoSum) FP32 hi/lo pair.
+     Particles whose acceleration is dominated by a single term (see
+     nbody_tuning.refine_ratio) are re-evaluated in FP64. */
+  NBODY_MIXED = 1,
+  /* as NBODY_MIXED, but x_j - x_i formed in FP32 from the FP64 predicted
+     positions split into double-single pairs (the paper's software double
+     precision, Sect. 5: within an FP32 ulp of the FP64 difference), and
+     v_j - v_i from velocities rounded to FP32 (j records of 48 bytes) */
+  NBODY_MIXED_DS = 2
 } nbody_precision;
 
 /* External Galactic field added to the pairwise forces (Sect. 4: the paper

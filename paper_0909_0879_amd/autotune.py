@@ -44,8 +44,11 @@ def arch_name() -> str:
     return getattr(props, "gcnArchName", "unknown").split(":")[0]
 
 
+PRECISION_NAMES = {binding.FP64: "fp64", binding.MIXED: "mixed", binding.MIXED_DS: "mixedds"}
+
+
 def cache_key(precision: int, n: int, ensemble: bool = False) -> str:
-    key = f"{arch_name()}/{'mixed' if precision == binding.MIXED else 'fp64'}/{int(round(math.log2(max(n, 1))))}"
+    key = f"{arch_name()}/{PRECISION_NAMES[precision]}/{int(round(math.log2(max(n, 1))))}"
     return key + "/ensemble" if ensemble else key
 
 
@@ -243,7 +246,7 @@ def tune_ensemble(n_clusters: int, precision: int, n_min: int = 256, n_max: int 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=1 << 20)
-    ap.add_argument("--precision", choices=("fp64", "mixed"), default="mixed")
+    ap.add_argument("--precision", choices=("fp64", "mixed", "mixedds"), default="mixed")
     ap.add_argument("--cache", default=DEFAULT_CACHE)
     ap.add_argument("--ensemble", type=int, default=0, metavar="C",
                     help="tune block steps of an ensemble of C Plummer clusters instead")
@@ -251,7 +254,7 @@ def main():
                     help="comma list of log2(n_active) buckets, or 'none' to choose only the "
                          "kernel variant (other buckets keep their cached values)")
     a = ap.parse_args()
-    prec = binding.MIXED if a.precision == "mixed" else binding.FP64
+    prec = {v: k for k, v in PRECISION_NAMES.items()}[a.precision]
     if a.ensemble > 1:
         n, t = tune_ensemble(a.ensemble, prec, path=a.cache)
         store(prec, n, t, a.cache, ensemble=True)

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnbody.so")
 
 OK, EINVAL, ENODEV, ENOMEM, EHIP, EINDEX, ENONFINITE, EDOMAIN = 0, -1, -2, -3, -4, -5, -6, -7
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_DS = 0, 1, 2   # nbody_precision
 VARIANT_DEFAULT, VARIANT_K1, VARIANT_K2, VARIANT_S1, VARIANT_S2 = 0, 1, 2, 3, 4
 GRAPH_ON, GRAPH_OFF = 1, 2
 LEAPFROG, SYMPLECTIC6 = 0, 1

@@ -106,7 +106,8 @@ int validate_params(const nbody_params *p, int64_t n) {
   if (n < 1 || n > kMaxN) return fail(NBODY_EINVAL, "n must be in [1, 2^30]");
   if (p->n_clusters < 1 || p->n_clusters > nbk::kMaxClusters)
     return fail(NBODY_EINVAL, "n_clusters must be in [1, 4096]");
-  if (p->precision != NBODY_FP64 && p->precision != NBODY_MIXED)
+  if (p->precision != NBODY_FP64 && p->precision != NBODY_MIXED &&
+      p->precision != NBODY_MIXED_DS)
     return fail(NBODY_EINVAL, "unknown precision");
   const int C = p->n_clusters;
   if (p->cluster_offsets) {
@@ -179,16 +180,25 @@ int device_present(int *dev) {
   return NBODY_OK;
 }
 
+// FP32 pair arithmetic (either mixed form)
+bool is_mixed(int precision) {
+  return precision == NBODY_MIXED || precision == NBODY_MIXED_DS;
+}
+
 nbody_tuning default_tuning(int precision) {
   nbody_tuning t;
   std::memset(&t, 0, sizeof t);
-  // measured on MI355X: the FP32 mixed loop runs fastest with one i per lane
-  // (more waves in flight), the FP64 loop with two (more reuse per LDS read)
-  t.variant = (precision == NBODY_MIXED) ? NBODY_VARIANT_K1 : NBODY_VARIANT_K2;
+  // measured on MI355X at N = 2^20: the mixed loop with FP64 differences runs
+  // fastest with one i per lane fed from scalar registers (its FP64 records
+  // as SGPR operands), the double-single one with one i per lane from LDS
+  // (more waves in flight), the FP64 loop with two i per lane
+  t.variant = precision == NBODY_MIXED      ? NBODY_VARIANT_S1
+              : precision == NBODY_MIXED_DS ? NBODY_VARIANT_K1
+                                            : NBODY_VARIANT_K2;
   t.use_graph = NBODY_GRAPH_ON;
   t.steps_per_launch = 16;
   t.min_split_j = 256;
-  t.refine_ratio = (precision == NBODY_MIXED) ? kDefaultRefineRatio : -1.0f;
+  t.refine_ratio = is_mixed(precision) ? kDefaultRefineRatio : -1.0f;
   const int K = (t.variant == NBODY_VARIANT_K2) ? 2 : 1;
   for (int b = 0; b < NBODY_TUNE_BUCKETS; ++b) {
     // one i-tile covers the bucket [2^b, 2^(b+1)) when possible
@@ -267,11 +277,13 @@ nbk::Tuning device_tuning(const nbody_ctx *c, int K) {
 }
 
 int mode_of(const nbody_ctx *c) {
-  return c->prec == NBODY_MIXED ? nbk::kModeMixed : nbk::kModeFP64;
+  return c->prec == NBODY_MIXED ? nbk::kModeMixed64
+         : c->prec == NBODY_MIXED_DS ? nbk::kModeMixed : nbk::kModeFP64;
 }
 
 int acc_mode_of(const nbody_ctx *c) {
-  return c->prec == NBODY_MIXED ? nbk::kModeMixedAcc : nbk::kModeFP64Acc;
+  return c->prec == NBODY_MIXED ? nbk::kModeMixed64Acc
+         : c->prec == NBODY_MIXED_DS ? nbk::kModeMixedAcc : nbk::kModeFP64Acc;
 }
 
 void drop_graph(nbody_ctx *c) {
@@ -321,7 +333,8 @@ int force_launch(nbody_ctx *c, int mode, int src, int K, const nbk::RawSrc *raw,
   const bool prof = c->profiling && s == c->stream;
   const bool use_pred = rec_kind >= 0;
   // clusters of a mixed block step with few active particles run in FP64
-  const bool small = rec_kind == nbk::kPlanStep && mode == nbk::kModeMixed;
+  const bool small = rec_kind == nbk::kPlanStep && nbk::mode_mixed(mode) &&
+                     !nbk::mode_acc_only(mode);
   // evaluations whose records are always built (mixed block steps beyond
   // the small ones, whole-state evaluations) use the record-only kernel
   const bool rec_only = small || rec_kind == nbk::kPlanState;
@@ -349,7 +362,7 @@ int force_launch(nbody_ctx *c, int mode, int src, int K, const nbk::RawSrc *raw,
     // of a mixed context are its re-evaluations
     const bool fp64 = mode == nbk::kModeFP64 || mode == nbk::kModeFP64Acc;
     c->ev_tag[c->ev_used] =
-        (mode == nbk::kModePot) ? -1 : ((fp64 && c->prec == NBODY_MIXED) ? 1 : 0);
+        (mode == nbk::kModePot) ? -1 : ((fp64 && is_mixed(c->prec)) ? 1 : 0);
     ++c->ev_used;
   }
   return NBODY_OK;
@@ -372,7 +385,7 @@ int harvest_events(nbody_ctx *c) {
 }
 
 float refine_ratio(const nbody_ctx *c) {
-  return (c->prec == NBODY_MIXED && c->tune.refine_ratio > 0.0f) ? c->tune.refine_ratio : 0.0f;
+  return (is_mixed(c->prec) && c->tune.refine_ratio > 0.0f) ? c->tune.refine_ratio : 0.0f;
 }
 
 // Sum the partial rows into fsum and, on the mixed path, re-evaluate the
@@ -400,7 +413,7 @@ int sum_and_refine(nbody_ctx *c, const int32_t *list, int64_t na_host, const nbk
 // One Hermite block step for every cluster, enqueued on s.
 int enqueue_block_step(nbody_ctx *c, hipStream_t s) {
   const nbk::Tuning t = device_tuning(c, c->K);
-  const bool allow_small = c->prec == NBODY_MIXED;
+  const bool allow_small = is_mixed(c->prec);
   NB_HIP(nbk::launch_compact(c->d, t, allow_small, s));
   if (!nbk::plan_fused(c->d))
     NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanStep, 0, allow_small, s));

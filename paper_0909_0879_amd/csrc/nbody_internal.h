@@ -142,16 +142,25 @@ struct Dev {
 // caller's arrays, or only the records (launches that always have them).
 enum Source : int { kSrcState = 0, kSrcRaw = 1, kSrcRec = 2 };
 // What the force kernel computes: acceleration and jerk, the potential, or
-// the acceleration alone (the symplectic drivers and nbody_accel).
+// the acceleration alone (the symplectic drivers and nbody_accel); in FP64,
+// mixed with double-single differences, or mixed with FP64 differences.
 enum Mode : int {
   kModeFP64 = 0,
   kModeMixed = 1,
   kModePot = 2,
   kModeFP64Acc = 3,
-  kModeMixedAcc = 4
+  kModeMixedAcc = 4,
+  kModeMixed64 = 5,
+  kModeMixed64Acc = 6
 };
-constexpr bool mode_acc_only(int m) { return m == kModeFP64Acc || m == kModeMixedAcc; }
-constexpr bool mode_mixed(int m) { return m == kModeMixed || m == kModeMixedAcc; }
+constexpr bool mode_acc_only(int m) {
+  return m == kModeFP64Acc || m == kModeMixedAcc || m == kModeMixed64Acc;
+}
+// FP32 pair arithmetic: compensated FP32 sums, the largest-term bound and
+// the FP64 re-evaluation
+constexpr bool mode_mixed(int m) {
+  return m == kModeMixed || m == kModeMixedAcc || m == kModeMixed64 || m == kModeMixed64Acc;
+}
 
 // Host-side launchers (defined in nbody_kernels.hip).  Every launcher only
 // enqueues on `s`; none synchronises.  They return the hipError_t of the

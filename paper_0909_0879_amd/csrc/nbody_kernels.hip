@@ -20,12 +20,14 @@
 //    records that k_records predicts once per evaluation for large ones —
 //    or, for large evaluations with full-width i-tiles, straight from the
 //    records through the scalar cache into SGPRs (k_force_sb);
-//  * FP32 arithmetic dual-issues on gfx950 while FP64 does not, so the mixed
-//    path keeps every per-pair operation in FP32: the FP64 predicted
-//    positions are stored as double-single (hi, lo) FP32 pairs and x_j - x_i
-//    is formed as (hi_j - hi_i) + (lo_j - lo_i); particles dominated by one
-//    term are re-evaluated by the FP64 kernel, and mixed block steps with
-//    few active particles run in FP64 outright;
+//  * the mixed paths keep the state in FP64 and run r^2, rsqrt, r^-3 and the
+//    jerk products in FP32: with x_j - x_i and v_j - v_i as FP64
+//    subtractions rounded to FP32 (its j records reach the broadcast kernel
+//    as SGPR operands, so the FP64 subtracts cost little), or with x_j - x_i
+//    formed in FP32 from double-single (hi, lo) pairs as (hi_j - hi_i) +
+//    (lo_j - lo_i); particles dominated by one term are re-evaluated by the
+//    FP64 kernel, and mixed block steps with few active particles run in
+//    FP64 outright;
 //  * small active sets put several lanes on one i (P i-slots x Q j-lanes,
 //    P * Q = 256) and split j over workgroups; lanes are reduced with
 //    wavefront shuffles in a fixed tree and splits by k_sum_flag in a fixed
@@ -285,6 +287,60 @@ __device__ __forceinline__ void pair_mixed_acc(const IDS &I, int iidx, const JRe
   t[2] = fmaf(mr3, dz, t[2]);
 }
 
+// Mixed precision with FP64 differences: x_j - x_i and v_j - v_i are taken
+// in FP64 from the FP64 records and rounded to FP32; everything after them is
+// the FP32 arithmetic of pair_mixed.
+template <bool MASK, bool SELF>
+__device__ __forceinline__ void pair_mixed64(const I64 &I, int iidx, const JRec64 &r,
+                                             float eps2, float *t, int &dom, float &tmx) {
+  const float dx = (float)(r.x - I.x[0]), dy = (float)(r.y - I.x[1]),
+              dz = (float)(r.z - I.x[2]);
+  const float wx = (float)(r.vx - I.v[0]), wy = (float)(r.vy - I.v[1]),
+              wz = (float)(r.vz - I.v[2]);
+  const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+  const float rv = fmaf(dx, wx, fmaf(dy, wy, dz * wz));
+  float rinv = __builtin_amdgcn_rsqf(s);
+  if (MASK) {
+    if (dx == 0.0f && dy == 0.0f && dz == 0.0f) {
+      rinv = 0.0f;
+      dom |= (r.idx != iidx);
+    }
+  }
+  const float rinv2 = rinv * rinv;
+  const float mq = r.mf * rinv2;
+  const float mr3 = mq * rinv;
+  const float al = (3.0f * rv) * rinv2;
+  tmx = fmaxf(tmx, (SELF && r.idx == iidx) ? 0.0f : mq);
+  t[0] = fmaf(mr3, dx, t[0]);
+  t[1] = fmaf(mr3, dy, t[1]);
+  t[2] = fmaf(mr3, dz, t[2]);
+  t[3] = fmaf(mr3, fmaf(-al, dx, wx), t[3]);
+  t[4] = fmaf(mr3, fmaf(-al, dy, wy), t[4]);
+  t[5] = fmaf(mr3, fmaf(-al, dz, wz), t[5]);
+}
+
+template <bool MASK, bool SELF>
+__device__ __forceinline__ void pair_mixed64_acc(const I64 &I, int iidx, const JRec64 &r,
+                                                 float eps2, float *t, int &dom, float &tmx) {
+  const float dx = (float)(r.x - I.x[0]), dy = (float)(r.y - I.x[1]),
+              dz = (float)(r.z - I.x[2]);
+  const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+  float rinv = __builtin_amdgcn_rsqf(s);
+  if (MASK) {
+    if (dx == 0.0f && dy == 0.0f && dz == 0.0f) {
+      rinv = 0.0f;
+      dom |= (r.idx != iidx);
+    }
+  }
+  const float rinv2 = rinv * rinv;
+  const float mq = r.mf * rinv2;
+  const float mr3 = mq * rinv;
+  tmx = fmaxf(tmx, (SELF && r.idx == iidx) ? 0.0f : mq);
+  t[0] = fmaf(mr3, dx, t[0]);
+  t[1] = fmaf(mr3, dy, t[1]);
+  t[2] = fmaf(mr3, dz, t[2]);
+}
+
 // Potential -m_j / sqrt(s) (energy diagnostics).  The i's own pair is
 // skipped: by s == 0 when unsoftened (MASK, as for the forces), else by
 // index in the tiles that can hold i (SELF).
@@ -332,6 +388,20 @@ template <> struct Traits<kModeMixedAcc> {
   static constexpr int NC = 3;
   static constexpr int FOLD = 64;
 };
+template <> struct Traits<kModeMixed64> {
+  using T = float;
+  using Rec = JRec64;
+  using Ist = I64;
+  static constexpr int NC = 6;
+  static constexpr int FOLD = 64;
+};
+template <> struct Traits<kModeMixed64Acc> {
+  using T = float;
+  using Rec = JRec64;
+  using Ist = I64;
+  static constexpr int NC = 3;
+  static constexpr int FOLD = 64;
+};
 template <> struct Traits<kModePot> {
   using T = double;
   using Rec = JRec64;
@@ -370,6 +440,10 @@ __device__ __forceinline__ void pair_k(const typename Traits<MODE>::Rec &r,
       pair_mixed_acc<MASK, SELF>(I[k], iidx[k], r, (float)eps2, t[k], dom[k], tmx[k]);
     else if constexpr (MODE == kModeFP64Acc)
       pair_fp64_acc<MASK>(I[k], iidx[k], r, eps2, t[k], dom[k]);
+    else if constexpr (MODE == kModeMixed64)
+      pair_mixed64<MASK, SELF>(I[k], iidx[k], r, (float)eps2, t[k], dom[k], tmx[k]);
+    else if constexpr (MODE == kModeMixed64Acc)
+      pair_mixed64_acc<MASK, SELF>(I[k], iidx[k], r, (float)eps2, t[k], dom[k], tmx[k]);
     else
       pair_pot<MASK, SELF>(I[k], iidx[k], r, eps2, t[k], dom[k]);
   }
@@ -1481,7 +1555,7 @@ __device__ __forceinline__ JRec64 load_rec(ScalarPtr<JRec64> p) {
   JRec64 r;
   r.x = p->x; r.y = p->y; r.z = p->z; r.m = p->m;
   r.vx = p->vx; r.vy = p->vy; r.vz = p->vz;
-  r.mf = 0.0f; r.idx = p->idx;
+  r.mf = p->mf; r.idx = p->idx;
   return r;
 }
 
@@ -1526,7 +1600,7 @@ __device__ __forceinline__ void load4(ScalarPtr<JRec64> p, JRec64 (&r)[4]) {
     r[u].vx = __builtin_bit_cast(double, __builtin_shufflevector(a, a, 8, 9));
     r[u].vy = __builtin_bit_cast(double, __builtin_shufflevector(a, a, 10, 11));
     r[u].vz = __builtin_bit_cast(double, __builtin_shufflevector(a, a, 12, 13));
-    r[u].mf = 0.0f;
+    r[u].mf = a[14];
     r[u].idx = __float_as_int(a[15]);
   }
 }
@@ -2197,6 +2271,18 @@ hipError_t launch_force(const Dev &d, int mode, int src, int K,
   NB_CASE(kModeFP64Acc, kSrcRec, 2)
   NB_CASE(kModeMixedAcc, kSrcRec, 1)
   NB_CASE(kModeMixedAcc, kSrcRec, 2)
+  NB_CASE(kModeMixed64, kSrcState, 1)
+  NB_CASE(kModeMixed64, kSrcState, 2)
+  NB_CASE(kModeMixed64, kSrcRaw, 1)
+  NB_CASE(kModeMixed64, kSrcRaw, 2)
+  NB_CASE(kModeMixed64, kSrcRec, 1)
+  NB_CASE(kModeMixed64, kSrcRec, 2)
+  NB_CASE(kModeMixed64Acc, kSrcState, 1)
+  NB_CASE(kModeMixed64Acc, kSrcState, 2)
+  NB_CASE(kModeMixed64Acc, kSrcRaw, 1)
+  NB_CASE(kModeMixed64Acc, kSrcRaw, 2)
+  NB_CASE(kModeMixed64Acc, kSrcRec, 1)
+  NB_CASE(kModeMixed64Acc, kSrcRec, 2)
   NB_CASE(kModePot, kSrcState, 1)
 #undef NB_CASE
   return hipErrorInvalidValue;
@@ -2229,6 +2315,18 @@ int force_grid_size(int mode, int src, int K, int device) {
   NB_CASE(kModeFP64Acc, kSrcRec, 2)
   NB_CASE(kModeMixedAcc, kSrcRec, 1)
   NB_CASE(kModeMixedAcc, kSrcRec, 2)
+  NB_CASE(kModeMixed64, kSrcState, 1)
+  NB_CASE(kModeMixed64, kSrcState, 2)
+  NB_CASE(kModeMixed64, kSrcRaw, 1)
+  NB_CASE(kModeMixed64, kSrcRaw, 2)
+  NB_CASE(kModeMixed64, kSrcRec, 1)
+  NB_CASE(kModeMixed64, kSrcRec, 2)
+  NB_CASE(kModeMixed64Acc, kSrcState, 1)
+  NB_CASE(kModeMixed64Acc, kSrcState, 2)
+  NB_CASE(kModeMixed64Acc, kSrcRaw, 1)
+  NB_CASE(kModeMixed64Acc, kSrcRaw, 2)
+  NB_CASE(kModeMixed64Acc, kSrcRec, 1)
+  NB_CASE(kModeMixed64Acc, kSrcRec, 2)
   NB_CASE(kModePot, kSrcState, 1)
 #undef NB_CASE
   return 0;
@@ -2268,7 +2366,7 @@ hipError_t launch_records(const Dev &d, int mode, int kind, const RawSrc *raw,
   const int64_t nj = (kind == kPlanApi && r.n_j > 0) ? r.n_j : d.n;
   const dim3 g(grid_for(nj, kWG, 1024)), b(kWG);
   const int sb = allow_sb ? 1 : 0, al = always ? 1 : 0;
-  if (mode_mixed(mode))
+  if (mode == kModeMixed || mode == kModeMixedAcc)     // double-single records
     hipLaunchKernelGGL(k_records<kModeMixed>, g, b, 0, s, d, kind, r, sb, al);
   else
     hipLaunchKernelGGL(k_records<kModeFP64>, g, b, 0, s, d, kind, r, sb, al);
@@ -2296,6 +2394,10 @@ hipError_t launch_force_sb(const Dev &d, int mode, int K, const RawSrc *raw,
   NB_CASE(kModeFP64Acc, 2)
   NB_CASE(kModeMixedAcc, 1)
   NB_CASE(kModeMixedAcc, 2)
+  NB_CASE(kModeMixed64, 1)
+  NB_CASE(kModeMixed64, 2)
+  NB_CASE(kModeMixed64Acc, 1)
+  NB_CASE(kModeMixed64Acc, 2)
 #undef NB_CASE
   return hipErrorInvalidValue;
 }
@@ -2312,6 +2414,10 @@ int force_sb_grid_size(int mode, int K, int device) {
   NB_CASE(kModeFP64Acc, 2)
   NB_CASE(kModeMixedAcc, 1)
   NB_CASE(kModeMixedAcc, 2)
+  NB_CASE(kModeMixed64, 1)
+  NB_CASE(kModeMixed64, 2)
+  NB_CASE(kModeMixed64Acc, 1)
+  NB_CASE(kModeMixed64Acc, 2)
 #undef NB_CASE
   if (!f) return 0;
   int per_cu = 0, cus = 0;

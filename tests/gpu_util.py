@@ -11,6 +11,12 @@ MIXED_JERK_MEDIAN = 1e-6
 MIXED_JERK_MAX = 3e-5
 
 
+def is_mixed(prec):
+    """FP32 pair arithmetic (either mixed form): the mixed tolerances apply."""
+    from paper_0909_0879_amd import binding
+    return prec in (binding.MIXED, binding.MIXED_DS)
+
+
 def rel_err(got, ref):
     """Per-particle relative error |got - ref| / |ref| (absolute where |ref| = 0)."""
     got = np.asarray(got, np.float64)

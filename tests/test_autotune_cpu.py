@@ -60,7 +60,7 @@ def test_shipped_cache_is_valid():
     assert cache
     for key, t in cache.items():
         parts = key.split("/")
-        assert parts[1] in ("mixed", "fp64") and parts[2].isdigit(), key
+        assert parts[1] in autotune.PRECISION_NAMES.values() and parts[2].isdigit(), key
         assert t["variant"] in (1, 2, 3, 4)
         assert t.get("acc_variant", 0) in (0, 1, 2, 3, 4)
         assert len(t["i_slots"]) == binding.TUNE_BUCKETS

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from paper_0909_0879_amd import binding, ics
-from tests.gpu_util import FP64_TOL, check_parity, require_gpu, to_np
+from tests.gpu_util import FP64_TOL, check_parity, is_mixed, require_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -85,11 +85,11 @@ def test_whole_level_step_builds_records():
     require_gpu()
     n = 16384
     m, x, v = ics.plummer(n, 8)
-    for prec in (binding.FP64, binding.MIXED):
+    for prec in (binding.FP64, binding.MIXED, binding.MIXED_DS):
         g = binding.NBody(m, x, v, eps=1e-3, precision=prec, dt_shared=1 / 256, level_min=4,
                           level_max=8, tuning={"variant": binding.VARIANT_S2
                                                if prec == binding.FP64 else binding.VARIANT_K1})
         sizes = _check_block_steps(g, m, 1e-3, 1 / 16, checks=2, every=1, sample=512,
-                                   mixed=prec == binding.MIXED, label=f"shared prec={prec}")
+                                   mixed=is_mixed(prec), label=f"shared prec={prec}")
         assert sizes == [n, n]
         g.close()

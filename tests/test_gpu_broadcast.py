@@ -10,12 +10,12 @@ import pytest
 
 import oracle
 from paper_0909_0879_amd import binding, ics
-from tests.gpu_util import check_parity, require_gpu, to_np
+from tests.gpu_util import check_parity, require_gpu, to_np, is_mixed
 
 pytestmark = pytest.mark.gpu
 
 PAIRS = [(binding.VARIANT_K1, binding.VARIANT_S1), (binding.VARIANT_K2, binding.VARIANT_S2)]
-PRECS = [binding.FP64, binding.MIXED]
+PRECS = [binding.FP64, binding.MIXED, binding.MIXED_DS]
 WIDE = {"i_slots": [256] * 25}       # kWG i-slots in every bucket: broadcast-eligible
 
 
@@ -43,7 +43,7 @@ def test_forces_bitwise_equal_to_lds_kernel(prec, lds, sb):
         assert np.array_equal(a0, a1) and np.array_equal(j0, j1)
         sel = np.arange(n) if idx is None else idx.astype(np.int64)
         a_ref, j_ref = oracle.forces(x, v, m, 1e-4, idx=sel)
-        check_parity(a1, j1, a_ref, j_ref, prec == binding.MIXED, f"variant {sb}")
+        check_parity(a1, j1, a_ref, j_ref, is_mixed(prec), f"variant {sb}")
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -59,7 +59,7 @@ def test_zero_softening_bitwise_and_edomain(prec):
         out.append(_forces(g, x, v, m))
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
     a_ref, j_ref = oracle.forces(x, v, m, 0.0)
-    check_parity(out[1][0], out[1][1], a_ref, j_ref, prec == binding.MIXED, "eps=0")
+    check_parity(out[1][0], out[1][1], a_ref, j_ref, is_mixed(prec), "eps=0")
     # two distinct coincident particles
     x2 = x.copy()
     x2[5] = x2[9]
@@ -100,7 +100,7 @@ def test_ensemble_bitwise_equal_to_lds_kernel(prec):
     for c in range(4):
         sl = slice(off[c], off[c + 1])
         a_ref, j_ref = oracle.forces(x[sl], v[sl], m[sl], eps[c])
-        check_parity(out[1][0][sl], out[1][1][sl], a_ref, j_ref, prec == binding.MIXED,
+        check_parity(out[1][0][sl], out[1][1][sl], a_ref, j_ref, is_mixed(prec),
                      f"cluster {c}")
 
 

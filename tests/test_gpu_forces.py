@@ -7,8 +7,8 @@ import pytest
 
 import oracle
 from paper_0909_0879_amd import binding, ics
-from tests.gpu_util import (FP64_TOL, MIXED_JERK_MAX, MIXED_TOL, check_parity, rel_err,
-                            require_gpu, to_np)
+from tests.gpu_util import (FP64_TOL, MIXED_JERK_MAX, MIXED_TOL, check_parity, is_mixed,
+                            rel_err, require_gpu, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -19,7 +19,7 @@ def _ctx(m, x, v, eps, prec, **kw):
     return binding.NBody(m, x, v, eps=eps, precision=prec, **kw)
 
 
-PRECS = [binding.FP64, binding.MIXED]
+PRECS = [binding.FP64, binding.MIXED, binding.MIXED_DS]
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -36,7 +36,7 @@ def test_all_particles_vs_oracle(n, prec):
     if n == 1:
         assert np.all(to_np(acc) == 0) and np.all(to_np(jerk) == 0)
         return
-    check_parity(to_np(acc), to_np(jerk), a_ref, j_ref, prec == binding.MIXED, f"n={n}")
+    check_parity(to_np(acc), to_np(jerk), a_ref, j_ref, is_mixed(prec), f"n={n}")
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -53,7 +53,7 @@ def test_subsets_with_repeats(na, prec):
     acc, jerk = g.forces(x, v, m, i_active=idx)
     g.sync()
     a_ref, j_ref = oracle.forces(x, v, m, 1e-4, idx=idx.astype(np.int64))
-    check_parity(to_np(acc), to_np(jerk), a_ref, j_ref, prec == binding.MIXED, f"na={na}")
+    check_parity(to_np(acc), to_np(jerk), a_ref, j_ref, is_mixed(prec), f"na={na}")
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -67,7 +67,7 @@ def test_j_set_larger_than_context(prec):
     acc, jerk = g.forces(x, v, m, i_active=idx)
     g.sync()
     a_ref, j_ref = oracle.forces(x, v, m, 1e-3, idx=idx.astype(np.int64))
-    check_parity(to_np(acc), to_np(jerk), a_ref, j_ref, prec == binding.MIXED)
+    check_parity(to_np(acc), to_np(jerk), a_ref, j_ref, is_mixed(prec))
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -86,7 +86,7 @@ def test_j_set_of_2_23(prec):
     acc, jerk = g.forces(x, v, m, i_active=idx)
     g.sync()
     a_ref, j_ref = oracle.forces(x, v, m, 1e-4, idx=idx.astype(np.int64))
-    check_parity(to_np(acc), to_np(jerk), a_ref, j_ref, prec == binding.MIXED, "n_j 2^23")
+    check_parity(to_np(acc), to_np(jerk), a_ref, j_ref, is_mixed(prec), "n_j 2^23")
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -100,7 +100,7 @@ def test_zero_softening(prec):
     acc, jerk = g.forces(x, v, m)
     g.sync()
     a_ref, j_ref = oracle.forces(x, v, m, 0.0)
-    check_parity(to_np(acc), to_np(jerk), a_ref, j_ref, prec == binding.MIXED)
+    check_parity(to_np(acc), to_np(jerk), a_ref, j_ref, is_mixed(prec))
 
 
 def test_zero_softening_coincident_is_edomain():
@@ -132,7 +132,7 @@ def test_index_out_of_range_is_eindex():
 
 @pytest.mark.parametrize("prec", PRECS)
 def test_ensemble_forces_per_cluster(prec):
-    tol = MIXED_TOL if prec == binding.MIXED else FP64_TOL
+    tol = MIXED_TOL if is_mixed(prec) else FP64_TOL
     require_gpu()
     m, x, v, off = ics.ensemble(5, sizes=[257, 64, 1000, 3, 511], seed=900)
     eps = [1e-3, 2e-3, 1e-4, 1e-3, 5e-4]
@@ -143,7 +143,7 @@ def test_ensemble_forces_per_cluster(prec):
     for c in range(5):
         sl = slice(off[c], off[c + 1])
         a_ref, j_ref = oracle.forces(x[sl], v[sl], m[sl], eps[c])
-        check_parity(a[sl], j[sl], a_ref, j_ref, prec == binding.MIXED, f"cluster {c}")
+        check_parity(a[sl], j[sl], a_ref, j_ref, is_mixed(prec), f"cluster {c}")
     # grouped subset with repeats, skipping cluster 1 entirely
     idx = np.array([0, 0, 5, 400, 400, 1321, 1322, 1400], np.int32)
     acc, jerk = g.forces(x, v, m, i_active=idx)
@@ -162,7 +162,8 @@ def test_ensemble_forces_per_cluster(prec):
 
 
 @pytest.mark.parametrize("prec,tol,jtol", [(binding.FP64, 1e-14, 1e-13),
-                                           (binding.MIXED, MIXED_TOL, MIXED_JERK_MAX)])
+                                           (binding.MIXED, MIXED_TOL, MIXED_JERK_MAX),
+                                           (binding.MIXED_DS, MIXED_TOL, MIXED_JERK_MAX)])
 def test_split_and_tile_shape_invariance(prec, tol, jtol):
     # every launch shape sums the same terms in another order (and, on the
     # mixed path, may re-evaluate a slightly different set in FP64)
@@ -181,7 +182,7 @@ def test_split_and_tile_shape_invariance(prec, tol, jtol):
             assert rel_err(j, base_j).max() <= jtol, (variant, slots, target)
 
 
-@pytest.mark.parametrize("prec", [binding.FP64, binding.MIXED])
+@pytest.mark.parametrize("prec", PRECS)
 def test_bitwise_deterministic(prec):
     require_gpu()
     m, x, v = ics.plummer(3000, 6)
@@ -266,8 +267,8 @@ def test_more_clusters_than_plan_threads(prec):
         a_ref, j_ref = oracle.forces(x[sl], v[sl], m[sl], eps[c])
         worst_a = max(worst_a, rel_err(a[sl], a_ref).max())
         worst_j = max(worst_j, rel_err(j[sl], j_ref).max())
-    tol = MIXED_TOL if prec == binding.MIXED else FP64_TOL
-    jtol = MIXED_JERK_MAX if prec == binding.MIXED else FP64_TOL
+    tol = MIXED_TOL if is_mixed(prec) else FP64_TOL
+    jtol = MIXED_JERK_MAX if is_mixed(prec) else FP64_TOL
     assert worst_a <= tol and worst_j <= jtol, (worst_a, worst_j)
     # block steps run the plan every step
     e0 = g.energy()[:, 2]
@@ -297,9 +298,9 @@ def test_massless_tracers(prec):
     acc, jerk = g.forces(x, v, m)
     g.sync()
     a_ref, j_ref = oracle.forces(x, v, m, 1e-3)
-    check_parity(to_np(acc), to_np(jerk), a_ref, j_ref, prec == binding.MIXED, "tracers")
+    check_parity(to_np(acc), to_np(jerk), a_ref, j_ref, is_mixed(prec), "tracers")
     # the massive particles' forces do not depend on the tracers at all
     heavy = np.nonzero(m > 0)[0]
     a_h, j_h = oracle.forces(x[heavy], v[heavy], m[heavy], 1e-3)
-    check_parity(to_np(acc)[heavy], to_np(jerk)[heavy], a_h, j_h, prec == binding.MIXED,
+    check_parity(to_np(acc)[heavy], to_np(jerk)[heavy], a_h, j_h, is_mixed(prec),
                  "tracers removed")

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_0909_0879_amd import binding, ics
-from tests.gpu_util import check_parity, require_gpu, to_np
+from tests.gpu_util import check_parity, require_gpu, to_np, is_mixed
 
 pytestmark = pytest.mark.gpu
 
@@ -21,7 +21,7 @@ def king():
     return ics.king(N, 7.0, 4)
 
 
-@pytest.mark.parametrize("prec", [binding.FP64, binding.MIXED])
+@pytest.mark.parametrize("prec", [binding.FP64, binding.MIXED, binding.MIXED_DS])
 def test_full_size_sampled(king, prec):
     require_gpu()
     m, x, v = king
@@ -36,7 +36,7 @@ def test_full_size_sampled(king, prec):
     # the initial full evaluation (state source, all active)
     s0 = {k: to_np(t) for k, t in g.get_state().items()}
     a_ref, j_ref = oracle.forces(x, v, m, EPS, idx=idx)
-    mixed = prec == binding.MIXED
+    mixed = is_mixed(prec)
     check_parity(s0["a"][idx], s0["j"][idx], a_ref, j_ref, mixed, "t=0")
     # one benchmark block step: forces at the predicted positions
     g.step(2.0 ** -LEVEL)

@@ -78,7 +78,7 @@ def test_block_mode_single_level_equals_shared_bitwise():
         assert np.array_equal(sa[k], sb[k]), k
 
 
-@pytest.mark.parametrize("prec", [binding.FP64, binding.MIXED])
+@pytest.mark.parametrize("prec", [binding.FP64, binding.MIXED, binding.MIXED_DS])
 def test_graph_replay_equals_eager_bitwise(prec):
     require_gpu()
     m, x, v = ics.plummer(1200, 8)
@@ -96,7 +96,7 @@ def test_graph_replay_equals_eager_bitwise(prec):
         assert np.array_equal(sa[k], sb[k]), k
 
 
-@pytest.mark.parametrize("prec", [binding.FP64, binding.MIXED])
+@pytest.mark.parametrize("prec", [binding.FP64, binding.MIXED, binding.MIXED_DS])
 def test_ensemble_equals_solo_bitwise(prec):
     require_gpu()
     sizes = [300, 1024, 64, 777]

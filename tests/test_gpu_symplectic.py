@@ -6,16 +6,16 @@ import pytest
 
 import oracle
 from paper_0909_0879_amd import binding, ics
-from tests.gpu_util import FP64_TOL, MIXED_TOL, rel_err, require_gpu, to_np
+from tests.gpu_util import FP64_TOL, MIXED_TOL, rel_err, require_gpu, to_np, is_mixed
 
 pytestmark = pytest.mark.gpu
 
-PRECS = [binding.FP64, binding.MIXED]
+PRECS = [binding.FP64, binding.MIXED, binding.MIXED_DS]
 SCHEMES = [binding.LEAPFROG, binding.SYMPLECTIC6]
 
 
 def _tol(prec):
-    return MIXED_TOL if prec == binding.MIXED else FP64_TOL
+    return MIXED_TOL if is_mixed(prec) else FP64_TOL
 
 
 @pytest.mark.parametrize("prec", PRECS)
