@@ -100,10 +100,11 @@ COUNTER_FILE = os.path.join(ROOT, "profiles", "counters_k_force_king1M.json")
 
 
 def measured_counters():
-    """Counter-based FLOP rates and the observed clock of the two force
-    kernels from the committed rocprofv3 SQ counter runs (every executed FP
-    operation: FMA 2, add / mul / transcendental 1, x 64 lanes); None if the
-    kernel source changed since."""
+    """Counter-based FLOP rates and the observed clock of the force kernels
+    (mixed with FP64 differences, double-single mixed, FP64) from the
+    committed rocprofv3 SQ counter runs (every executed FP operation: FMA 2,
+    add / mul / transcendental 1, x 64 lanes); None if the kernel source
+    changed since."""
     if not os.path.exists(COUNTER_FILE):
         return None
     with open(COUNTER_FILE) as f:
@@ -111,9 +112,9 @@ def measured_counters():
     if c.get("kernel_sha256") != kernel_hash():
         return None
     return {k: {"kernel": c[k]["kernel"], "counter_tflops": c[k]["counter_tflops"],
-                "frac_peak": c[k]["frac_fp32_peak" if k == "mixed" else "frac_fp64_peak"],
+                "frac_peak": c[k]["frac_peak"],
                 "valu_instr_per_interaction": c[k]["valu_instr_per_interaction"],
-                "clock_ghz": c[k]["clock_ghz"]} for k in ("mixed", "fp64")}
+                "clock_ghz": c[k]["clock_ghz"]} for k in ("mixed", "mixed_ds", "fp64") if k in c}
 
 
 def calibrate_copy(nbytes):

@@ -266,7 +266,9 @@ const char *nbody_last_error(void);
  * (0..24), i_slots[b] threads of a 256-thread workgroup hold i-particles
  * (a power of two, 1..256; the other 256 / i_slots lanes split j inside the
  * workgroup) and the j range is split until the cluster has about
- * target_items[b] items.  variant selects the compiled kernel shape:
+ * target_items[b] items (1..2^20), within two bounds: no split shorter than
+ * min_split_j, and splits x n_active <= 32 n_j (the partial-sum rows the
+ * workspace holds per j-particle).  variant selects the compiled kernel shape:
  * NBODY_VARIANT_K1 (one i per thread slot) or NBODY_VARIANT_K2 (two), both
  * staging j through LDS; NBODY_VARIANT_S1 / _S2 add the broadcast kernel
  * (j records read into scalar registers) for evaluations with at least

@@ -35,7 +35,7 @@ from . import binding, ics
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 SLOT_CHOICES = (1, 4, 16, 64, 256)
-TARGET_CHOICES = (256, 1024, 2048, 4096, 8192)
+TARGET_CHOICES = (256, 1024, 2048, 4096, 8192, 32768, 131072)
 
 
 def arch_name() -> str:

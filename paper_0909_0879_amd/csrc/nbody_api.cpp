@@ -52,7 +52,7 @@ size_t carve(int64_t n, int32_t C, char *base, Dev *d) {
   t.C = C;
   t.nblk = (int32_t)((n + nbk::kScanBlock - 1) / nbk::kScanBlock);
   t.cap_active = n;
-  t.rows_cap = 5 * n + 4096;
+  t.rows_cap = (int64_t)(nbk::kRowsPerJ + 1) * n + 4096;
   t.x = (double *)take(sizeof(double) * 3 * n);
   t.v = (double *)take(sizeof(double) * 3 * n);
   t.a = (double *)take(sizeof(double) * 3 * n);
@@ -961,8 +961,8 @@ int nbody_set_tuning(nbody_ctx *c, const nbody_tuning *t) {
       n.i_slots[b] = P;
     }
     if (t->target_items[b]) {
-      if (t->target_items[b] < 1 || t->target_items[b] > 65536)
-        return fail(NBODY_EINVAL, "target_items must be in [1, 65536]");
+      if (t->target_items[b] < 1 || t->target_items[b] > (1 << 20))
+        return fail(NBODY_EINVAL, "target_items must be in [1, 2^20]");
       n.target_items[b] = t->target_items[b];
     }
   }

@@ -23,6 +23,7 @@ constexpr int kSmallStep = 256;     // mixed block steps up to this many active
                                     // particles are evaluated by the FP64 kernel,
 constexpr int64_t kSmallWork = (int64_t)1 << 27;   // and so are those of up to
                                     // this many interactions (n_active x N_c)
+constexpr int kRowsPerJ = 32;       // partial rows a cluster may take per j-particle
 constexpr int kRowStride = 8;       // doubles per partial row: a(3), jerk(3),
                                     // bound on the largest acc term, pad
 

@@ -559,9 +559,11 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
       if (d.item_prefix[mid] <= g) lo = mid; else hi = mid;
     }
     const ClusterPlan cp = d.plan_lpt[lo];
+    // split-major: the workgroups that run at the same time work on the
+    // same j chunk, so each XCD's L2 serves the chunk to all of them
     const int t_item = g - d.item_prefix[lo];
-    const int tile_i = t_item / cp.S;
-    const int split = t_item - tile_i * cp.S;
+    const int split = t_item / cp.tiles;
+    const int tile_i = t_item - split * cp.tiles;
     const int64_t js = cp.jb + (int64_t)split * cp.chunk;
     const int64_t je = (js + cp.chunk < cp.je) ? js + cp.chunk : cp.je;
     const int Qlog = cp.Qlog;
@@ -873,10 +875,10 @@ __device__ ClusterPlan plan_cluster(const Dev &d, const Tuning &tu, int kind, in
     const int64_t mj = tu.min_split_j > 0 ? tu.min_split_j : 64;
     const int64_t s_j = (nc + mj - 1) / mj;
     if (S > s_j) S = s_j;
-    // partial rows of a cluster: at most 4 per j-particle (so an ensemble
-    // needs at most 4 n rows, and a cluster splits the same way alone or
-    // in an ensemble), and never more than the workspace holds
-    int64_t rowcap = 4 * nc;
+    // partial rows of a cluster: at most kRowsPerJ per j-particle (so an
+    // ensemble needs at most kRowsPerJ n rows, and a cluster splits the same
+    // way alone or in an ensemble), and never more than the workspace holds
+    int64_t rowcap = (int64_t)kRowsPerJ * nc;
     if (rowcap > d.rows_cap) rowcap = d.rows_cap;
     const int64_t s_r = rowcap / p.na;
     if (S > s_r) S = s_r;
@@ -1652,9 +1654,10 @@ __global__ __launch_bounds__(kWG) void k_force_sb(ForceArgs A) {
       if (d.item_prefix[mid] <= g) lo = mid; else hi = mid;
     }
     const ClusterPlan cp = d.plan_lpt[lo];
+    // split-major, as in k_force
     const int t_item = g - d.item_prefix[lo];
-    const int tile_i = t_item / cp.S;
-    const int split = t_item - tile_i * cp.S;
+    const int split = t_item / cp.tiles;
+    const int tile_i = t_item - split * cp.tiles;
     const int64_t js = cp.jb + (int64_t)split * cp.chunk;
     const int64_t je = (js + cp.chunk < cp.je) ? js + cp.chunk : cp.je;
     const double eps2 = d.eps2[cp.c];
