@@ -188,13 +188,14 @@ bool is_mixed(int precision) {
 nbody_tuning default_tuning(int precision) {
   nbody_tuning t;
   std::memset(&t, 0, sizeof t);
-  // measured on MI355X at N = 2^20: the mixed loop with FP64 differences runs
-  // fastest with one i per lane fed from scalar registers (its FP64 records
-  // as SGPR operands), the double-single one with one i per lane from LDS
-  // (more waves in flight), the FP64 loop with two i per lane
+  // measured on MI355X at N = 2^18 and 2^20: the mixed loop with FP64
+  // differences runs fastest with one i per lane fed from scalar registers
+  // (its FP64 records as SGPR operands), the double-single one with one i
+  // per lane from LDS (more waves in flight), the FP64 loop with two i per
+  // lane from scalar registers
   t.variant = precision == NBODY_MIXED      ? NBODY_VARIANT_S1
               : precision == NBODY_MIXED_DS ? NBODY_VARIANT_K1
-                                            : NBODY_VARIANT_K2;
+                                            : NBODY_VARIANT_S2;
   t.use_graph = NBODY_GRAPH_ON;
   t.steps_per_launch = 16;
   t.min_split_j = 256;
@@ -208,7 +209,10 @@ nbody_tuning default_tuning(int precision) {
     int P = 1;
     while (P < cover && P < 256) P <<= 1;
     t.i_slots[b] = P;
-    t.target_items[b] = 2048;
+    // from 2^16 active particles on, split j as finely as the partial rows
+    // allow: 2 MB chunks at N = 2^20, which each XCD's L2 holds while all
+    // resident workgroups stream them
+    t.target_items[b] = b >= 16 ? 131072 : 2048;
   }
   return t;
 }
