@@ -804,7 +804,17 @@ int nbody_step_blocks(nbody_ctx *c, double t_end, int64_t max_block_steps,
 
 int nbody_energy(nbody_ctx *c, double *out) {
   if (!c || !out) return fail(NBODY_EINVAL, "NULL argument");
-  const nbk::Tuning t = device_tuning(c, 1);
+  nbk::Tuning t = device_tuning(c, 1);
+  // the energy sums run one workgroup per cluster, each particle's split
+  // rows in turn: keep the potential evaluation to at most four j-splits
+  // per i-tile (target <= 4 x the fewest i-tiles of the bucket)
+  for (int b = 0; b < nbk::kBuckets; ++b) {
+    int P = t.i_slots[b] < 1 ? 1 : (t.i_slots[b] > 256 ? 256 : t.i_slots[b]);
+    while (P & (P - 1)) P &= P - 1;
+    const int64_t tiles_min = (((int64_t)1 << b) + P - 1) / P;
+    const int64_t cap = 4 * tiles_min;
+    if (t.target_items[b] > cap) t.target_items[b] = (int32_t)cap;
+  }
   NB_HIP(nbk::launch_all_active(c->d, t, c->stream));
   if (c->C > 1) NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, false, c->stream));
   int rc0 = force_launch(c, nbk::kModePot, nbk::kSrcState, 1, nullptr, c->d.active, c->grid_pot,

@@ -183,6 +183,45 @@ def test_split_and_tile_shape_invariance(prec, tol, jtol):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_full_evaluation_at_the_partial_row_bound(prec):
+    # every particle active with the largest split target: the plan cuts j
+    # into 32 chunks of 256 (32 partial rows per particle, the workspace
+    # bound) and hands the items out split-major; every variant against the
+    # oracle, and per K the broadcast kernel = the workgroup kernel bitwise
+    require_gpu()
+    n = 8192
+    m, x, v = ics.plummer(n, 21)
+    a_ref, j_ref = oracle.forces(x, v, m, 1e-3)
+    g = _ctx(m, x, v, 1e-3, prec)
+    got = {}
+    for variant in (binding.VARIANT_K1, binding.VARIANT_K2, binding.VARIANT_S1,
+                    binding.VARIANT_S2):
+        print(f"partial-row bound n={n} prec={prec} variant={variant}", flush=True)
+        g.set_tuning({"variant": variant, "i_slots": [256] * 25,
+                      "target_items": [1 << 20] * 25, "min_split_j": 64})
+        a, j = (to_np(t) for t in g.forces(x, v, m))
+        check_parity(a, j, a_ref, j_ref, is_mixed(prec), f"variant {variant}")
+        got[variant] = (a, j)
+    for lds, sb in ((binding.VARIANT_K1, binding.VARIANT_S1),
+                    (binding.VARIANT_K2, binding.VARIANT_S2)):
+        assert np.array_equal(got[lds][0], got[sb][0])
+        assert np.array_equal(got[lds][1], got[sb][1])
+    # an ensemble at the same bound: the clusters' rows add up to at most
+    # 32 per particle of the context
+    m, x, v, off = ics.ensemble(4, sizes=[4096, 300, 2048, 1537], seed=901)
+    eps = [1e-3, 2e-3, 1e-3, 5e-4]
+    ge = _ctx(m, x, v, eps, prec, cluster_offsets=off)
+    ge.set_tuning({"variant": binding.VARIANT_S1, "i_slots": [256] * 25,
+                   "target_items": [1 << 20] * 25, "min_split_j": 64})
+    acc, jerk = ge.forces(x, v, m)
+    a, j = to_np(acc), to_np(jerk)
+    for c in range(4):
+        sl = slice(off[c], off[c + 1])
+        a_ref, j_ref = oracle.forces(x[sl], v[sl], m[sl], eps[c])
+        check_parity(a[sl], j[sl], a_ref, j_ref, is_mixed(prec), f"cluster {c}")
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_bitwise_deterministic(prec):
     require_gpu()
     m, x, v = ics.plummer(3000, 6)
