@@ -56,6 +56,19 @@ def test_workspace_bytes_host_only():
     assert binding.workspace_bytes(1024, n_clusters=512, cluster_offsets=off, eps=[1e-3] * 512) > b1
 
 
+def test_precisions_accepted_and_workspace_holds_the_split_rows():
+    lib = binding.lib()
+    for prec in (binding.FP64, binding.MIXED, binding.MIXED_DS):
+        p = _params(precision=prec)
+        assert lib.nbody_workspace_bytes(C.byref(p), 16) > 0, prec
+    p = _params(precision=3)
+    assert lib.nbody_workspace_bytes(C.byref(p), 16) == 0
+    # the planner gives a cluster up to 32 partial rows (8 doubles each) per
+    # j-particle, so the workspace must hold 32 n rows besides the state
+    for n in (1 << 10, 1 << 16, 1 << 20):
+        assert binding.workspace_bytes(n) >= 32 * 8 * 8 * n, n
+
+
 @pytest.mark.parametrize("bad", [
     dict(eps=-1.0), dict(eps=float("nan")), dict(eta=0.0), dict(eta_start=-1.0),
     dict(level_min=5, level_max=4), dict(level_max=21), dict(level_min=-1),
