@@ -157,14 +157,20 @@ def test_set_state_validates():
 def test_energy_matches_oracle():
     require_gpu()
     m, x, v = ics.plummer(3000, 17)
-    for prec in (binding.FP64, binding.MIXED):
+    r = oracle.energy(x, v, m, 1e-3)
+    for prec in (binding.FP64, binding.MIXED, binding.MIXED_DS):
         g = binding.NBody(m, x, v, eps=1e-3, precision=prec)
-        e = g.energy()[0]
-        r = oracle.energy(x, v, m, 1e-3)
-        assert abs(e[0] - r["K"]) <= 1e-14 * abs(r["K"])
-        assert abs(e[1] - r["W"]) <= 1e-13 * abs(r["W"])
-        assert np.allclose(e[3:6], r["L"], rtol=1e-12, atol=1e-16)
-        assert np.allclose(e[6:9], r["P"], rtol=0, atol=1e-15)
+        # the context's tuning, then the largest split target (the energy
+        # evaluation caps its own splits)
+        for tu in (None, {"i_slots": [256] * 25, "target_items": [1 << 20] * 25,
+                          "min_split_j": 64}):
+            if tu:
+                g.set_tuning(tu)
+            e = g.energy()[0]
+            assert abs(e[0] - r["K"]) <= 1e-14 * abs(r["K"])
+            assert abs(e[1] - r["W"]) <= 1e-13 * abs(r["W"])
+            assert np.allclose(e[3:6], r["L"], rtol=1e-12, atol=1e-16)
+            assert np.allclose(e[6:9], r["P"], rtol=0, atol=1e-15)
 
 
 def test_nonfinite_input_reported():
