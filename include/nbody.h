@@ -67,15 +67,19 @@ typedef enum nbody_precision {
   NBODY_FP64 = 0,
   /* FP64 state, predictor and corrector; x_j - x_i and v_j - v_i are FP64
      subtractions of the FP64 predicted positions and velocities, rounded to
-     FP32 for the FP32 r^2, r.v, rsqrt, r^-3 and jerk products; FP32 sums of
-     every 64 j folded into a compensated (TwoSum) FP32 hi/lo pair.
-     Particles whose acceleration is dominated by a single term (see
-     nbody_tuning.refine_ratio) are re-evaluated in FP64. */
+     FP32 for the FP32 r^2, r.v, rsqrt, r^-3 and jerk products (the hardware
+     rsqrt corrected by its FMA residual); FP32 sums of every 64 j folded
+     into a compensated (TwoSum) FP32 hi/lo pair.  Pairs that dominate a
+     particle's jerk are evaluated in FP64 instead (near pairs, see
+     nbody_tuning.near_jerk), and particles whose acceleration is dominated
+     by a single term (nbody_tuning.refine_ratio) are re-evaluated in FP64;
+     acceleration and jerk then meet 1e-6 relative. */
   NBODY_MIXED = 1,
-  /* as NBODY_MIXED, but x_j - x_i formed in FP32 from the FP64 predicted
-     positions split into double-single pairs (the paper's software double
-     precision, Sect. 5: within an FP32 ulp of the FP64 difference), and
-     v_j - v_i from velocities rounded to FP32 (j records of 48 bytes) */
+  /* as NBODY_MIXED, but x_j - x_i and v_j - v_i formed in FP32 from the
+     FP64 predicted positions and velocities split into double-single pairs
+     (the paper's software double precision, Sect. 5): (hi_j - hi_i) +
+     (lo_j - lo_i), within an FP32 ulp of the FP64 difference (j records of
+     64 bytes) */
   NBODY_MIXED_DS = 2
 } nbody_precision;
 
@@ -237,8 +241,10 @@ int nbody_sync(nbody_ctx *c);
 /* Per-context counters since nbody_init (host, 8 int64): block steps,
  * interactions (n_active * n_cluster summed over steps), clamps at the
  * smallest step, current time of cluster 0 in ticks, particles re-evaluated
- * in FP64 by the mixed path (steps and nbody_forces), and 3 reserved.
- * Syncs. */
+ * in FP64 by the mixed path (steps and nbody_forces), near pairs evaluated
+ * in FP64 by the mixed path (see nbody_tuning.near_jerk), interactions of
+ * mixed block steps that ran on the FP64 kernel (steps with few active
+ * particles), and 1 reserved.  Syncs. */
 int nbody_stats(nbody_ctx *c, int64_t *out8);
 
 /* Kernel timing for measurement.  While enabled, block steps launch their
@@ -301,6 +307,19 @@ typedef struct nbody_tuning {
                                0: the same as variant.  In nbody_set_tuning
                                0 keeps the current value and -1 resets it
                                to 0. */
+  float near_jerk;          /* mixed paths, evaluations with jerk: a pair
+                               whose jerk scale m_j s_ij^-3/2 max_c
+                               |v_j,c - v_i,c| exceeds near_jerk times an
+                               estimate of i's jerk is evaluated in FP64 and
+                               left out of the FP32 sums (the few close
+                               neighbours whose terms set the FP32 error of
+                               the jerk; about two pairs per particle at
+                               the default 0.125).  The estimate is i's
+                               stored jerk in block steps, and a first FP64-
+                               free pass over the same evaluation otherwise
+                               (nbody_init, nbody_forces, the closing
+                               evaluation of nbody_step_symplectic).  < 0
+                               turns near pairs off. */
 } nbody_tuning;
 
 /* Read or replace the tuning of a context (host only, no device work). */

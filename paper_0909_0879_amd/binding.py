@@ -86,7 +86,7 @@ class Tuning(C.Structure):
         ("variant", C.c_int32), ("use_graph", C.c_int32), ("steps_per_launch", C.c_int32),
         ("min_split_j", C.c_int32), ("refine_ratio", C.c_float),
         ("i_slots", C.c_int32 * TUNE_BUCKETS), ("target_items", C.c_int32 * TUNE_BUCKETS),
-        ("acc_variant", C.c_int32),
+        ("acc_variant", C.c_int32), ("near_jerk", C.c_float),
     ]
 
     def as_dict(self):
@@ -94,7 +94,7 @@ class Tuning(C.Structure):
                 "steps_per_launch": self.steps_per_launch, "min_split_j": self.min_split_j,
                 "refine_ratio": self.refine_ratio,
                 "i_slots": list(self.i_slots), "target_items": list(self.target_items),
-                "acc_variant": self.acc_variant}
+                "acc_variant": self.acc_variant, "near_jerk": self.near_jerk}
 
     @classmethod
     def from_dict(cls, d):
@@ -109,6 +109,7 @@ class Tuning(C.Structure):
         for b, v in enumerate(d.get("target_items", [0] * TUNE_BUCKETS)):
             t.target_items[b] = int(v)
         t.acc_variant = int(d.get("acc_variant", 0))
+        t.near_jerk = float(d.get("near_jerk", 0.0))
         return t
 
 
@@ -327,7 +328,8 @@ class NBody:
         out = np.zeros(8, np.int64)
         check(lib().nbody_stats(self.ctx, out.ctypes.data_as(C.c_void_p)), "nbody_stats")
         return {"block_steps": int(out[0]), "interactions": int(out[1]),
-                "floor_clamps": int(out[2]), "t_tick": int(out[3]), "refined": int(out[4])}
+                "floor_clamps": int(out[2]), "t_tick": int(out[3]), "refined": int(out[4]),
+                "near_pairs": int(out[5]), "small_step_interactions": int(out[6])}
 
     def get_tuning(self) -> dict:
         t = Tuning()

@@ -35,6 +35,10 @@ constexpr int kEvPairs = 1024;
 // mixed path: re-evaluate in FP64 the particles whose largest acceleration
 // term exceeds this multiple of their net acceleration
 constexpr float kDefaultRefineRatio = 1.0f;
+// mixed path with jerk: evaluate in FP64 the pairs whose jerk scale
+// m_j s_ij^-3/2 max_c |v_ij,c| exceeds this fraction of the i-particle's
+// jerk (a few pairs per particle)
+constexpr float kDefaultNearJerk = 0.0625f;
 constexpr int64_t kMaxN = (int64_t)1 << 30;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -80,6 +84,7 @@ size_t carve(int64_t n, int32_t C, char *base, Dev *d) {
   t.ref_i = (int32_t *)take(sizeof(int32_t) * t.cap_active);
   t.ref_k = (int32_t *)take(sizeof(int32_t) * t.cap_active);
   t.ref_off = (int32_t *)take(sizeof(int32_t) * (C + 1));
+  t.theta = (float *)take(sizeof(float) * t.cap_active);
   t.pred = (void *)take((size_t)64 * n);
   t.pred_on = (int32_t *)take(sizeof(int32_t) * 4);
   t.work = (int32_t *)take(sizeof(int32_t) * 4);
@@ -200,6 +205,7 @@ nbody_tuning default_tuning(int precision) {
   t.steps_per_launch = 16;
   t.min_split_j = 256;
   t.refine_ratio = is_mixed(precision) ? kDefaultRefineRatio : -1.0f;
+  t.near_jerk = is_mixed(precision) ? kDefaultNearJerk : -1.0f;
   const int K = (t.variant == NBODY_VARIANT_K2) ? 2 : 1;
   for (int b = 0; b < NBODY_TUNE_BUCKETS; ++b) {
     // one i-tile covers the bucket [2^b, 2^(b+1)) when possible
@@ -333,7 +339,8 @@ int harvest_events(nbody_ctx *c);
 // rec_kind >= 0 (a PlanKind): build the evaluation's j records first when its
 // active set is large, and let the broadcast kernel take it when enabled.
 int force_launch(nbody_ctx *c, int mode, int src, int K, const nbk::RawSrc *raw,
-                 const int32_t *list, int grid, hipStream_t s, int rec_kind = -1) {
+                 const int32_t *list, int grid, hipStream_t s, int rec_kind = -1,
+                 nbk::NearSpec nr = nbk::NearSpec{nbk::kNearNone, 0.0f}) {
   const bool prof = c->profiling && s == c->stream;
   const bool use_pred = rec_kind >= 0;
   // clusters of a mixed block step with few active particles run in FP64
@@ -350,16 +357,16 @@ int force_launch(nbody_ctx *c, int mode, int src, int K, const nbk::RawSrc *raw,
   }
   if (prof) NB_HIP(hipEventRecord(c->ev[2 * c->ev_used], s));
   NB_HIP(nbk::launch_force(c->d, mode, rec_only ? nbk::kSrcRec : src, K, raw, list,
-                            use_pred ? nbk::kRoleMain : nbk::kRoleAlways,
+                            use_pred ? nbk::kRoleMain : nbk::kRoleAlways, nr,
                             rec_only ? (nbk::mode_acc_only(mode) ? c->grid_acc_rec : c->grid_rec)
                                      : grid,
                             s));
   if (use_pred && sb)
-    NB_HIP(nbk::launch_force_sb(c->d, mode, K, raw, list,
+    NB_HIP(nbk::launch_force_sb(c->d, mode, K, raw, list, nr,
                                 nbk::mode_acc_only(mode) ? c->grid_acc_sb : c->grid_sb, s));
   if (small)
     NB_HIP(nbk::launch_force(c->d, nbk::kModeFP64, src, K, raw, list, nbk::kRoleSmall,
-                             c->grid_small, s));
+                             nbk::NearSpec{nbk::kNearNone, 0.0f}, c->grid_small, s));
   if (prof) {
     NB_HIP(hipEventRecord(c->ev[2 * c->ev_used + 1], s));
     // the potential kernel (energy diagnostics) is not counted; FP64 launches
@@ -392,16 +399,31 @@ float refine_ratio(const nbody_ctx *c) {
   return (is_mixed(c->prec) && c->tune.refine_ratio > 0.0f) ? c->tune.refine_ratio : 0.0f;
 }
 
+// Near pairs of a mixed evaluation with jerk, from the given threshold
+// source, when the context's precision and tuning use them.
+nbk::NearSpec near_spec(const nbody_ctx *c, int mode, int src) {
+  nbk::NearSpec nr;
+  nr.c = c->tune.near_jerk;
+  const bool on = is_mixed(c->prec) && nr.c > 0.0f && !nbk::mode_acc_only(mode) &&
+                  mode != nbk::kModePot && mode != nbk::kModeFP64;
+  nr.src = on ? src : nbk::kNearNone;
+  if (!on) nr.c = 0.0f;
+  return nr;
+}
+
 // Sum the partial rows into fsum and, on the mixed path, re-evaluate the
 // flagged entries with the FP64 kernel (a second plan over the flagged list).
+// nr: where the evaluation's near-pair thresholds came from (the flags test
+// them against the jerk found).
 int sum_and_refine(nbody_ctx *c, const int32_t *list, int64_t na_host, const nbk::RawSrc *raw,
-                   hipStream_t s, bool acc_only = false) {
+                   hipStream_t s, bool acc_only, nbk::NearSpec nr) {
   const float ratio = refine_ratio(c);
   const nbk::Tuning t1 = device_tuning(c, 1);
   const bool api = raw != nullptr;
   const int ref_kind = api ? nbk::kPlanApiRefine : nbk::kPlanRefine;
   const int64_t api_nj = api ? raw->n_j : 0;
-  NB_HIP(nbk::launch_sum_and_flag(c->d, list, na_host, ratio, t1, ref_kind, api_nj, s));
+  NB_HIP(nbk::launch_sum_and_flag(c->d, list, na_host, ratio, nr, false, t1, ref_kind, api_nj,
+                                  s));
   if (ratio <= 0.0f) return NBODY_OK;
   if (!nbk::plan_fused(c->d))
     NB_HIP(nbk::launch_plan(c->d, t1, ref_kind, api_nj, false, s));
@@ -414,17 +436,40 @@ int sum_and_refine(nbody_ctx *c, const int32_t *list, int64_t na_host, const nbk
   return NBODY_OK;
 }
 
-// One Hermite block step for every cluster, enqueued on s.
+// One mixed evaluation with jerk when no jerk estimate is at hand (initial
+// state, full re-evaluations, nbody_forces): a first pass without near pairs
+// gives each entry's jerk, from which the second pass takes its near-pair
+// thresholds.  `launch` enqueues the force launch(es) of one pass (the plan
+// and the records stay valid; the item counters are reset in between).
+template <class F>
+int two_pass(nbody_ctx *c, const int32_t *list, int64_t na_host, const nbk::RawSrc *raw,
+             hipStream_t s, int mode, F launch) {
+  const nbk::NearSpec first = near_spec(c, mode, nbk::kNearNone);
+  const nbk::NearSpec second = near_spec(c, mode, nbk::kNearList);
+  int rc = launch(first);
+  if (rc) return rc;
+  if (second.src == nbk::kNearList) {
+    const nbk::Tuning t1 = device_tuning(c, 1);
+    NB_HIP(nbk::launch_sum_and_flag(c->d, list, na_host, 0.0f, second, true, t1, 0, 0, s));
+    NB_HIP(nbk::launch_fill32(c->d.work, 0, 2, s));
+    if ((rc = launch(second))) return rc;
+  }
+  return sum_and_refine(c, list, na_host, raw, s, nbk::mode_acc_only(mode), second);
+}
+
+// One Hermite block step for every cluster, enqueued on s.  The near-pair
+// thresholds come from each active particle's stored jerk.
 int enqueue_block_step(nbody_ctx *c, hipStream_t s) {
   const nbk::Tuning t = device_tuning(c, c->K);
   const bool allow_small = is_mixed(c->prec);
   NB_HIP(nbk::launch_compact(c->d, t, allow_small, s));
   if (!nbk::plan_fused(c->d))
     NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanStep, 0, allow_small, s));
+  const nbk::NearSpec nr = near_spec(c, mode_of(c), nbk::kNearState);
   int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->d.active,
-                        c->grid_state, s, nbk::kPlanStep);
+                        c->grid_state, s, nbk::kPlanStep, nr);
   if (rc) return rc;
-  if ((rc = sum_and_refine(c, c->d.active, -1, nullptr, s))) return rc;
+  if ((rc = sum_and_refine(c, c->d.active, -1, nullptr, s, false, nr))) return rc;
   NB_HIP(nbk::launch_correct(c->d, c->eta, c->dt_shared, c->lmin, c->lmax, s));
   return NBODY_OK;
 }
@@ -473,12 +518,15 @@ int full_evaluation_into_state(nbody_ctx *c) {
   const nbk::Tuning t = device_tuning(c, c->K);
   NB_HIP(nbk::launch_all_active(c->d, t, c->stream));
   if (c->C > 1) NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, false, c->stream));
-  int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->d.active,
-                        c->grid_state, c->stream, nbk::kPlanState);
-  if (rc) return rc;
   // all particles start at T = T_next = 0, so the re-evaluation plan
   // (predicting to T_next) sees the same positions
-  if ((rc = sum_and_refine(c, c->d.active, -1, nullptr, c->stream))) return rc;
+  int rc = two_pass(c, c->d.active, -1, nullptr, c->stream, mode_of(c),
+                    [&](nbk::NearSpec nr) {
+                      return force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr,
+                                          c->d.active, c->grid_state, c->stream,
+                                          nbk::kPlanState, nr);
+                    });
+  if (rc) return rc;
   NB_HIP(nbk::launch_init_levels(c->d, c->eta_start, c->dt_shared, c->lmin, c->lmax,
                                  c->stream));
   return NBODY_OK;
@@ -528,10 +576,11 @@ int api_forces(nbody_ctx *c, bool acc_only, const int32_t *i_active, int64_t n_a
     r.jerk = jerk ? jerk + 3 * k0 : nullptr;
     NB_HIP(nbk::launch_api_group(c->d, r, t, c->stream));
     if (c->C > 1) NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanApi, r.n_j, false, c->stream));
-    int rc = force_launch(c, mode, nbk::kSrcRaw, K, &r, r.i_active, grid, c->stream,
-                          nbk::kPlanApi);
+    int rc = two_pass(c, r.i_active, r.n_active, &r, c->stream, mode, [&](nbk::NearSpec nr) {
+      return force_launch(c, mode, nbk::kSrcRaw, K, &r, r.i_active, grid, c->stream,
+                          nbk::kPlanApi, nr);
+    });
     if (rc) return rc;
-    if ((rc = sum_and_refine(c, r.i_active, r.n_active, &r, c->stream, acc_only))) return rc;
     NB_HIP(nbk::launch_api_finalize(c->d, r, c->stream));
   }
   return NBODY_OK;
@@ -663,7 +712,8 @@ int nbody_step_symplectic(nbody_ctx *c, int scheme, double h, int64_t n_steps,
     int r = force_launch(c, mode, nbk::kSrcState, c->Ka, nullptr, c->d.active, c->grid_acc_state,
                          s, nbk::kPlanState);
     if (r) return r;
-    return sum_and_refine(c, c->d.active, -1, nullptr, s, /*acc_only=*/true);
+    return sum_and_refine(c, c->d.active, -1, nullptr, s, /*acc_only=*/true,
+                          nbk::NearSpec{nbk::kNearNone, 0.0f});
   };
   // one step: every stage kicks (merging the previous stage's half kick),
   // drifts and evaluates; returns the half kick still owed
@@ -869,7 +919,9 @@ int nbody_stats(nbody_ctx *c, int64_t *out8) {
   out8[2] = c->pinned[nbk::kCtrFloor];
   out8[3] = c->T_host[0];
   out8[4] = c->pinned[nbk::kCtrRefined];
-  out8[5] = out8[6] = out8[7] = 0;
+  out8[5] = c->pinned[nbk::kCtrNear];
+  out8[6] = c->pinned[nbk::kCtrSmallInter];
+  out8[7] = 0;
   return NBODY_OK;
 }
 
@@ -967,6 +1019,10 @@ int nbody_set_tuning(nbody_ctx *c, const nbody_tuning *t) {
   if (t->refine_ratio != 0.0f) {
     if (!std::isfinite(t->refine_ratio)) return fail(NBODY_EINVAL, "refine_ratio must be finite");
     n.refine_ratio = t->refine_ratio;
+  }
+  if (t->near_jerk != 0.0f) {
+    if (!std::isfinite(t->near_jerk)) return fail(NBODY_EINVAL, "near_jerk must be finite");
+    n.near_jerk = t->near_jerk;
   }
   for (int b = 0; b < NBODY_TUNE_BUCKETS; ++b) {
     if (t->i_slots[b]) {

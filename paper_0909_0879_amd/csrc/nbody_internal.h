@@ -25,7 +25,14 @@ constexpr int64_t kSmallWork = (int64_t)1 << 27;   // and so are those of up to
                                     // this many interactions (n_active x N_c)
 constexpr int kRowsPerJ = 32;       // partial rows a cluster may take per j-particle
 constexpr int kRowStride = 8;       // doubles per partial row: a(3), jerk(3),
-                                    // bound on the largest acc term, pad
+                                    // bound on the largest acc term, far-field
+                                    // jerk scale (double-single)
+constexpr double kFarRatio = 8.0;   // double-single: a far-field jerk scale
+                                    // above this many times the jerk sends the
+                                    // particle to FP64
+constexpr double kNearStale = 2.0;  // a near-pair threshold taken from a jerk
+                                    // estimate more than this many times the
+                                    // jerk found sends the particle to FP64
 
 // kErrState: a state given to nbody_set_state, or found by a driver, that
 // breaks the block-step invariants
@@ -39,6 +46,9 @@ enum Ctr : int {
   kCtrNotDone = 3,      // clusters still short of t_end after the last step
   kCtrTend = 4,         // t_end in ticks for nbody_step
   kCtrRefined = 5,      // entries re-evaluated in FP64 (mixed path)
+  kCtrNear = 6,         // near pairs evaluated in FP64 (mixed path)
+  kCtrSmallInter = 7,   // interactions of mixed block steps run by the FP64
+                        // kernel (small steps)
   kCtrCount = 8
 };
 
@@ -126,6 +136,8 @@ struct Dev {
   int32_t *ref_i;         // cap_active: particles re-evaluated in FP64
   int32_t *ref_k;         // cap_active: their active-list positions
   int32_t *ref_off;       // C + 1: per-cluster offsets in ref_i (last = count)
+  float *theta;           // cap_active: near-pair threshold of each entry,
+                          // from the first pass of a two-pass evaluation
   // j records of an evaluation with many active particles
   void *pred;             // n records of 64 bytes (the LDS record format)
   int32_t *pred_on;       // 0 none, 1 built, 2 built for the broadcast kernel
@@ -163,6 +175,16 @@ constexpr bool mode_mixed(int m) {
   return m == kModeMixed || m == kModeMixedAcc || m == kModeMixed64 || m == kModeMixed64Acc;
 }
 
+// Near pairs of the mixed evaluations with jerk (evaluated in FP64, left out
+// of the FP32 sums): the threshold of each i is c times a jerk estimate,
+// the magnitude of its stored jerk (kNearState: block steps) or the first
+// pass's jerk of its entry (kNearList: d.theta holds c |jerk| already);
+// kNearNone: no near pairs.
+enum NearSrc : int { kNearNone = 0, kNearState = 1, kNearList = 2 };
+struct NearSpec {
+  int src;
+  float c;
+};
 // Host-side launchers (defined in nbody_kernels.hip).  Every launcher only
 // enqueues on `s`; none synchronises.  They return the hipError_t of the
 // launch.
@@ -191,12 +213,16 @@ hipError_t launch_compact(const Dev &d, const Tuning &t, bool allow_small, hipSt
 // small-step FP64 launch (mixed contexts).
 hipError_t launch_plan(const Dev &d, const Tuning &t, int kind,
                        int64_t api_nj, bool allow_small, hipStream_t s);
-// Sum each active entry's partial rows into fsum; with refine_ratio > 0 also
-// flag entries whose largest acceleration term exceeds refine_ratio times
-// their net acceleration, and build the grouped re-evaluation list.
+// Sum each active entry's partial rows into fsum.  theta_out (first pass of
+// a two-pass mixed evaluation): store each entry's near-pair threshold
+// nr.c |jerk| in d.theta.  Otherwise, with refine_ratio > 0, flag the entries
+// whose largest acceleration term exceeds refine_ratio times their net
+// acceleration or whose near-pair threshold came from a jerk estimate above
+// kNearStale times their jerk (nr.src), and build the grouped re-evaluation
+// list.
 hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_host,
-                               float refine_ratio, const Tuning &t1, int ref_kind,
-                               int64_t api_nj, hipStream_t s);
+                               float refine_ratio, const NearSpec &nr, bool theta_out,
+                               const Tuning &t1, int ref_kind, int64_t api_nj, hipStream_t s);
 hipError_t launch_refine_finalize(const Dev &d, hipStream_t s);
 // Which work a force launch takes.  The plan splits the items in two:
 // [0, work[2]) for the main launches, [work[2], total) for the small-step
@@ -209,7 +235,7 @@ hipError_t launch_refine_finalize(const Dev &d, hipStream_t s);
 enum Role : int { kRoleAlways = 0, kRoleMain = 1, kRoleSmall = 2 };
 hipError_t launch_force(const Dev &d, int mode, int src, int K,
                         const RawSrc *raw, const int32_t *list, int role,
-                        int grid, hipStream_t s);
+                        const NearSpec &nr, int grid, hipStream_t s);
 // Build the records of one evaluation into d.pred when its active set is at
 // least 1/16 of its j particles, and set *d.pred_on (0, 1, or 2 when the
 // broadcast kernel may take it: allow_sb and kWG i-slots in every cluster
@@ -220,7 +246,7 @@ hipError_t launch_records(const Dev &d, int mode, int kind, const RawSrc *raw,
 // The broadcast force kernel (j records in scalar registers); it does the
 // evaluation only when *d.pred_on == 2 and returns at once otherwise.
 hipError_t launch_force_sb(const Dev &d, int mode, int K, const RawSrc *raw,
-                           const int32_t *list, int grid, hipStream_t s);
+                           const int32_t *list, const NearSpec &nr, int grid, hipStream_t s);
 int force_sb_grid_size(int mode, int K, int device);
 // Symplectic drivers: kick (v += ck a, a from fsum) then drift (x += cd v)
 // (with one cluster also the next evaluation's kPlanState plan, tuning t);

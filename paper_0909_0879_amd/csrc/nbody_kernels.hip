@@ -128,19 +128,20 @@ struct JRec64 {          // one j-particle for FP64 and potential modes, 64 byte
   int32_t idx;
 };
 
-struct JRecDS {          // one j-particle for mixed mode, 48 bytes: position as a
-  float xh, yh, zh, m;   // double-single pair (hi + lo = the FP64 predicted
-  float xl, yl, zl, pad; // position to ~48 bits), velocity and mass in FP32
-  float vx, vy, vz;
-  int32_t idx;
+struct JRecDS {          // one j-particle for the double-single mode, 64 bytes:
+  float xh, yh, zh, m;   // position and velocity as double-single pairs (hi +
+  float xl, yl, zl, pad0;  // lo = the FP64 predicted value to ~48 bits), the
+  float vx, vy, vz;      // mass (in units of the cluster's reference mass)
+  int32_t idx;           // in FP32
+  float vlx, vly, vlz, pad1;
 };
 
 struct I64 {             // an i-particle in registers, FP64 modes
   double x[3], v[3];
 };
 
-struct IDS {             // an i-particle in registers, mixed mode
-  float xh[3], xl[3], v[3];
+struct IDS {             // an i-particle in registers, mixed mode: position
+  float xh[3], xl[3], v[3], vl[3];   // and velocity as (hi, lo) pairs
 };
 
 __device__ __forceinline__ void make_i(const double *xp, const double *vp, I64 &s) {
@@ -159,26 +160,36 @@ __device__ __forceinline__ void make_i(const double *xp, const double *vp, IDS &
     s.xh[c] = h;
     s.xl[c] = (float)(xp[c] - (double)h);
     s.v[c] = (float)vp[c];
+    s.vl[c] = (float)(vp[c] - (double)s.v[c]);
   }
 }
 
+// Reference mass of a cluster's FP32 sums: the mass of the first particle of
+// its j range (1 if that is zero).  The FP32 pair terms take m_j / m_ref, so
+// equal masses enter them as exactly 1 and the rounding of a mass such as
+// 1/N does not scale all FP32 terms against the FP64 near terms of the same
+// sum; the kernels scale their sums back by m_ref in FP64.
+__device__ __forceinline__ double mass_ref(double m0) { return m0 != 0.0 ? m0 : 1.0; }
+
+// FP64 records keep m exact (FP64 and potential modes) and m / m_ref in FP32.
 __device__ __forceinline__ void make_rec(const double *xp, const double *vp, double m,
-                                         int32_t idx, JRec64 &r) {
+                                         int32_t idx, JRec64 &r, double mref) {
   r.x = xp[0]; r.y = xp[1]; r.z = xp[2]; r.m = m;
   r.vx = vp[0]; r.vy = vp[1]; r.vz = vp[2];
-  r.mf = (float)m;
+  r.mf = (float)(m / mref);
   r.idx = idx;
 }
 
 __device__ __forceinline__ void make_rec(const double *xp, const double *vp, double m,
-                                         int32_t idx, JRecDS &r) {
+                                         int32_t idx, JRecDS &r, double mref) {
   IDS s;
   make_i(xp, vp, s);
   r.xh = s.xh[0]; r.yh = s.xh[1]; r.zh = s.xh[2];
   r.xl = s.xl[0]; r.yl = s.xl[1]; r.zl = s.xl[2];
   r.vx = s.v[0]; r.vy = s.v[1]; r.vz = s.v[2];
-  r.m = (float)m;
-  r.pad = 0.0f;
+  r.vlx = s.vl[0]; r.vly = s.vl[1]; r.vlz = s.vl[2];
+  r.m = (float)(m / mref);
+  r.pad0 = r.pad1 = 0.0f;
   r.idx = idx;
 }
 
@@ -209,38 +220,102 @@ __device__ __forceinline__ void pair_fp64(const I64 &I, int iidx, const JRec64 &
   t[5] = fma(mr3, fma(-al, dz, wz), t[5]);
 }
 
-// Mixed precision: x_j - x_i from the double-single pairs, (hi_j - hi_i) +
-// (lo_j - lo_i), which is the FP64 difference rounded to FP32 within an ulp
-// (the hi difference is exact for close pairs); everything after it in FP32.
+// Per-i quantities the mixed paths collect for k_sum_flag: `a`, a bound on
+// the largest single acceleration term, max_j m_j / s_ij (a close encounter
+// or a heavy neighbour dominates the sum); `f1`, double-single form only, the
+// sum over the pairs left in the FP32 sums of the jerk scale m_j s_ij^-3/2
+// max_c |v_ij,c|: the far field's terms mostly share a direction (the mean
+// field's tide), so a part of their rounding adds up coherently, which
+// matters where the jerk is a small remainder of a far field many times
+// larger.
+struct Bnd {
+  float a, f1;
+};
+
+// FP32 factors shared by the mixed pair terms.  The hardware rsqrt is good
+// to about one FP32 ulp, and r^-2 and r^-3 would carry its error two and
+// three times over; with r0 = rsqrt(s), e = 1 - s r0^2 is its residual
+// (one FMA; its own rounding is of second order), and r0^2 (1 + e) is 1/s
+// to about half an ulp.  1/s feeds the largest-term bound, m r^-3 and the
+// jerk's 3 (r.v) / s; r^-3 = (m / s) r0 keeps r0's error only once.
+struct Fac32 {
+  float rinv, rinv2, mq, mr3;
+};
+
+__device__ __forceinline__ Fac32 fac32(float s, float m, float r0) {
+  Fac32 f;
+  const float r0sq = r0 * r0;
+  const float e = fmaf(-s, r0sq, 1.0f);
+  f.rinv = r0;
+  f.rinv2 = fmaf(r0sq, e, r0sq);
+  f.mq = m * f.rinv2;       // m / s >= |this pair's acceleration term|
+  f.mr3 = f.mq * r0;
+  return f;
+}
+
+// Near pairs of the mixed path.  A pair's jerk term m r^-3 (v_ij - 3 (r.v)
+// r / s) carries an FP32 rounding error of a few ulp of m r^-3 |v_ij| (the
+// differences, 1/s and r.v each enter 3 (r.v) r / s, whose size is up to
+// 3 |v_ij|), and the jerk of most particles is dominated by a handful of
+// close neighbours whose terms largely cancel; those few terms set the
+// error of the sum.  A pair whose jerk scale m r^-3 max_c |v_ij,c| exceeds
+// the threshold th of its i (a fraction of i's jerk) is therefore left out
+// of the FP32 sums and evaluated in FP64 instead (near_fp64); with th at
+// 1/8 of |jerk| that is about two pairs per particle.  th = +inf turns it
+// off.  Returns the wave's lane mask of near pairs (a NaN scale counts as
+// near, so a non-finite input still reaches the sums) and the m r^-3 that
+// the FP32 sums take: zero in the near lanes.  The compare's lane mask
+// serves both the select and the queueing (one compare per pair).
+__device__ __forceinline__ uint64_t near_pair(float mr3, float wx, float wy, float wz,
+                                              float th, float &mr3_fp32, float &w) {
+  w = fmaxf(fmaxf(fabsf(wx), fabsf(wy)), fabsf(wz));
+  constexpr int kCmpUGT = 10;      // unordered or greater than
+  const uint64_t m = __builtin_amdgcn_fcmpf(mr3 * w, th, kCmpUGT);
+  asm("v_cndmask_b32_e64 %0, %1, 0, %2" : "=v"(mr3_fp32) : "v"(mr3), "s"(m));
+  return m;
+}
+
+// Mixed precision: x_j - x_i and v_j - v_i from the double-single pairs,
+// (hi_j - hi_i) + (lo_j - lo_i), which is the FP64 difference rounded to
+// FP32 within an ulp (the hi difference is exact for close pairs);
+// everything after it in FP32.
 // SELF: this tile may hold the i-particle itself; its slot must not count in
-// the largest-term bound (its terms are exactly zero, but m_i / eps^2 is not).
+// the largest-term bound (its terms are exactly zero, but m_i / eps^2 is not;
+// its velocity difference is zero, so it is never a near pair).
 template <bool MASK, bool SELF>
-__device__ __forceinline__ void pair_mixed(const IDS &I, int iidx, const JRecDS &r,
-                                           float eps2, float *t, int &dom, float &tmx) {
+__device__ __forceinline__ uint64_t pair_mixed(const IDS &I, int iidx, const JRecDS &r,
+                                           float eps2, float th, float *t, int &dom,
+                                           Bnd &ba) {
   const float dx = (r.xh - I.xh[0]) + (r.xl - I.xl[0]);
   const float dy = (r.yh - I.xh[1]) + (r.yl - I.xl[1]);
   const float dz = (r.zh - I.xh[2]) + (r.zl - I.xl[2]);
-  const float wx = r.vx - I.v[0], wy = r.vy - I.v[1], wz = r.vz - I.v[2];
+  const float wx = (r.vx - I.v[0]) + (r.vlx - I.vl[0]);
+  const float wy = (r.vy - I.v[1]) + (r.vly - I.vl[1]);
+  const float wz = (r.vz - I.v[2]) + (r.vlz - I.vl[2]);
   const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
   const float rv = fmaf(dx, wx, fmaf(dy, wy, dz * wz));
-  float rinv = __builtin_amdgcn_rsqf(s);
+  float r0 = __builtin_amdgcn_rsqf(s);
   if (MASK) {
     if (dx == 0.0f && dy == 0.0f && dz == 0.0f) {
-      rinv = 0.0f;
+      r0 = 0.0f;
       dom |= (r.idx != iidx);
     }
   }
-  const float rinv2 = rinv * rinv;
-  const float mq = r.m * rinv2;       // m / s >= |this pair's acceleration term|
-  const float mr3 = mq * rinv;
-  const float al = (3.0f * rv) * rinv2;
-  tmx = fmaxf(tmx, (SELF && r.idx == iidx) ? 0.0f : mq);
+  const Fac32 f = fac32(s, r.m, r0);
+  const float al = (3.0f * rv) * f.rinv2;
+  ba.a = fmaxf(ba.a, (SELF && r.idx == iidx) ? 0.0f : f.mq);
+  float mr3, wm;
+  const uint64_t nr = near_pair(f.mr3, wx, wy, wz, th, mr3, wm);
+  // double-single differences carry about twice the rounding of the FP64
+  // ones: the pairs left in FP32 also count in the far-field error scale
+  ba.f1 = fmaf(mr3, wm, ba.f1);
   t[0] = fmaf(mr3, dx, t[0]);
   t[1] = fmaf(mr3, dy, t[1]);
   t[2] = fmaf(mr3, dz, t[2]);
   t[3] = fmaf(mr3, fmaf(-al, dx, wx), t[3]);
   t[4] = fmaf(mr3, fmaf(-al, dy, wy), t[4]);
   t[5] = fmaf(mr3, fmaf(-al, dz, wz), t[5]);
+  return nr;
 }
 
 // Acceleration only: the same operations as the two functions above up to
@@ -265,80 +340,102 @@ __device__ __forceinline__ void pair_fp64_acc(const I64 &I, int iidx, const JRec
 }
 
 template <bool MASK, bool SELF>
-__device__ __forceinline__ void pair_mixed_acc(const IDS &I, int iidx, const JRecDS &r,
-                                               float eps2, float *t, int &dom, float &tmx) {
+__device__ __forceinline__ uint64_t pair_mixed_acc(const IDS &I, int iidx, const JRecDS &r,
+                                               float eps2, float th, float *t, int &dom,
+                                               Bnd &ba) {
   const float dx = (r.xh - I.xh[0]) + (r.xl - I.xl[0]);
   const float dy = (r.yh - I.xh[1]) + (r.yl - I.xl[1]);
   const float dz = (r.zh - I.xh[2]) + (r.zl - I.xl[2]);
   const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
-  float rinv = __builtin_amdgcn_rsqf(s);
+  float r0 = __builtin_amdgcn_rsqf(s);
   if (MASK) {
     if (dx == 0.0f && dy == 0.0f && dz == 0.0f) {
-      rinv = 0.0f;
+      r0 = 0.0f;
       dom |= (r.idx != iidx);
     }
   }
-  const float rinv2 = rinv * rinv;
-  const float mq = r.m * rinv2;
-  const float mr3 = mq * rinv;
-  tmx = fmaxf(tmx, (SELF && r.idx == iidx) ? 0.0f : mq);
-  t[0] = fmaf(mr3, dx, t[0]);
-  t[1] = fmaf(mr3, dy, t[1]);
-  t[2] = fmaf(mr3, dz, t[2]);
+  const Fac32 f = fac32(s, r.m, r0);
+  ba.a = fmaxf(ba.a, (SELF && r.idx == iidx) ? 0.0f : f.mq);
+  t[0] = fmaf(f.mr3, dx, t[0]);
+  t[1] = fmaf(f.mr3, dy, t[1]);
+  t[2] = fmaf(f.mr3, dz, t[2]);
+  return 0;
 }
 
 // Mixed precision with FP64 differences: x_j - x_i and v_j - v_i are taken
 // in FP64 from the FP64 records and rounded to FP32; everything after them is
 // the FP32 arithmetic of pair_mixed.
 template <bool MASK, bool SELF>
-__device__ __forceinline__ void pair_mixed64(const I64 &I, int iidx, const JRec64 &r,
-                                             float eps2, float *t, int &dom, float &tmx) {
+__device__ __forceinline__ uint64_t pair_mixed64(const I64 &I, int iidx, const JRec64 &r,
+                                             float eps2, float th, float *t, int &dom,
+                                             Bnd &ba) {
   const float dx = (float)(r.x - I.x[0]), dy = (float)(r.y - I.x[1]),
               dz = (float)(r.z - I.x[2]);
   const float wx = (float)(r.vx - I.v[0]), wy = (float)(r.vy - I.v[1]),
               wz = (float)(r.vz - I.v[2]);
   const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
   const float rv = fmaf(dx, wx, fmaf(dy, wy, dz * wz));
-  float rinv = __builtin_amdgcn_rsqf(s);
+  float r0 = __builtin_amdgcn_rsqf(s);
   if (MASK) {
     if (dx == 0.0f && dy == 0.0f && dz == 0.0f) {
-      rinv = 0.0f;
+      r0 = 0.0f;
       dom |= (r.idx != iidx);
     }
   }
-  const float rinv2 = rinv * rinv;
-  const float mq = r.mf * rinv2;
-  const float mr3 = mq * rinv;
-  const float al = (3.0f * rv) * rinv2;
-  tmx = fmaxf(tmx, (SELF && r.idx == iidx) ? 0.0f : mq);
+  const Fac32 f = fac32(s, r.mf, r0);
+  const float al = (3.0f * rv) * f.rinv2;
+  ba.a = fmaxf(ba.a, (SELF && r.idx == iidx) ? 0.0f : f.mq);
+  float mr3, wm;
+  const uint64_t nr = near_pair(f.mr3, wx, wy, wz, th, mr3, wm);
   t[0] = fmaf(mr3, dx, t[0]);
   t[1] = fmaf(mr3, dy, t[1]);
   t[2] = fmaf(mr3, dz, t[2]);
   t[3] = fmaf(mr3, fmaf(-al, dx, wx), t[3]);
   t[4] = fmaf(mr3, fmaf(-al, dy, wy), t[4]);
   t[5] = fmaf(mr3, fmaf(-al, dz, wz), t[5]);
+  return nr;
 }
 
 template <bool MASK, bool SELF>
-__device__ __forceinline__ void pair_mixed64_acc(const I64 &I, int iidx, const JRec64 &r,
-                                                 float eps2, float *t, int &dom, float &tmx) {
+__device__ __forceinline__ uint64_t pair_mixed64_acc(const I64 &I, int iidx, const JRec64 &r,
+                                                 float eps2, float th, float *t, int &dom,
+                                                 Bnd &ba) {
   const float dx = (float)(r.x - I.x[0]), dy = (float)(r.y - I.x[1]),
               dz = (float)(r.z - I.x[2]);
   const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
-  float rinv = __builtin_amdgcn_rsqf(s);
+  float r0 = __builtin_amdgcn_rsqf(s);
   if (MASK) {
     if (dx == 0.0f && dy == 0.0f && dz == 0.0f) {
-      rinv = 0.0f;
+      r0 = 0.0f;
       dom |= (r.idx != iidx);
     }
   }
-  const float rinv2 = rinv * rinv;
-  const float mq = r.mf * rinv2;
-  const float mr3 = mq * rinv;
-  tmx = fmaxf(tmx, (SELF && r.idx == iidx) ? 0.0f : mq);
-  t[0] = fmaf(mr3, dx, t[0]);
-  t[1] = fmaf(mr3, dy, t[1]);
-  t[2] = fmaf(mr3, dz, t[2]);
+  const Fac32 f = fac32(s, r.mf, r0);
+  ba.a = fmaxf(ba.a, (SELF && r.idx == iidx) ? 0.0f : f.mq);
+  t[0] = fmaf(f.mr3, dx, t[0]);
+  t[1] = fmaf(f.mr3, dy, t[1]);
+  t[2] = fmaf(f.mr3, dz, t[2]);
+  return 0;
+}
+
+// The FP64 term of a near pair (pair_fp64's arithmetic on the FP64 predicted
+// states), added to the compensated FP32 sums: each component as the FP32
+// pair hi = T rounded, lo = (T - hi) rounded, hi through TwoSum into
+// (shi, slo) and lo into slo.
+__device__ __forceinline__ void near_add(double T, float &shi, float &slo) {
+  const float h = (float)T;
+  const float l = (float)(T - (double)h);
+  two_sum_into(shi, slo, h);
+  slo += l;
+}
+
+__device__ __forceinline__ void near_fp64(const I64 &I, const JRec64 &r, double eps2,
+                                          float *shi, float *slo) {
+  double tt[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int dd = 0;
+  pair_fp64<false>(I, -1, r, eps2, tt, dd);   // a near pair has s > 0
+#pragma unroll
+  for (int c = 0; c < 6; ++c) near_add(tt[c], shi[c], slo[c]);
 }
 
 // Potential -m_j / sqrt(s) (energy diagnostics).  The i's own pair is
@@ -424,55 +521,124 @@ __device__ __forceinline__ void fold(typename Traits<MODE>::T (&t)[K][Traits<MOD
     }
 }
 
+// Modes whose FP32 pairs may hand near pairs to FP64 (acceleration and jerk).
+constexpr bool mode_near(int m) { return m == kModeMixed || m == kModeMixed64; }
+
+// One j record against the K i-particles of a lane; nr[k] is the wave's lane
+// mask of near pairs with i-particle k (left out of the FP32 sums, see
+// near_pair).
 template <int MODE, int K, bool MASK, bool SELF>
 __device__ __forceinline__ void pair_k(const typename Traits<MODE>::Rec &r,
                                        const typename Traits<MODE>::Ist (&I)[K],
                                        const int (&iidx)[K], double eps2,
+                                       const float (&th)[K],
                                        typename Traits<MODE>::T (&t)[K][Traits<MODE>::NC],
-                                       int (&dom)[K], float (&tmx)[K]) {
+                                       int (&dom)[K], Bnd (&ba)[K], uint64_t (&nr)[K]) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
+    nr[k] = 0;
     if constexpr (MODE == kModeMixed)
-      pair_mixed<MASK, SELF>(I[k], iidx[k], r, (float)eps2, t[k], dom[k], tmx[k]);
+      nr[k] = pair_mixed<MASK, SELF>(I[k], iidx[k], r, (float)eps2, th[k], t[k], dom[k], ba[k]);
     else if constexpr (MODE == kModeFP64)
       pair_fp64<MASK>(I[k], iidx[k], r, eps2, t[k], dom[k]);
     else if constexpr (MODE == kModeMixedAcc)
-      pair_mixed_acc<MASK, SELF>(I[k], iidx[k], r, (float)eps2, t[k], dom[k], tmx[k]);
+      pair_mixed_acc<MASK, SELF>(I[k], iidx[k], r, (float)eps2, th[k], t[k], dom[k], ba[k]);
     else if constexpr (MODE == kModeFP64Acc)
       pair_fp64_acc<MASK>(I[k], iidx[k], r, eps2, t[k], dom[k]);
     else if constexpr (MODE == kModeMixed64)
-      pair_mixed64<MASK, SELF>(I[k], iidx[k], r, (float)eps2, t[k], dom[k], tmx[k]);
+      nr[k] = pair_mixed64<MASK, SELF>(I[k], iidx[k], r, (float)eps2, th[k], t[k], dom[k], ba[k]);
     else if constexpr (MODE == kModeMixed64Acc)
-      pair_mixed64_acc<MASK, SELF>(I[k], iidx[k], r, (float)eps2, t[k], dom[k], tmx[k]);
+      pair_mixed64_acc<MASK, SELF>(I[k], iidx[k], r, (float)eps2, th[k], t[k], dom[k], ba[k]);
     else
       pair_pot<MASK, SELF>(I[k], iidx[k], r, eps2, t[k], dom[k]);
+  }
+}
+
+// Near pairs wait in a per-lane queue in LDS (the j index of each, up to
+// kNearQ per i-particle and work item) and are evaluated in FP64 after the
+// item's FP32 loop (near_drain), where the FP32 temporaries are dead: the
+// rare FP64 work then costs the hot loop no registers.  A lane with more
+// near pairs than the queue holds marks its particle for the FP64
+// re-evaluation of the whole evaluation.
+constexpr int kNearQ = 16;
+
+template <int MODE, int K>
+struct NearQueue {
+  static constexpr bool on = mode_near(MODE);
+  int32_t j[on ? K : 1][on ? kNearQ : 1][on ? kWG : 1];
+};
+
+// Queue the near pairs of a group of U records (record u has index j[u]):
+// the compares' lane masks, and a single wave-uniform branch per group, so
+// the FP32 path stays free of branches.
+template <int MODE, int K, int U>
+__device__ __forceinline__ void near_push(const uint64_t (&m)[U][K], const int (&j)[U],
+                                          int (&cnt)[K], NearQueue<MODE, K> &q) {
+  if constexpr (mode_near(MODE)) {
+    uint64_t any = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < K; ++k) any |= m[u][k];
+    if (any) {
+      const uint64_t me = 1ull << __lane_id();
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          if (m[u][k] & me) {
+            if (cnt[k] < kNearQ) q.j[k][cnt[k]][threadIdx.x] = j[u];
+            ++cnt[k];
+          }
+        }
+    }
   }
 }
 
 // One LDS tile against K i-particles, folding the running tile sums into the
 // compensated (hi, lo) pairs every FOLD records.  WIDE: every lane owns its
 // i (Q = 1); otherwise lane q of a slot takes records q, q + Q, ... and
-// folds once per tile.
+// folds once per tile.  Near pairs go to (hi, lo) as they come, so the
+// sequence of operations on (hi, lo) is the same as in the broadcast kernel.
 template <int MODE, int K, bool WIDE, bool MASK, bool SELF>
 __device__ __forceinline__ void tile_loop(
     const typename Traits<MODE>::Rec *tile, int cnt, int q, int Q,
     const typename Traits<MODE>::Ist (&I)[K], const int (&iidx)[K], double eps2,
+    const float (&th)[K],
     typename Traits<MODE>::T (&t)[K][Traits<MODE>::NC],
     typename Traits<MODE>::T (&hi)[K][Traits<MODE>::NC],
     typename Traits<MODE>::T (&lo)[K][Traits<MODE>::NC], int (&dom)[K],
-    float (&tmx)[K]) {
+    Bnd (&ba)[K], int (&ncnt)[K], NearQueue<MODE, K> &nq) {
   constexpr int F = Traits<MODE>::FOLD;
   if (WIDE) {
     for (int j0 = 0; j0 < cnt; j0 += F) {
       const int j1 = (j0 + F < cnt) ? j0 + F : cnt;
-#pragma unroll 2
-      for (int jj = j0; jj < j1; ++jj)
-        pair_k<MODE, K, MASK, SELF>(tile[jj], I, iidx, eps2, t, dom, tmx);
+      int jj = j0;
+      for (; jj + 2 <= j1; jj += 2) {
+        uint64_t nr[2][K];
+        int ji[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          pair_k<MODE, K, MASK, SELF>(tile[jj + u], I, iidx, eps2, th, t, dom, ba, nr[u]);
+          ji[u] = tile[jj + u].idx;
+        }
+        near_push<MODE, K, 2>(nr, ji, ncnt, nq);
+      }
+      if (jj < j1) {
+        uint64_t nr[1][K];
+        int ji[1] = {tile[jj].idx};
+        pair_k<MODE, K, MASK, SELF>(tile[jj], I, iidx, eps2, th, t, dom, ba, nr[0]);
+        near_push<MODE, K, 1>(nr, ji, ncnt, nq);
+      }
       fold<MODE, K>(t, hi, lo);
     }
   } else {
-    for (int jj = q; jj < cnt; jj += Q)
-      pair_k<MODE, K, MASK, SELF>(tile[jj], I, iidx, eps2, t, dom, tmx);
+    for (int jj = q; jj < cnt; jj += Q) {
+      uint64_t nr[1][K];
+      int ji[1] = {tile[jj].idx};
+      pair_k<MODE, K, MASK, SELF>(tile[jj], I, iidx, eps2, th, t, dom, ba, nr[0]);
+      near_push<MODE, K, 1>(nr, ji, ncnt, nq);
+    }
     fold<MODE, K>(t, hi, lo);
   }
 }
@@ -484,7 +650,74 @@ struct ForceArgs {
   const double *rx, *rv, *rm;   // raw source (nbody_forces)
   const int32_t *pred_on;       // the evaluation's record flag (d.pred_on)
   int role;                     // which flags this launch serves (Role)
+  int near;                     // near-pair threshold source (NearSrc)
+  float near_c;                 // threshold = near_c * jerk estimate
 };
+
+// Near-pair threshold of active entry k (particle i) of a mixed evaluation
+// with jerk: near_c times the magnitude of i's stored jerk (block steps),
+// of the entry's jerk from a first pass (d.theta, which holds near_c |jerk|
+// already), or +inf (no near pairs).
+__device__ __forceinline__ float near_threshold(const ForceArgs &A, int64_t k, int i) {
+  if (A.near == kNearState) {
+    const Dev &d = A.d;
+    const double jx = d.j[i], jy = d.j[d.n + i], jz = d.j[2 * d.n + i];
+    return A.near_c * (float)sqrt(jx * jx + jy * jy + jz * jz);
+  }
+  if (A.near == kNearList) return A.d.theta[k];
+  return INFINITY;
+}
+
+// FP64 predicted state of particle p for a near pair: the caller's arrays
+// (raw source) or the state predicted to the plan's time.
+__device__ __forceinline__ void near_state(const ForceArgs &A, const ClusterPlan &cp, int p,
+                                           bool raw, double x[3], double v[3], double &m) {
+  if (raw) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      x[c] = A.rx[3 * (int64_t)p + c];
+      v[c] = A.rv[3 * (int64_t)p + c];
+    }
+    m = A.rm[p];
+  } else {
+    predict_state(A.d, p, cp.t_pred, x, v);
+    m = A.d.m[p];
+  }
+}
+
+// The FP64 terms of the queued near pairs of one work item, in queue order
+// (ascending j), into the lane's compensated sums.
+template <int MODE, int K>
+__device__ __forceinline__ void near_drain(const ForceArgs &A, const ClusterPlan &cp, bool raw,
+                                           double mref, const int (&iidx)[K], const bool (&ok)[K],
+                                           const int (&ncnt)[K], const NearQueue<MODE, K> &nq,
+                                           double eps2,
+                                           typename Traits<MODE>::T (&hi)[K][Traits<MODE>::NC],
+                                           typename Traits<MODE>::T (&lo)[K][Traits<MODE>::NC],
+                                           Bnd (&ba)[K]) {
+  if constexpr (mode_near(MODE)) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (!ok[k] || ncnt[k] == 0) continue;
+      if (ncnt[k] > kNearQ) {    // queue overflow: the whole particle in FP64
+        ba[k].a = INFINITY;
+        continue;
+      }
+      atomicAdd((unsigned long long *)&A.d.ctr[kCtrNear], (unsigned long long)ncnt[k]);
+      I64 ip;
+      double mi;
+      near_state(A, cp, iidx[k], raw, ip.x, ip.v, mi);
+      for (int u = 0; u < ncnt[k]; ++u) {
+        const int j = nq.j[k][u][threadIdx.x];
+        double xj[3], vj[3], mj;
+        near_state(A, cp, j, raw, xj, vj, mj);
+        JRec64 r;
+        make_rec(xj, vj, mj / mref, j, r, 1.0);   // in the FP32 sums' mass unit
+        near_fp64(ip, r, eps2, hi[k], lo[k]);
+      }
+    }
+  }
+}
 
 __device__ __forceinline__ void rec_to_i(const JRec64 &r, I64 &s) {
   s.x[0] = r.x; s.x[1] = r.y; s.x[2] = r.z;
@@ -495,16 +728,17 @@ __device__ __forceinline__ void rec_to_i(const JRecDS &r, IDS &s) {
   s.xh[0] = r.xh; s.xh[1] = r.yh; s.xh[2] = r.zh;
   s.xl[0] = r.xl; s.xl[1] = r.yl; s.xl[2] = r.zl;
   s.v[0] = r.vx; s.v[1] = r.vy; s.v[2] = r.vz;
+  s.vl[0] = r.vlx; s.vl[1] = r.vly; s.vl[2] = r.vlz;
 }
 
 // ------------------------------------------------------------ force kernel
 
-// Waves per SIMD to aim for: the record-only mixed kernel with one i per
-// lane fits five waves (95 VGPRs, a few spills outside the j loop) and runs
-// ~4 % faster than at four (measured at N = 2^20); the others keep the
-// compiler's choice (1 = no minimum).
+// Waves per SIMD to aim for: the compiler's choice (1 = no minimum) for
+// every shape of this kernel; a hint of five waves on the record-only
+// double-single kernel spills its i-state since the velocity carries a low
+// part.
 template <int MODE, int SRC, int K> struct ForceOcc {
-  static constexpr int waves = (MODE == kModeMixed && SRC == kSrcRec && K == 1) ? 5 : 1;
+  static constexpr int waves = 1;
 };
 
 template <int MODE, int SRC, int K>
@@ -516,7 +750,8 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
   constexpr int NC = Tr::NC;
   __shared__ Rec tile[kTJ];
   __shared__ double red[kWG / 64][K][NC];
-  __shared__ float red_t[kWG / 64][K];
+  __shared__ Bnd red_t[kWG / 64][K];
+  __shared__ NearQueue<MODE, K> nq;
   __shared__ int s_g;
   const Dev &d = A.d;
   const int tid = threadIdx.x;
@@ -571,9 +806,13 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
     const int p = tid >> Qlog;
     const int q = tid & (Q - 1);
     const double eps2 = d.eps2[cp.c];
+    // FP32 sums in units of the cluster's reference mass (mixed modes)
+    const double mref = !mode_mixed(MODE) ? 1.0
+                        : mass_ref(SRC == kSrcRaw ? A.rm[cp.jb] : d.m[cp.jb]);
 
     typename Tr::Ist I[K];
     int iidx[K], dom[K];
+    float th[K];
     bool ok[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -585,6 +824,10 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
         ok[k] = false;
         if (q == 0 && split == 0) atomicOr(d.err, (int)kErrIndex);
       }
+      // the FP32 jerk scales are in units of mref
+      th[k] = (mode_near(MODE) && ok[k])
+                  ? (float)(near_threshold(A, cp.act_off + slot, iidx[k]) / mref)
+                  : INFINITY;
       double xp[3] = {0.0, 0.0, 0.0}, vp[3] = {0.0, 0.0, 0.0};
       if (!ok[k]) {
         iidx[k] = -1;
@@ -603,10 +846,12 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
       make_i(xp, vp, I[k]);
     }
     T t[K][NC], shi[K][NC], slo[K][NC];
-    float tmx[K];
+    Bnd ba[K];
+    int ncnt[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      tmx[k] = 0.0f;
+      ba[k].a = ba[k].f1 = 0.0f;
+      ncnt[k] = 0;
 #pragma unroll
       for (int c = 0; c < NC; ++c) t[k][c] = shi[k][c] = slo[k][c] = (T)0;
     }
@@ -631,7 +876,7 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
           m = A.rm[j];
         }
         Rec r;
-        make_rec(xp, vp, m, (int32_t)j, r);
+        make_rec(xp, vp, m, (int32_t)j, r, mref);
         tile[tid] = r;
       }
       // the tile barrier also tells whether any i of this workgroup lies in
@@ -645,28 +890,29 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
       constexpr bool has_self = mode_mixed(MODE) || MODE == kModePot;
       if (Q == 1) {
         if (mask)
-          tile_loop<MODE, K, true, true, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
+          tile_loop<MODE, K, true, true, false>(tile, cnt, q, Q, I, iidx, eps2, th, t, shi, slo, dom, ba, ncnt, nq);
         else if (has_self && self_tile)
-          tile_loop<MODE, K, true, false, true>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
+          tile_loop<MODE, K, true, false, true>(tile, cnt, q, Q, I, iidx, eps2, th, t, shi, slo, dom, ba, ncnt, nq);
         else
-          tile_loop<MODE, K, true, false, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
+          tile_loop<MODE, K, true, false, false>(tile, cnt, q, Q, I, iidx, eps2, th, t, shi, slo, dom, ba, ncnt, nq);
       } else {
         if (mask)
-          tile_loop<MODE, K, false, true, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
+          tile_loop<MODE, K, false, true, false>(tile, cnt, q, Q, I, iidx, eps2, th, t, shi, slo, dom, ba, ncnt, nq);
         else if (has_self && self_tile)
-          tile_loop<MODE, K, false, false, true>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
+          tile_loop<MODE, K, false, false, true>(tile, cnt, q, Q, I, iidx, eps2, th, t, shi, slo, dom, ba, ncnt, nq);
         else
-          tile_loop<MODE, K, false, false, false>(tile, cnt, q, Q, I, iidx, eps2, t, shi, slo, dom, tmx);
+          tile_loop<MODE, K, false, false, false>(tile, cnt, q, Q, I, iidx, eps2, th, t, shi, slo, dom, ba, ncnt, nq);
       }
       __syncthreads();
     }
 
+    near_drain<MODE, K>(A, cp, SRC == kSrcRaw, mref, iidx, ok, ncnt, nq, eps2, shi, slo, ba);
     // combine hi + lo in FP64, reduce the Q lanes of a slot in a fixed tree
     double res[K][NC];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
 #pragma unroll
-      for (int c = 0; c < NC; ++c) res[k][c] = (double)shi[k][c] + (double)slo[k][c];
+      for (int c = 0; c < NC; ++c) res[k][c] = ((double)shi[k][c] + (double)slo[k][c]) * mref;
       if (ok[k] && dom[k]) atomicOr(d.err, (int)kErrDomain);
     }
     if (Q > 1) {
@@ -676,7 +922,8 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
         for (int k = 0; k < K; ++k) {
 #pragma unroll
           for (int c = 0; c < NC; ++c) res[k][c] += __shfl_xor(res[k][c], off);
-          tmx[k] = fmaxf(tmx[k], __shfl_xor(tmx[k], off));
+          ba[k].a = fmaxf(ba[k].a, __shfl_xor(ba[k].a, off));
+          ba[k].f1 += __shfl_xor(ba[k].f1, off);
         }
       }
       if (Q > 64) {
@@ -686,7 +933,7 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
           for (int k = 0; k < K; ++k) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) red[w][k][c] = res[k][c];
-            red_t[w][k] = tmx[k];
+            red_t[w][k] = ba[k];
           }
         }
         __syncthreads();
@@ -700,9 +947,12 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
               for (int u = 1; u < nw; ++u) s += red[w + u][k][c];
               res[k][c] = s;
             }
-            float tm = red_t[w][k];
-            for (int u = 1; u < nw; ++u) tm = fmaxf(tm, red_t[w + u][k]);
-            tmx[k] = tm;
+            Bnd tm = red_t[w][k];
+            for (int u = 1; u < nw; ++u) {
+              tm.a = fmaxf(tm.a, red_t[w + u][k].a);
+              tm.f1 += red_t[w + u][k].f1;
+            }
+            ba[k] = tm;
           }
         }
         __syncthreads();
@@ -719,7 +969,8 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
           if (MODE != kModePot) {
 #pragma unroll
             for (int c = NC; c < 6; ++c) row[c] = 0.0;    // no jerk in acc-only modes
-            row[6] = ok[k] ? (double)tmx[k] : 0.0;
+            row[6] = ok[k] ? (double)ba[k].a * mref : 0.0;
+            row[7] = ok[k] ? (double)ba[k].f1 * mref : 0.0;
           }
         }
       }
@@ -913,6 +1164,7 @@ __device__ void plan_single(const Dev &d, const Tuning &tu, int kind, int64_t ap
     d.T[0] = d.Tnext[0];
     if (p.items > 0) {
       d.ctr[kCtrInter] += (int64_t)p.na * (p.je - p.jb);
+      if (p.small) d.ctr[kCtrSmallInter] += (int64_t)p.na * (p.je - p.jb);
       d.ctr[kCtrSteps] += 1;
     }
     d.ctr[kCtrNotDone] = (d.Tnext[0] < d.ctr[kCtrTend]) ? 1 : 0;
@@ -1107,7 +1359,7 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
   const int C = d.C;
   const int K = tu.K;
   const int tid = threadIdx.x;
-  int64_t my_inter = 0;
+  int64_t my_inter = 0, my_small = 0;
   int my_active = 0, my_notdone = 0;
   ClusterPlan cp[QN];
 #pragma unroll
@@ -1124,6 +1376,7 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
     p = plan_cluster(d, tu, kind, api_nj, allow_small, c, offs[c], offs[c + 1] - offs[c]);
     if (p.items > 0) {
       my_inter += (int64_t)p.na * (p.je - p.jb);
+      if (p.small) my_small += (int64_t)p.na * (p.je - p.jb);
       my_active += p.na;
     }
     if (kind == kPlanStep && d.Tnext[c] < d.ctr[kCtrTend]) ++my_notdone;
@@ -1204,6 +1457,8 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
     // block totals (deterministic: integer atomics)
     if (my_inter) atomicAdd((unsigned long long *)&d.ctr[kCtrInter],
                             (unsigned long long)my_inter);
+    if (my_small) atomicAdd((unsigned long long *)&d.ctr[kCtrSmallInter],
+                            (unsigned long long)my_small);
     __shared__ int any_active, notdone;
     if (tid == 0) { any_active = 0; notdone = 0; }
     __syncthreads();
@@ -1509,7 +1764,7 @@ __global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, in
   Rec *pred = reinterpret_cast<Rec *>(d.pred);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nj;
        i += (int64_t)gridDim.x * blockDim.x) {
-    double xp[3], vp[3], m;
+    double xp[3], vp[3], m, m0;
     if (api) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -1517,15 +1772,17 @@ __global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, in
         vp[c] = raw.v ? raw.v[3 * i + c] : 0.0;
       }
       m = raw.m[i];
+      m0 = raw.m[d.C == 1 ? 0 : d.coff[d.cid[i]]];
     } else {
       const int c = d.cid[i];
       if (kind == kPlanStep && (d.Lthr[c] == kNoActive || d.plan_c[c].small))
         continue;                   // not stepping, or evaluated by the FP64 launch
       predict_state(d, i, kind == kPlanStep ? d.Tnext[c] : d.T[c], xp, vp);
       m = d.m[i];
+      m0 = d.m[d.coff[c]];
     }
     Rec r;
-    make_rec(xp, vp, m, (int32_t)i, r);
+    make_rec(xp, vp, m, (int32_t)i, r, mode_mixed(MODE) ? mass_ref(m0) : 1.0);
     pred[i] = r;
   }
 }
@@ -1548,8 +1805,9 @@ using ScalarPtr = const __attribute__((address_space(4))) T *;
 __device__ __forceinline__ JRecDS load_rec(ScalarPtr<JRecDS> p) {
   JRecDS r;
   r.xh = p->xh; r.yh = p->yh; r.zh = p->zh; r.m = p->m;
-  r.xl = p->xl; r.yl = p->yl; r.zl = p->zl; r.pad = 0.0f;
+  r.xl = p->xl; r.yl = p->yl; r.zl = p->zl; r.pad0 = 0.0f;
   r.vx = p->vx; r.vy = p->vy; r.vz = p->vz; r.idx = p->idx;
+  r.vlx = p->vlx; r.vly = p->vly; r.vlz = p->vlz; r.pad1 = 0.0f;
   return r;
 }
 
@@ -1565,29 +1823,18 @@ __device__ __forceinline__ JRec64 load_rec(ScalarPtr<JRec64> p) {
 // 64-byte load is one request to the scalar cache).
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ JRecDS rec_at(const f32x16 &a, int o) {
-  JRecDS r;
-  r.xh = a[o]; r.yh = a[o + 1]; r.zh = a[o + 2]; r.m = a[o + 3];
-  r.xl = a[o + 4]; r.yl = a[o + 5]; r.zl = a[o + 6]; r.pad = 0.0f;
-  r.vx = a[o + 8]; r.vy = a[o + 9]; r.vz = a[o + 10];
-  r.idx = __float_as_int(a[o + 11]);
-  return r;
-}
-
-// 4 x 48 bytes = three 64-byte blocks
+// one 64-byte block per record
 __device__ __forceinline__ void load4(ScalarPtr<JRecDS> p, JRecDS (&r)[4]) {
   const ScalarPtr<f32x16> b = (ScalarPtr<f32x16>)p;
-  const f32x16 b0 = b[0], b1 = b[1], b2 = b[2];
-  r[0] = rec_at(b0, 0);
-  r[1].xh = b0[12]; r[1].yh = b0[13]; r[1].zh = b0[14]; r[1].m = b0[15];
-  r[1].xl = b1[0]; r[1].yl = b1[1]; r[1].zl = b1[2]; r[1].pad = 0.0f;
-  r[1].vx = b1[4]; r[1].vy = b1[5]; r[1].vz = b1[6];
-  r[1].idx = __float_as_int(b1[7]);
-  r[2].xh = b1[8]; r[2].yh = b1[9]; r[2].zh = b1[10]; r[2].m = b1[11];
-  r[2].xl = b1[12]; r[2].yl = b1[13]; r[2].zl = b1[14]; r[2].pad = 0.0f;
-  r[2].vx = b2[0]; r[2].vy = b2[1]; r[2].vz = b2[2];
-  r[2].idx = __float_as_int(b2[3]);
-  r[3] = rec_at(b2, 4);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const f32x16 a = b[u];
+    r[u].xh = a[0]; r[u].yh = a[1]; r[u].zh = a[2]; r[u].m = a[3];
+    r[u].xl = a[4]; r[u].yl = a[5]; r[u].zl = a[6]; r[u].pad0 = 0.0f;
+    r[u].vx = a[8]; r[u].vy = a[9]; r[u].vz = a[10];
+    r[u].idx = __float_as_int(a[11]);
+    r[u].vlx = a[12]; r[u].vly = a[13]; r[u].vlz = a[14]; r[u].pad1 = 0.0f;
+  }
 }
 
 __device__ __forceinline__ void load4(ScalarPtr<JRec64> p, JRec64 (&r)[4]) {
@@ -1607,33 +1854,53 @@ __device__ __forceinline__ void load4(ScalarPtr<JRec64> p, JRec64 (&r)[4]) {
   }
 }
 
+// A chunk of records against the lane's K i-particles, four records per
+// scalar load group; near pairs go to the lane's queue.
 template <int MODE, int K, bool MASK, bool SELF>
 __device__ __forceinline__ void sb_run(
     ScalarPtr<typename Traits<MODE>::Rec> rec, int cnt,
     const typename Traits<MODE>::Ist (&I)[K], const int (&iidx)[K], double eps2,
-    typename Traits<MODE>::T (&t)[K][Traits<MODE>::NC], int (&dom)[K], float (&tmx)[K]) {
+    const float (&th)[K], typename Traits<MODE>::T (&t)[K][Traits<MODE>::NC],
+    int (&dom)[K], Bnd (&ba)[K], int (&ncnt)[K], NearQueue<MODE, K> &nq) {
   using Rec = typename Traits<MODE>::Rec;
   int jj = 0;
   for (; jj + 4 <= cnt; jj += 4) {
     Rec r[4];
+    uint64_t nr[4][K];
+    int ji[4];
     load4(rec + jj, r);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) pair_k<MODE, K, MASK, SELF>(r[u], I, iidx, eps2, t, dom, tmx);
+    for (int u = 0; u < 4; ++u) {
+      pair_k<MODE, K, MASK, SELF>(r[u], I, iidx, eps2, th, t, dom, ba, nr[u]);
+      ji[u] = r[u].idx;
+    }
+    near_push<MODE, K, 4>(nr, ji, ncnt, nq);
   }
   for (; jj < cnt; ++jj) {
     const Rec r = load_rec(rec + jj);
-    pair_k<MODE, K, MASK, SELF>(r, I, iidx, eps2, t, dom, tmx);
+    uint64_t nr[1][K];
+    int ji[1] = {r.idx};
+    pair_k<MODE, K, MASK, SELF>(r, I, iidx, eps2, th, t, dom, ba, nr[0]);
+    near_push<MODE, K, 1>(nr, ji, ncnt, nq);
   }
 }
 
+// The mixed broadcast kernel with one i per lane holds five waves per SIMD
+// (at most 96 VGPRs); the others keep the compiler's choice.
+template <int MODE, int K> struct SbOcc {
+  static constexpr int waves = (mode_near(MODE) && K == 1) ? 5 : 1;
+};
+
 template <int MODE, int K>
-__global__ __launch_bounds__(kWG) void k_force_sb(ForceArgs A) {
+__global__ __launch_bounds__(kWG)
+__attribute__((amdgpu_waves_per_eu(SbOcc<MODE, K>::waves))) void k_force_sb(ForceArgs A) {
   using Tr = Traits<MODE>;
   using T = typename Tr::T;
   using Rec = typename Tr::Rec;
   constexpr int NC = Tr::NC;
   constexpr int F = Tr::FOLD;
   __shared__ int s_g;
+  __shared__ NearQueue<MODE, K> nq;
   const Dev &d = A.d;
   if (*A.pred_on != 2) return;      // the workgroup kernel takes this evaluation
   const int tid = threadIdx.x;
@@ -1661,9 +1928,11 @@ __global__ __launch_bounds__(kWG) void k_force_sb(ForceArgs A) {
     const int64_t js = cp.jb + (int64_t)split * cp.chunk;
     const int64_t je = (js + cp.chunk < cp.je) ? js + cp.chunk : cp.je;
     const double eps2 = d.eps2[cp.c];
+    const double mref = !mode_mixed(MODE) ? 1.0 : mass_ref(raw ? A.rm[cp.jb] : d.m[cp.jb]);
 
     typename Tr::Ist I[K];
     int iidx[K], dom[K];
+    float th[K];
     bool ok[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -1675,6 +1944,10 @@ __global__ __launch_bounds__(kWG) void k_force_sb(ForceArgs A) {
         ok[k] = false;
         if (split == 0) atomicOr(d.err, (int)kErrIndex);
       }
+      // the FP32 jerk scales are in units of mref
+      th[k] = (mode_near(MODE) && ok[k])
+                  ? (float)(near_threshold(A, cp.act_off + slot, iidx[k]) / mref)
+                  : INFINITY;
       if (ok[k]) {
         rec_to_i(pred[iidx[k]], I[k]);
       } else {
@@ -1684,10 +1957,12 @@ __global__ __launch_bounds__(kWG) void k_force_sb(ForceArgs A) {
       }
     }
     T t[K][NC], shi[K][NC], slo[K][NC];
-    float tmx[K];
+    Bnd ba[K];
+    int ncnt[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      tmx[k] = 0.0f;
+      ba[k].a = ba[k].f1 = 0.0f;
+      ncnt[k] = 0;
 #pragma unroll
       for (int c = 0; c < NC; ++c) t[k][c] = shi[k][c] = slo[k][c] = (T)0;
     }
@@ -1701,13 +1976,14 @@ __global__ __launch_bounds__(kWG) void k_force_sb(ForceArgs A) {
       const bool self = __any(mine);
       const ScalarPtr<Rec> rb = spred + jb;
       if (mask)
-        sb_run<MODE, K, true, false>(rb, cnt, I, iidx, eps2, t, dom, tmx);
+        sb_run<MODE, K, true, false>(rb, cnt, I, iidx, eps2, th, t, dom, ba, ncnt, nq);
       else if (mode_mixed(MODE) && self)
-        sb_run<MODE, K, false, true>(rb, cnt, I, iidx, eps2, t, dom, tmx);
+        sb_run<MODE, K, false, true>(rb, cnt, I, iidx, eps2, th, t, dom, ba, ncnt, nq);
       else
-        sb_run<MODE, K, false, false>(rb, cnt, I, iidx, eps2, t, dom, tmx);
+        sb_run<MODE, K, false, false>(rb, cnt, I, iidx, eps2, th, t, dom, ba, ncnt, nq);
       fold<MODE, K>(t, shi, slo);
     }
+    near_drain<MODE, K>(A, cp, raw, mref, iidx, ok, ncnt, nq, eps2, shi, slo, ba);
 
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -1717,10 +1993,11 @@ __global__ __launch_bounds__(kWG) void k_force_sb(ForceArgs A) {
         double *row = d.partial + (cp.row_off + (int64_t)split * cp.na + slot) * kRowStride;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-          row[c] = ok[k] ? (double)shi[k][c] + (double)slo[k][c] : 0.0;
+          row[c] = ok[k] ? ((double)shi[k][c] + (double)slo[k][c]) * mref : 0.0;
 #pragma unroll
         for (int c = NC; c < 6; ++c) row[c] = 0.0;
-        row[6] = ok[k] ? (double)tmx[k] : 0.0;
+        row[6] = ok[k] ? (double)ba[k].a * mref : 0.0;
+        row[7] = ok[k] ? (double)ba[k].f1 * mref : 0.0;
       }
     }
   }
@@ -1840,12 +2117,13 @@ __device__ __forceinline__ void wave_neu_reduce(double (&s)[NC], double (&c)[NC]
 }
 
 // Sum the S partial rows of one slot with the 64 lanes of a wave: lane l
-// takes rows l, l + 64, ...; returns the 6 sums and the max of column 6.
+// takes rows l, l + 64, ...; returns the 6 sums, the max of column 6 and the
+// sum of column 7.
 __device__ __forceinline__ void wave_sum_rows(const Dev &d, const ClusterPlan &cp, int slot,
-                                              double *out, double &tmax) {
+                                              double *out, double &tmax, double &tf1) {
   const int lane = threadIdx.x & 63;
   double s[6], c[6];
-  double tm = 0.0;
+  double tm = 0.0, f1 = 0.0;
 #pragma unroll
   for (int q = 0; q < 6; ++q) s[q] = c[q] = 0.0;
   for (int sp = lane; sp < cp.S; sp += 64) {
@@ -1853,6 +2131,7 @@ __device__ __forceinline__ void wave_sum_rows(const Dev &d, const ClusterPlan &c
 #pragma unroll
     for (int q = 0; q < 6; ++q) neu_add(s[q], c[q], row[q]);
     tm = fmax(tm, row[6]);
+    f1 += row[7];
   }
   if (cp.S > 1) {
     // lanes >= S hold exact zeros, so the butterfly rounds that would only
@@ -1860,11 +2139,17 @@ __device__ __forceinline__ void wave_sum_rows(const Dev &d, const ClusterPlan &c
     int top = 32;
     while (top > 1 && top >= cp.S) top >>= 1;
     wave_neu_reduce<6>(s, c, top);
-    for (int off = top; off >= 1; off >>= 1) tm = fmax(tm, __shfl_xor(tm, off));
+    for (int off = top; off >= 1; off >>= 1) {
+      tm = fmax(tm, __shfl_xor(tm, off));
+      // ordered by lane, so both lanes of a butterfly hold the same sum
+      const double o = __shfl_xor(f1, off);
+      f1 = ((threadIdx.x & off) == 0) ? f1 + o : o + f1;
+    }
   }
 #pragma unroll
   for (int q = 0; q < 6; ++q) out[q] = s[q] + c[q];
   tmax = tm;
+  tf1 = f1;
 }
 
 // Cluster of active entry k: from the particle (state lists) or from the
@@ -1882,12 +2167,23 @@ __device__ __forceinline__ int entry_cluster(const Dev &d, const int32_t *list,
 }
 
 // Sum the partial rows of every active entry (split order, compensated) into
-// fsum.  With ratio > 0 (mixed path), flag the entries whose bound on the
-// largest single acceleration term, max_j m_j / s_ij, exceeds ratio times the
-// net acceleration: there the FP32 error of that term is not small against
-// the result, and the entry is re-evaluated in FP64.
+// fsum.
+//  * theta_out (first pass of a mixed evaluation with jerk): store the
+//    near-pair threshold near_c |jerk| of each entry in d.theta for the
+//    second pass; nothing is flagged.
+//  * otherwise, with ratio > 0 (mixed path), flag for the FP64 re-evaluation
+//    the entries whose bound on the largest single acceleration term,
+//    max_j m_j / s_ij, exceeds ratio times the net acceleration (there the
+//    FP32 error of that term is not small against the result), and the
+//    entries whose near-pair threshold was taken from a jerk estimate (the
+//    stored jerk, or the first pass) more than kNearStale times the jerk
+//    found (the near pairs were then chosen too coarsely), and, in the
+//    double-single form, the entries whose far-field scale (column 7)
+//    exceeds kFarRatio times the jerk (a jerk that is a small remainder of a
+//    far field many times larger).
 __global__ __launch_bounds__(kWG) void k_sum_flag(Dev d, const int32_t *list,
-                                                  int64_t na_host, float ratio) {
+                                                  int64_t na_host, float ratio, float near_c,
+                                                  int near_src, int theta_out) {
   const bool api = na_host >= 0;
   const int64_t total = api ? na_host : d.act_off[d.C];
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
@@ -1896,15 +2192,29 @@ __global__ __launch_bounds__(kWG) void k_sum_flag(Dev d, const int32_t *list,
     const ClusterPlan cp = d.plan_c[entry_cluster(d, list, k, api)];
     const int slot = (int)(k - cp.act_off);
     double f[6] = {0, 0, 0, 0, 0, 0};
-    double tmax = 0.0;
-    if (slot >= 0 && slot < cp.na) wave_sum_rows(d, cp, slot, f, tmax);
+    double tmax = 0.0, tf1 = 0.0;
+    if (slot >= 0 && slot < cp.na) wave_sum_rows(d, cp, slot, f, tmax, tf1);
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) d.fsum[6 * k + c] = f[c];
+      const double jn = sqrt(f[3] * f[3] + f[4] * f[4] + f[5] * f[5]);
       int flag = 0;
-      if (ratio > 0.0f && !cp.small) {     // small-step clusters ran in FP64
+      if (theta_out) {
+        d.theta[k] = near_c * (float)jn;
+      } else if (ratio > 0.0f && !cp.small) {     // small-step clusters ran in FP64
         const double an = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
         flag = !(tmax <= (double)ratio * an);
+        double jest = -1.0;
+        if (near_src == kNearState) {
+          const int i = list[k];
+          const double jx = d.j[i], jy = d.j[d.n + i], jz = d.j[2 * d.n + i];
+          jest = sqrt(jx * jx + jy * jy + jz * jz);
+        } else if (near_src == kNearList) {
+          jest = (double)d.theta[k] / (double)near_c;
+        }
+        if (jest >= 0.0) flag |= !(jest <= kNearStale * jn);
+        // double-single form: the far-field scale against the jerk
+        if (near_src != kNearNone && tf1 > 0.0) flag |= !(tf1 <= kFarRatio * jn);
       }
       d.rflag[k] = flag;
     }
@@ -2018,8 +2328,8 @@ __global__ __launch_bounds__(kWG) void k_ref_final(Dev d) {
       c = lo;
     }
     const ClusterPlan cp = d.plan_c[c];
-    double f[6], tmax;
-    wave_sum_rows(d, cp, r - cp.act_off, f, tmax);
+    double f[6], tmax, tf1;
+    wave_sum_rows(d, cp, r - cp.act_off, f, tmax, tf1);
     if ((threadIdx.x & 63) == 0) {
       const int64_t k = d.ref_k[r];
 #pragma unroll
@@ -2234,13 +2544,15 @@ hipError_t launch_plan(const Dev &d, const Tuning &t, int kind, int64_t api_nj,
 
 hipError_t launch_force(const Dev &d, int mode, int src, int K,
                         const RawSrc *raw, const int32_t *list, int role,
-                        int grid, hipStream_t s) {
+                        const NearSpec &nr, int grid, hipStream_t s) {
   ForceArgs A;
   A.d = d;
   A.active = list;
   A.rx = A.rv = A.rm = nullptr;
   A.pred_on = d.pred_on;
   A.role = role;
+  A.near = nr.src;
+  A.near_c = nr.c;
   if (src == kSrcRaw) {
     if (!raw) return hipErrorInvalidValue;
     A.rx = raw->x;
@@ -2371,13 +2683,15 @@ hipError_t launch_records(const Dev &d, int mode, int kind, const RawSrc *raw,
   const int sb = allow_sb ? 1 : 0, al = always ? 1 : 0;
   if (mode == kModeMixed || mode == kModeMixedAcc)     // double-single records
     hipLaunchKernelGGL(k_records<kModeMixed>, g, b, 0, s, d, kind, r, sb, al);
+  else if (mode == kModeMixed64 || mode == kModeMixed64Acc)   // FP64 records, m / m_ref
+    hipLaunchKernelGGL(k_records<kModeMixed64>, g, b, 0, s, d, kind, r, sb, al);
   else
     hipLaunchKernelGGL(k_records<kModeFP64>, g, b, 0, s, d, kind, r, sb, al);
   return hipGetLastError();
 }
 
 hipError_t launch_force_sb(const Dev &d, int mode, int K, const RawSrc *raw,
-                           const int32_t *list, int grid, hipStream_t s) {
+                           const int32_t *list, const NearSpec &nr, int grid, hipStream_t s) {
   ForceArgs A;
   A.d = d;
   A.active = list;
@@ -2386,6 +2700,8 @@ hipError_t launch_force_sb(const Dev &d, int mode, int K, const RawSrc *raw,
   A.rm = raw ? raw->m : nullptr;
   A.pred_on = d.pred_on;
   A.role = kRoleMain;
+  A.near = nr.src;
+  A.near_c = nr.c;
   const dim3 g(grid), b(kWG);
 #define NB_CASE(M, KK) \
   if (mode == M && K == KK) { hipLaunchKernelGGL((k_force_sb<M, KK>), g, b, 0, s, A); return hipGetLastError(); }
@@ -2432,13 +2748,13 @@ int force_sb_grid_size(int mode, int K, int device) {
 }
 
 hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_host,
-                               float refine_ratio, const Tuning &t1, int ref_kind,
-                               int64_t api_nj, hipStream_t s) {
+                               float refine_ratio, const NearSpec &nr, bool theta_out,
+                               const Tuning &t1, int ref_kind, int64_t api_nj, hipStream_t s) {
   const int64_t cap = na_host >= 0 ? na_host : d.cap_active;
   // one wave (64 lanes) per entry, grid-stride
   hipLaunchKernelGGL(k_sum_flag, dim3(grid_for(cap * 64, kWG, 4096)), dim3(kWG), 0, s, d,
-                     list, na_host, refine_ratio);
-  if (refine_ratio > 0.0f) {
+                     list, na_host, refine_ratio, nr.c, nr.src, theta_out ? 1 : 0);
+  if (refine_ratio > 0.0f && !theta_out) {
     hipLaunchKernelGGL(k_rcount, dim3(d.nblk), dim3(kWG), 0, s, d, na_host);
     const bool fused = d.nblk <= kFusedScan;
     if (fused) {

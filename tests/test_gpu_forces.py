@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_0909_0879_amd import binding, ics
-from tests.gpu_util import (FP64_TOL, MIXED_JERK_MAX, MIXED_TOL, check_parity, is_mixed,
+from tests.gpu_util import (FP64_TOL, MIXED_TOL, check_parity, is_mixed,
                             rel_err, require_gpu, to_np)
 
 pytestmark = pytest.mark.gpu
@@ -162,8 +162,8 @@ def test_ensemble_forces_per_cluster(prec):
 
 
 @pytest.mark.parametrize("prec,tol,jtol", [(binding.FP64, 1e-14, 1e-13),
-                                           (binding.MIXED, MIXED_TOL, MIXED_JERK_MAX),
-                                           (binding.MIXED_DS, MIXED_TOL, MIXED_JERK_MAX)])
+                                           (binding.MIXED, MIXED_TOL, MIXED_TOL),
+                                           (binding.MIXED_DS, MIXED_TOL, MIXED_TOL)])
 def test_split_and_tile_shape_invariance(prec, tol, jtol):
     # every launch shape sums the same terms in another order (and, on the
     # mixed path, may re-evaluate a slightly different set in FP64)
@@ -307,7 +307,7 @@ def test_more_clusters_than_plan_threads(prec):
         worst_a = max(worst_a, rel_err(a[sl], a_ref).max())
         worst_j = max(worst_j, rel_err(j[sl], j_ref).max())
     tol = MIXED_TOL if is_mixed(prec) else FP64_TOL
-    jtol = MIXED_JERK_MAX if is_mixed(prec) else FP64_TOL
+    jtol = MIXED_TOL if is_mixed(prec) else FP64_TOL
     assert worst_a <= tol and worst_j <= jtol, (worst_a, worst_j)
     # block steps run the plan every step
     e0 = g.energy()[:, 2]

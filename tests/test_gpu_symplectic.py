@@ -39,18 +39,31 @@ def test_accel_vs_oracle(n, prec):
                                      binding.VARIANT_S1, binding.VARIANT_S2])
 def test_accel_equals_forces_acceleration_bitwise(prec, variant):
     # the acceleration-only pair term performs the same operations as the
-    # acceleration part of the full one, on the same tiles and splits
+    # acceleration part of the full one, on the same tiles and splits.  The
+    # mixed full evaluation also takes its near pairs (chosen by their jerk
+    # scale, which the acceleration-only path cannot see) in FP64: with near
+    # pairs off the two agree bitwise, with them on both meet the oracle.
     require_gpu()
     n = 3000
     m, x, v = ics.plummer(n, 71)
     g = binding.NBody(m, x, v, eps=1e-4, precision=prec)
     g.set_tuning({"variant": variant})
     rng = np.random.default_rng(72)
+    a_ref, _ = oracle.forces(x, v, m, 1e-4)
     for idx in (None, rng.integers(0, n, 500).astype(np.int32)):
+        ref = a_ref if idx is None else a_ref[idx]
+        if is_mixed(prec):
+            a_near, _ = g.forces(x, v, m, i_active=idx)
+            g.sync()
+            assert rel_err(to_np(a_near), ref).max() <= _tol(prec)
+            g.set_tuning({"near_jerk": -1.0})
         a_full, _ = g.forces(x, v, m, i_active=idx)
         a_only = g.accel(x, m, i_active=idx)
         g.sync()
         assert np.array_equal(to_np(a_full), to_np(a_only))
+        assert rel_err(to_np(a_only), ref).max() <= _tol(prec)
+        if is_mixed(prec):
+            g.set_tuning({"near_jerk": 0.0625})
 
 
 @pytest.mark.parametrize("prec", PRECS)
