@@ -160,6 +160,25 @@ int nbody_forces(nbody_ctx *c, const int32_t *i_active, int64_t n_active,
                  const double *xj, const double *vj, const double *mj,
                  int64_t n_j, double *acc, double *jerk);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the evaluation of
+ * nbody_forces for one cluster without a context, allocating nothing.
+ * acc[k] and jerk[k] ((n_active, 3), device; jerk may be NULL) receive the
+ * pair sums over xj, vj ((n_j, 3), device) and mj (n_j, device) on particle
+ * i_active[k] (device), skipping j == i, with softening eps >= 0, in the
+ * given precision (nbody_precision, default tuning), enqueued on stream
+ * (hipStream_t; NULL = null stream) and asynchronous.  Limits: n_j in
+ * [1, 16384] and n_active <= 16384 (NBODY_EINVAL otherwise).  Its scratch
+ * is a fixed 16 MiB device array in the library, one per GPU, held until the
+ * process ends; calls that overlap on one GPU (other streams, other host
+ * threads' streams) race on it and must be ordered by the caller.  An index
+ * out of range leaves that entry's outputs zero; no error is reported for
+ * it (there is no context to hold a sticky error). */
+int nbody_forces_noalloc(int precision, double eps, const int32_t *i_active,
+                         int64_t n_active, const double *xj, const double *vj,
+                         const double *mj, int64_t n_j, double *acc, double *jerk,
+                         void *stream);
+
 /* Acceleration only (eq. (1) with Plummer softening; the force function of
  * the paper's symplectic drivers): acc[k] ((n_active, 3), device) receives
  * the sum over xj ((n_j, 3)) and mj (n_j) of the pair accelerations on

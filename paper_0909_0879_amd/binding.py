@@ -28,7 +28,7 @@ EXPORTED = [
     "nbody_get_state", "nbody_set_state", "nbody_sync", "nbody_stats", "nbody_destroy",
     "nbody_strerror", "nbody_last_error", "nbody_get_tuning", "nbody_set_tuning",
     "nbody_profile", "nbody_profile_read", "nbody_accel", "nbody_step_symplectic",
-    "nbody_step_blocks",
+    "nbody_step_blocks", "nbody_forces_noalloc",
 ]
 
 
@@ -148,6 +148,7 @@ def lib():
         L.nbody_accel.argtypes = [P, P, C.c_int64, P, P, C.c_int64, P]
         L.nbody_step_symplectic.argtypes = [P, C.c_int, C.c_double, C.c_int64, P]
         L.nbody_step_blocks.argtypes = [P, C.c_double, C.c_int64, P, P]
+        L.nbody_forces_noalloc.argtypes = [C.c_int, C.c_double, P, I64, P, P, P, I64, P, P, P]
         _lib = L
     return _lib
 
@@ -201,6 +202,20 @@ def make_params(n, n_clusters=1, cluster_offsets=None, eps=1e-3, precision=FP64,
 def workspace_bytes(n, **kw) -> int:
     p = make_params(n, **kw)
     return int(lib().nbody_workspace_bytes(C.byref(p), int(n)))
+
+
+def nbody_forces_noalloc(precision, eps, i_active, xj, vj, mj, acc, jerk, stream=None):
+    """nbody_forces_noalloc on device tensors the caller provides (i_active
+    int32 (n_active,), xj, vj (n_j, 3), mj (n_j,), acc, jerk (n_active, 3),
+    all float64 and contiguous; jerk may be None): the one-cluster
+    evaluation that allocates nothing, enqueued on `stream` (default: the
+    current stream).  Marshalling only."""
+    handle, _ = _stream_handle(stream)
+    na = int(i_active.shape[0])
+    nj = int(mj.shape[0])
+    check(lib().nbody_forces_noalloc(int(precision), float(eps), _ptr(i_active), na, _ptr(xj),
+                                     _ptr(vj), _ptr(mj), nj, _ptr(acc), _ptr(jerk), handle),
+          "nbody_forces_noalloc")
 
 
 class NBody:

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -44,7 +45,9 @@ constexpr int64_t kMaxN = (int64_t)1 << 30;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Carve the workspace.  With base == nullptr only the size is computed.
-size_t carve(int64_t n, int32_t C, char *base, Dev *d) {
+// rows_per_j: partial rows per j-particle (a context's workspace holds
+// kRowsPerJ + 1; the no-allocation evaluation's fixed buffer fewer).
+size_t carve(int64_t n, int32_t C, char *base, Dev *d, int rows_per_j = nbk::kRowsPerJ + 1) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> char * {
     char *p = base ? base + off : nullptr;
@@ -56,7 +59,7 @@ size_t carve(int64_t n, int32_t C, char *base, Dev *d) {
   t.C = C;
   t.nblk = (int32_t)((n + nbk::kScanBlock - 1) / nbk::kScanBlock);
   t.cap_active = n;
-  t.rows_cap = (int64_t)(nbk::kRowsPerJ + 1) * n + 4096;
+  t.rows_cap = (int64_t)rows_per_j * n + 4096;
   t.x = (double *)take(sizeof(double) * 3 * n);
   t.v = (double *)take(sizeof(double) * 3 * n);
   t.a = (double *)take(sizeof(double) * 3 * n);
@@ -1039,6 +1042,94 @@ int nbody_set_tuning(nbody_ctx *c, const nbody_tuning *t) {
   c->tune = n;
   drop_graph(c);
   return refresh_grids(c);
+}
+
+}  // extern "C"
+
+// ---- evaluation without any allocation ------------------------------------
+//
+// nbody_forces_noalloc: the evaluation of nbody_forces for one cluster of at
+// most kStaticMaxN particles, without a context and without any allocation.
+// Its scratch (plan, partial rows, j records, near-pair queue thresholds,
+// re-evaluation lists) lives in the file-scope device array `scratch`; the
+// host side of the evaluation is a per-device static context that only ever
+// holds plain values.  On each device, the first call takes the array's
+// device address with hipGetSymbolAddress (with that device current) and
+// keeps it; kernels receive that address, never the array's name.
+
+namespace {
+
+constexpr int64_t kStaticMaxN = 16384;        // particles (n_j and n_active)
+constexpr int kStaticRowsPerJ = 4;            // partial rows per j-particle
+constexpr size_t kStaticBytes = (size_t)16 << 20;
+constexpr int kStaticDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+struct StaticCtx {
+  bool ready = false;
+  char *base = nullptr;       // device address of `scratch` on this device
+  int grids_prec = -1;        // precision the launch grids were sized for
+  nbody_ctx ctx;              // empty vectors only: nothing is allocated
+};
+
+StaticCtx g_static[kStaticDevices];
+std::mutex g_static_mu;
+
+}  // namespace
+
+extern "C" {
+
+int nbody_forces_noalloc(int precision, double eps, const int32_t *i_active, int64_t n_active,
+                         const double *xj, const double *vj, const double *mj, int64_t n_j,
+                         double *acc, double *jerk, void *stream) {
+  if (precision != NBODY_FP64 && precision != NBODY_MIXED && precision != NBODY_MIXED_DS)
+    return fail(NBODY_EINVAL, "unknown precision");
+  if (!std::isfinite(eps) || eps < 0.0) return fail(NBODY_EINVAL, "eps must be finite and >= 0");
+  if (n_active < 0) return fail(NBODY_EINVAL, "n_active < 0");
+  if (n_j < 1 || n_j > kStaticMaxN)
+    return fail(NBODY_EINVAL, "n_j must be in [1, 16384] for nbody_forces_noalloc");
+  if (n_active > kStaticMaxN)
+    return fail(NBODY_EINVAL, "n_active must be at most 16384 for nbody_forces_noalloc");
+  if (n_active == 0) return NBODY_OK;
+  if (!i_active || !xj || !vj || !mj || !acc) return fail(NBODY_EINVAL, "NULL array argument");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(NBODY_ENODEV, "no current HIP device");
+  if (dev < 0 || dev >= kStaticDevices) return fail(NBODY_ENODEV, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  StaticCtx &g = g_static[dev];
+  if (!g.ready) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(NBODY_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    if (carve(kStaticMaxN, 1, nullptr, nullptr, kStaticRowsPerJ) > kStaticBytes)
+      return fail(NBODY_EHIP, "static scratch smaller than its largest evaluation");
+    g.base = (char *)p;
+    g.ctx.device = dev;
+    g.ready = true;
+  }
+  nbody_ctx *c = &g.ctx;
+  c->stream = (hipStream_t)stream;
+  c->n = n_j;
+  c->C = 1;
+  carve(n_j, 1, g.base, &c->d, kStaticRowsPerJ);
+  c->d.fld = nbk::Field{};
+  if (g.grids_prec != precision) {
+    c->prec = precision;
+    c->tune = default_tuning(precision);
+    int rc = refresh_grids(c);
+    if (rc) return rc;
+    g.grids_prec = precision;
+  }
+  // the cluster table of this call: [0, n_j) and eps^2 (kernels, no copies)
+  const double eps2 = eps * eps;
+  int64_t eps2_bits;
+  std::memcpy(&eps2_bits, &eps2, sizeof eps2_bits);
+  NB_HIP(nbk::launch_set_word64(c->d.coff, 0, c->stream));
+  NB_HIP(nbk::launch_set_word64(c->d.coff + 1, n_j, c->stream));
+  NB_HIP(nbk::launch_set_word64((int64_t *)c->d.eps2, eps2_bits, c->stream));
+  return api_forces(c, false, i_active, n_active, xj, vj, mj, n_j, acc, jerk);
 }
 
 }  // extern "C"

@@ -174,3 +174,17 @@ def test_tuning_struct_roundtrip():
     t = binding.Tuning.from_dict({"variant": 2, "i_slots": [1] * 25, "target_items": [64] * 25})
     assert t.as_dict()["i_slots"][3] == 1
     assert C.sizeof(binding.Tuning) == 4 * (7 + 2 * binding.TUNE_BUCKETS)
+
+
+def test_noalloc_limits_checked_on_host():
+    # sizes beyond the fixed scratch and bad arguments are rejected before
+    # any device work (no GPU needed)
+    lib = binding.lib()
+    fake = C.c_void_p(0x1000)
+    f = lib.nbody_forces_noalloc
+    assert f(binding.MIXED, 1e-3, fake, 10, fake, fake, fake, 16385, fake, fake, None) == binding.EINVAL
+    assert f(binding.MIXED, 1e-3, fake, 16385, fake, fake, fake, 100, fake, fake, None) == binding.EINVAL
+    assert f(3, 1e-3, fake, 10, fake, fake, fake, 100, fake, fake, None) == binding.EINVAL
+    assert f(binding.FP64, -1.0, fake, 10, fake, fake, fake, 100, fake, fake, None) == binding.EINVAL
+    assert f(binding.FP64, 1e-3, None, 10, fake, fake, fake, 100, fake, fake, None) == binding.EINVAL
+    assert f(binding.FP64, 1e-3, fake, 0, fake, fake, fake, 100, fake, fake, None) == binding.OK
