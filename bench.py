@@ -11,10 +11,15 @@ N^2 kernel slots.  The mixed-precision path is the headline value; the
 plain FP64 path is timed the same way beside it.
 
 Prints ONE JSON line.  Extra keys: "fp64" (the FP64 path's throughput),
-"mixed_over_fp64", "roofline" (force kernel, HIP-event timed), "counters"
-(counter-based FLOP rates and observed clock from the committed rocprofv3
-runs), "cpu_baseline" (the CPU oracle on a bounded sample of the same
-evaluation).
+"mixed_over_fp64", "roofline" (force kernel, HIP-event timed; its "traffic"
+replayed from the committed counter runs, see "traffic_source"), "counters"
+(counter-based FLOP rates and observed clock, replayed from the committed
+rocprofv3 runs, not measured by this invocation), "block_step_configs" (the
+block-step workloads over real active sets: shared-step Plummer 1024 with the
+CPU oracle beside it, Plummer 65536 FP64 to t = 1/8, Salpeter 262144 mixed
+to t = 1/16, the 256-cluster mixed ensemble to t = 1/4: interactions/s,
+block steps, energy drift and the FP64/mixed split of the interactions),
+"cpu_baseline" (the CPU oracle on a bounded sample of the same evaluation).
 """
 import argparse
 import json
@@ -27,6 +32,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "pairwise interactions/s (acc+jerk), mixed vs FP64 path at ≤1e-6 rel force err"
+# how the CPU oracle is compiled (oracle/build.py): a conservative baseline
+ORACLE_BUILD = "gcc -O2, generic x86-64 (no -march=native), OpenMP, -ffp-contract=off"
 FLOPS_PER_INTERACTION = 41          # algorithmic count, rsqrt counted as one
 FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X published dense FP32 vector peak
 FP64_VECTOR_PEAK_TFLOPS = 78.6
@@ -45,12 +52,18 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the FP64 and FP64-difference comparison runs")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-block-steps", action="store_true",
+                    help="headline only: skip the block-step configurations (shared-step "
+                         "Plummer 1024, Plummer 65536 FP64, Salpeter 262144 mixed, "
+                         "256-cluster ensemble) carried under \"block_step_configs\"")
     ap.add_argument("--workload", default="headline",
-                    choices=("headline", "sweep", "ensemble", "blocksteps", "kingsteps",
-                             "symplectic", "galactic"),
+                    choices=("headline", "sweep", "ensemble", "batching", "blocksteps",
+                             "kingsteps", "symplectic", "galactic"),
                     help="headline: the contract line (default); sweep: n_active sweep of "
                          "the King 2^20 evaluation; ensemble: 256-cluster block steps; "
-                         "blocksteps: Plummer 65536 FP64 and Salpeter 262144 mixed runs; "
+                         "batching: 32 clusters as one batched context vs 32 contexts; "
+                         "blocksteps: Plummer 1024 shared-step (with the oracle), Plummer "
+                         "65536 FP64 and Salpeter 262144 mixed runs; "
                          "kingsteps: King 2^20 mixed block steps (real active sets); "
                          "symplectic: time per leapfrog / sixth-order step vs N on the "
                          "paper's uniform-sphere initial conditions; galactic: a cluster on "
@@ -111,10 +124,14 @@ def measured_counters():
         c = json.load(f)
     if c.get("kernel_sha256") != kernel_hash():
         return None
-    return {k: {"kernel": c[k]["kernel"], "counter_tflops": c[k]["counter_tflops"],
-                "frac_peak": c[k]["frac_peak"],
-                "valu_instr_per_interaction": c[k]["valu_instr_per_interaction"],
-                "clock_ghz": c[k]["clock_ghz"]} for k in ("mixed", "mixed_ds", "fp64") if k in c}
+    out = {k: {"kernel": c[k]["kernel"], "counter_tflops": c[k]["counter_tflops"],
+               "frac_peak": c[k]["frac_peak"],
+               "valu_instr_per_interaction": c[k]["valu_instr_per_interaction"],
+               "clock_ghz": c[k]["clock_ghz"]} for k in ("mixed", "mixed_ds", "fp64") if k in c}
+    out["source"] = ("replayed from " + os.path.relpath(COUNTER_FILE, ROOT) +
+                     " (rocprofv3 SQ counter runs of this kernel source; not measured by "
+                     "this invocation)")
+    return out
 
 
 def calibrate_copy(nbytes):
@@ -198,7 +215,7 @@ def cpu_baseline(m, x, v, seconds):
             "kind": "oracle",
             "sample": f"{k} random i x {n} j of the same King W0=7 evaluation (FP64, "
                       f"compensated sums), {dt:.1f} s",
-            "single_thread": k1 * n / dt1, "cpu_model": model}
+            "single_thread": k1 * n / dt1, "cpu_model": model, "build": ORACLE_BUILD}
 
 
 def sweep(binding, torch, ics, n):
@@ -230,16 +247,33 @@ def sweep(binding, torch, ics, n):
         g.close()
 
 
+def _ang_lin_scales(m, x, v, offsets):
+    """Per cluster, sum m |r x v| and sum m |v| of the initial state: the
+    scales the angular and linear momentum drifts are divided by (both
+    totals are near zero for isotropic centre-of-mass-frame systems)."""
+    import numpy as np
+    off = offsets if offsets is not None else np.array([0, m.shape[0]])
+    lsc, psc = [], []
+    for c in range(len(off) - 1):
+        sl = slice(int(off[c]), int(off[c + 1]))
+        lsc.append(float((m[sl] * np.linalg.norm(np.cross(x[sl], v[sl]), axis=1)).sum()))
+        psc.append(float((m[sl] * np.linalg.norm(v[sl], axis=1)).sum()))
+    return np.array(lsc), np.array(psc)
+
+
 def run_blocksteps(binding, torch, label, m, x, v, t_end, precision, cluster_offsets=None,
                    eps=1e-3, level_min=3, chunks=8, dt_shared=0.0, level_max=20,
-                   oracle_time=False, field=None):
+                   oracle_time=False, field=None, emit=True):
     """Hermite-4 block steps to t_end in `chunks` equal calls (the largest
     step 2^-level_min divides each chunk); progress to stderr per chunk.
-    oracle_time: also run the CPU oracle over the same steps (small N)."""
+    oracle_time: also run the CPU oracle over the same steps (small N).
+    Returns the result dict (and prints it as one JSON line when emit)."""
+    import numpy as np
     g = binding.NBody(m, x, v, eps=eps, precision=precision, eta=0.01, eta_start=0.01,
                       dt_shared=dt_shared, level_min=level_min, level_max=level_max,
                       cluster_offsets=cluster_offsets, tuning="auto", field=field)
     e0 = g.energy()
+    st0 = g.stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     steps = inter = 0
@@ -255,15 +289,27 @@ def run_blocksteps(binding, torch, label, m, x, v, t_end, precision, cluster_off
     st = g.stats()
     de = abs(e1[:, 2] - e0[:, 2]) / abs(e0[:, 2])
     de_w = abs(e1[:, 2] - e0[:, 2]) / abs(e0[:, 1])     # against the clusters' own |W|
-    lz = abs(e1[:, 5] - e0[:, 5])
+    lsc, psc = _ang_lin_scales(m, x, v, cluster_offsets)
+    dl = np.linalg.norm(e1[:, 3:6] - e0[:, 3:6], axis=1) / lsc
+    dp = np.linalg.norm(e1[:, 6:9] - e0[:, 6:9], axis=1) / psc
     q_vir = 2 * e1[:, 0] / abs(e1[:, 1])
-    dp = (e1[:, 6:9] - e0[:, 6:9])
-    out = {"workload": label, "precision": "mixed" if precision else "fp64", "n": int(m.shape[0]),
-           "clusters": int(e0.shape[0]), "t_end": t_end, "block_steps": steps,
-           "interactions": inter, "wall_s": wall, "interactions_per_s": inter / wall,
+    fp64_routed = st["small_step_interactions"] - st0["small_step_interactions"]
+    mixed = precision != binding.FP64
+    out = {"workload": label,
+           "precision": {binding.FP64: "fp64", binding.MIXED: "mixed",
+                         binding.MIXED_DS: "mixed-ds"}[precision],
+           "n": int(m.shape[0]), "clusters": int(e0.shape[0]), "t_end": t_end,
+           "block_steps": steps, "interactions": inter, "wall_s": wall,
+           "interactions_per_s": inter / wall,
+           # mixed paths: interactions of block steps routed to the FP64
+           # kernel (small active sets) against those of the mixed kernels
+           "interactions_fp64_kernel": fp64_routed if mixed else inter,
+           "interactions_mixed_kernel": inter - fp64_routed if mixed else 0,
+           "fp64_reevaluated_particles": st["refined"] - st0["refined"],
+           "near_pairs_fp64": st["near_pairs"] - st0["near_pairs"],
            "dE_over_E_max": float(de.max()), "dE_over_E_median": float(sorted(de)[len(de) // 2]),
            "dE_over_W_max": float(de_w.max()), "external_field": field is not None,
-           "dLz_max": float(lz.max()), "dP_max": float(abs(dp).max()),
+           "dL_rel_max": float(dl.max()), "dP_rel_max": float(dp.max()),
            "virial_Q_median": float(sorted(q_vir)[len(q_vir) // 2]),
            "floor_clamps": st["floor_clamps"]}
     g.close()
@@ -276,8 +322,61 @@ def run_blocksteps(binding, torch, label, m, x, v, t_end, precision, cluster_off
         ref.run(t_end)
         out["oracle_wall_s"] = time.perf_counter() - t0
         out["oracle_cores"] = oracle.threads()
+        out["oracle_build"] = ORACLE_BUILD
         out["oracle_dE_over_E"] = abs(oracle.energy(ref.x, ref.v, m, eps)["E"] - e_ref0) / abs(e_ref0)
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
+
+
+BLOCK_STEP_CONFIGS = ("shared", "plummer65536", "salpeter262144", "ensemble")
+
+
+def block_step_configs(binding, torch, ics, with_cpu, only=BLOCK_STEP_CONFIGS, emit=False):
+    """The block-step workloads beside the full-evaluation headline, each
+    the whole Hermite-4 path (scheduler, prediction, forces, FP64
+    re-evaluation, corrector, levels) over real active sets:
+      shared:          Plummer N = 1024, FP64, shared step 1/256 to t = 1, with
+                       the CPU oracle over the same steps;
+      plummer65536:    Plummer N = 65536, FP64 block steps to t = 1/8;
+      salpeter262144:  Plummer N = 262144 with Salpeter masses, eps = 1e-4,
+                       mixed block steps to t = 1/16;
+      ensemble:        256 Plummer clusters, N_c log-uniform in [256, 16384],
+                       mixed block steps to t = 1/4 in one batched context.
+    Returns {name: result dict}."""
+    out = {}
+    if "shared" in only:
+        m, x, v = ics.plummer(1024, 1)
+        out["shared"] = run_blocksteps(
+            binding, torch, "plummer1024-shared", m, x, v, 1.0, binding.FP64, eps=1e-3,
+            level_min=8, level_max=8, dt_shared=1 / 256, chunks=4, oracle_time=with_cpu,
+            emit=emit)
+    if "plummer65536" in only:
+        m, x, v = ics.plummer(65536, 2)
+        out["plummer65536"] = run_blocksteps(
+            binding, torch, "plummer65536", m, x, v, 0.125, binding.FP64, eps=1e-3,
+            level_min=6, chunks=8, emit=emit)
+    if "salpeter262144" in only:
+        n3 = 262144
+        m, x, v = ics.plummer(n3, 3, masses=ics.salpeter_masses(n3, 3))
+        out["salpeter262144"] = run_blocksteps(
+            binding, torch, "salpeter262144", m, x, v, 0.0625, binding.MIXED, eps=1e-4,
+            level_min=7, chunks=8, emit=emit)
+    if "ensemble" in only:
+        m, x, v, off = ics.ensemble(256, 256, 16384, seed=5000)
+        out["ensemble"] = run_blocksteps(
+            binding, torch, "ensemble", m, x, v, 0.25, binding.MIXED, cluster_offsets=off,
+            eps=1e-3, level_min=5, chunks=8, emit=emit)
+    return out
+
+
+def compact_block_step(r):
+    """The few figures of one block-step run that the headline line carries."""
+    keys = ("precision", "n", "clusters", "t_end", "block_steps", "interactions",
+            "wall_s", "interactions_per_s", "interactions_fp64_kernel",
+            "interactions_mixed_kernel", "fp64_reevaluated_particles", "dE_over_E_max",
+            "dL_rel_max", "dP_rel_max", "oracle_wall_s", "oracle_cores", "oracle_dE_over_E")
+    return {k: r[k] for k in keys if k in r}
 
 
 def galactic(binding, torch, ics):
@@ -306,7 +405,9 @@ def symplectic_scaling(binding, torch, ics, with_cpu):
     runs of k1 < k2 steps cancels each call's fixed work (the extra first
     evaluation and the closing Hermite re-evaluation).  One JSON line per
     (N, precision, scheme); with_cpu adds the oracle's time per leapfrog
-    step (measured up to N = 65536 and scaled by N^2 above)."""
+    step, once with all its threads (measured up to N = 65536) and once with
+    one thread (the paper's serial version; measured up to N = 16384),
+    scaled by N^2 above those sizes and marked "extrapolated"."""
     import numpy as np
     h = 2.0 ** -10
     for n in (1024, 4096, 16384, 65536, 262144, 1048576):
@@ -333,16 +434,22 @@ def symplectic_scaling(binding, torch, ics, with_cpu):
             g.close()
         if with_cpu:
             # the oracle's own leapfrog: one step costs two evaluations here
-            # (the call starts with one); above 65536 scaled by N^2
+            # (the call starts with one); above the measured size scaled by N^2
             import oracle
-            nn = min(n, 65536)
-            t0 = time.perf_counter()
-            oracle.symplectic(x[:nn], v[:nn], m[:nn] * (n / nn), 1e-3, h, 1, oracle.LEAPFROG)
-            dt = (time.perf_counter() - t0) / 2 * (n / nn) ** 2
-            print(json.dumps({"workload": "symplectic", "scheme": "leapfrog", "n": n,
-                              "precision": "oracle-fp64", "ms_per_step": 1e3 * dt,
-                              "cores": oracle.threads(), "scaled_from_n": nn,
-                              "interactions_per_s": n * n / dt}), flush=True)
+            cores = oracle.threads()
+            for threads, n_max in ((cores, 65536), (1, 16384)):
+                nn = min(n, n_max)
+                oracle.set_threads(threads)
+                t0 = time.perf_counter()
+                oracle.symplectic(x[:nn], v[:nn], m[:nn] * (n / nn), 1e-3, h, 1,
+                                  oracle.LEAPFROG)
+                dt = (time.perf_counter() - t0) / 2 * (n / nn) ** 2
+                print(json.dumps({"workload": "symplectic", "scheme": "leapfrog", "n": n,
+                                  "precision": "oracle-fp64", "ms_per_step": 1e3 * dt,
+                                  "cores": threads, "measured_n": nn,
+                                  "extrapolated": nn != n, "build": ORACLE_BUILD,
+                                  "interactions_per_s": n * n / dt}), flush=True)
+            oracle.set_threads(cores)
 
 
 def ensemble_vs_solo(binding, torch, m, x, v, off, k):
@@ -394,9 +501,10 @@ def main():
         sweep(binding, torch, ics, a.n)
         return
     if a.workload == "ensemble":
+        block_step_configs(binding, torch, ics, with_cpu=False, only=("ensemble",), emit=True)
+        return
+    if a.workload == "batching":
         m, x, v, off = ics.ensemble(256, 256, 16384, seed=5000)
-        run_blocksteps(binding, torch, "ensemble", m, x, v, 0.25, binding.MIXED,
-                       cluster_offsets=off, eps=1e-3, level_min=5, chunks=8)
         ensemble_vs_solo(binding, torch, m, x, v, off, 32)
         return
     if a.workload == "kingsteps":
@@ -411,17 +519,8 @@ def main():
         galactic(binding, torch, ics)
         return
     if a.workload == "blocksteps":
-        m, x, v = ics.plummer(1024, 1)
-        run_blocksteps(binding, torch, "plummer1024-shared", m, x, v, 1.0, binding.FP64,
-                       eps=1e-3, level_min=8, level_max=8, dt_shared=1 / 256, chunks=4,
-                       oracle_time=not a.no_cpu)
-        m, x, v = ics.plummer(65536, 2)
-        run_blocksteps(binding, torch, "plummer65536", m, x, v, 0.125, binding.FP64, eps=1e-3,
-                       level_min=6, chunks=8)
-        n3 = 262144
-        m, x, v = ics.plummer(n3, 3, masses=ics.salpeter_masses(n3, 3))
-        run_blocksteps(binding, torch, "salpeter262144", m, x, v, 0.0625, binding.MIXED,
-                       eps=1e-4, level_min=7, chunks=8)
+        block_step_configs(binding, torch, ics, with_cpu=not a.no_cpu,
+                           only=("shared", "plummer65536", "salpeter262144"), emit=True)
         return
 
     m, x, v = ics.king(a.n, 7.0, 4)
@@ -456,6 +555,10 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": measured_traffic(),
+                     "traffic_source": ("replayed from " + os.path.relpath(TRAFFIC_FILE, ROOT)
+                                        + " (rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this "
+                                        "kernel source; not measured by this invocation)")
+                     if measured_traffic() is not None else None,
                      "kernel": "k_force_sb<mixed,K=1> (FP64 j records through the scalar cache)",
                      "kernel_ms": mixed["kernel_ms"],
                      "flops_per_launch": per_launch_flops},
@@ -478,6 +581,9 @@ def main():
             "kernel_ms": mixed_ds["kernel_ms"], "achieved_tflops": d_ach,
             "frac_fp32_peak": d_ach / FP32_VECTOR_PEAK_TFLOPS,
             "over_fp64": mixed_ds["rate"] / fp64["rate"] if fp64 else None}
+    if not a.no_block_steps:
+        runs = block_step_configs(binding, torch, ics, with_cpu=not a.no_cpu)
+        out["block_step_configs"] = {k: compact_block_step(r) for k, r in runs.items()}
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(m, x, v, a.cpu_seconds)
     print(json.dumps(out), flush=True)

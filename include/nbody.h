@@ -138,7 +138,9 @@ size_t nbody_workspace_bytes(const nbody_params *p, int64_t n);
 
 /* Create a context for n particles, copy masses m (n), positions x and
  * velocities v ((n, 3), device) into the workspace, evaluate the initial
- * acceleration and jerk of every particle and choose initial levels
+ * acceleration (Sect. 2, eq. (1), softened as in Sect. 4) and its time
+ * derivative, the jerk, of every particle, and choose initial levels of the
+ * individual block time steps (Sect. 3)
  * (dt_shared, or the largest power-of-two step <= eta_start |a| / |jerk|,
  * clamped to the level range).  All particles start at t = 0.  Syncs.
  * *out is set to NULL on failure. */
@@ -210,7 +212,9 @@ enum { NBODY_LEAPFROG = 0, NBODY_SYMPLECTIC6 = 1 };
 int nbody_step_symplectic(nbody_ctx *c, int scheme, double h, int64_t n_steps,
                           int64_t *n_interactions);
 
-/* Advance every cluster with Hermite-4 block steps to the absolute time
+/* Advance every cluster with Hermite-4 block steps (the individual,
+ * per-particle time steps of Sect. 3, over the force of Sect. 2 eq. (1)
+ * with the softening of Sect. 4) to the absolute time
  * t_end, which must be a multiple of 2^-level_min and not earlier than the
  * current time.  Each block step: per cluster, the next time
  * T_next = min_i (t_i + dt_i) and the active set {i : t_i + dt_i = T_next};
@@ -333,12 +337,22 @@ typedef struct nbody_tuning {
                                left out of the FP32 sums (the few close
                                neighbours whose terms set the FP32 error of
                                the jerk; about two pairs per particle at
-                               the default 0.125).  The estimate is i's
+                               the default 0.0625).  The estimate is i's
                                stored jerk in block steps, and a first FP64-
                                free pass over the same evaluation otherwise
                                (nbody_init, nbody_forces, the closing
                                evaluation of nbody_step_symplectic).  < 0
                                turns near pairs off. */
+  int32_t small_log2;       /* mixed paths, block steps: a cluster whose step
+                               has at most 256 active particles or at most
+                               2^small_log2 interactions (n_active x N_c) is
+                               evaluated by the FP64 kernel, which predicts
+                               its j-particles on the fly and needs neither
+                               j records nor near pairs (default 27).  In
+                               nbody_set_tuning 0 keeps the current value
+                               and -1 routes every block step through the
+                               mixed kernels; otherwise 1..62.  nbody_stats
+                               counts the interactions so routed. */
 } nbody_tuning;
 
 /* Read or replace the tuning of a context (host only, no device work). */

@@ -86,7 +86,7 @@ class Tuning(C.Structure):
         ("variant", C.c_int32), ("use_graph", C.c_int32), ("steps_per_launch", C.c_int32),
         ("min_split_j", C.c_int32), ("refine_ratio", C.c_float),
         ("i_slots", C.c_int32 * TUNE_BUCKETS), ("target_items", C.c_int32 * TUNE_BUCKETS),
-        ("acc_variant", C.c_int32), ("near_jerk", C.c_float),
+        ("acc_variant", C.c_int32), ("near_jerk", C.c_float), ("small_log2", C.c_int32),
     ]
 
     def as_dict(self):
@@ -94,7 +94,8 @@ class Tuning(C.Structure):
                 "steps_per_launch": self.steps_per_launch, "min_split_j": self.min_split_j,
                 "refine_ratio": self.refine_ratio,
                 "i_slots": list(self.i_slots), "target_items": list(self.target_items),
-                "acc_variant": self.acc_variant, "near_jerk": self.near_jerk}
+                "acc_variant": self.acc_variant, "near_jerk": self.near_jerk,
+                "small_log2": self.small_log2}
 
     @classmethod
     def from_dict(cls, d):
@@ -110,6 +111,7 @@ class Tuning(C.Structure):
             t.target_items[b] = int(v)
         t.acc_variant = int(d.get("acc_variant", 0))
         t.near_jerk = float(d.get("near_jerk", 0.0))
+        t.small_log2 = int(d.get("small_log2", 0))
         return t
 
 

@@ -40,6 +40,7 @@ constexpr float kDefaultRefineRatio = 1.0f;
 // m_j s_ij^-3/2 max_c |v_ij,c| exceeds this fraction of the i-particle's
 // jerk (a few pairs per particle)
 constexpr float kDefaultNearJerk = 0.0625f;
+constexpr int kDefaultSmallLog2 = 27;    // 2^27 interactions: n_active x N_c
 constexpr int64_t kMaxN = (int64_t)1 << 30;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -81,6 +82,7 @@ size_t carve(int64_t n, int32_t C, char *base, Dev *d, int rows_per_j = nbk::kRo
   t.plan_c = (nbk::ClusterPlan *)take(sizeof(nbk::ClusterPlan) * C);
   t.plan_lpt = (nbk::ClusterPlan *)take(sizeof(nbk::ClusterPlan) * C);
   t.item_prefix = (int32_t *)take(sizeof(int32_t) * (C + 1));
+  t.sum_prefix = (int32_t *)take(sizeof(int32_t) * (C + 1));
   t.partial = (double *)take(sizeof(double) * nbk::kRowStride * t.rows_cap);
   t.fsum = (double *)take(sizeof(double) * 6 * t.cap_active);
   t.rflag = (int32_t *)take(sizeof(int32_t) * t.cap_active);
@@ -209,6 +211,7 @@ nbody_tuning default_tuning(int precision) {
   t.min_split_j = 256;
   t.refine_ratio = is_mixed(precision) ? kDefaultRefineRatio : -1.0f;
   t.near_jerk = is_mixed(precision) ? kDefaultNearJerk : -1.0f;
+  t.small_log2 = kDefaultSmallLog2;
   const int K = (t.variant == NBODY_VARIANT_K2) ? 2 : 1;
   for (int b = 0; b < NBODY_TUNE_BUCKETS; ++b) {
     // one i-tile covers the bucket [2^b, 2^(b+1)) when possible
@@ -256,6 +259,8 @@ struct nbody_ctx {
   bool sb = false;                // broadcast kernel for large evaluations
   int Ka = 1;                     // the same two for the acceleration-only
   bool sba = false;               // evaluations (tuning acc_variant)
+  bool step_sb_only = false;      // mixed block steps: the broadcast kernel
+                                  // provably takes every main item
   int grid_state = 0, grid_raw = 0, grid_pot = 0, grid_sb = 0;
   int grid_ref_state = 0, grid_ref_raw = 0;   // FP64 K = 1 re-evaluation
   int grid_small = 0;             // FP64, the context's K: small mixed block steps
@@ -286,6 +291,7 @@ nbk::Tuning device_tuning(const nbody_ctx *c, int K) {
   }
   t.min_split_j = c->tune.min_split_j;
   t.K = K;
+  t.small_work = c->tune.small_log2 < 0 ? -1 : (int64_t)1 << c->tune.small_log2;
   return t;
 }
 
@@ -314,6 +320,15 @@ int refresh_grids(nbody_ctx *c) {
   const int va = c->tune.acc_variant ? c->tune.acc_variant : v;
   c->Ka = (va == NBODY_VARIANT_K2 || va == NBODY_VARIANT_S2) ? 2 : 1;
   c->sba = (va == NBODY_VARIANT_S1 || va == NBODY_VARIANT_S2);
+  // A mixed block step's records are always built, and the record kernel
+  // hands the main items to the broadcast kernel when every cluster with
+  // main work has kWG i-slots.  With small steps routed to FP64, a cluster
+  // with main work has more than kSmallStep active particles, so when the
+  // i-slots of those buckets are all kWG the workgroup kernel's launch would
+  // only return: it is not enqueued.
+  c->step_sb_only = c->sb && is_mixed(c->prec) && c->tune.small_log2 >= 0;
+  for (int b = 31 - __builtin_clz((unsigned)nbk::kSmallStep + 1); b < nbk::kBuckets; ++b)
+    if (c->tune.i_slots[b] != nbk::kWG) c->step_sb_only = false;
   c->grid_sb = c->sb ? nbk::force_sb_grid_size(mode_of(c), c->K, c->device) : 1;
   c->grid_acc_sb = c->sba ? nbk::force_sb_grid_size(acc_mode_of(c), c->Ka, c->device) : 1;
   c->grid_acc_state = nbk::force_grid_size(acc_mode_of(c), nbk::kSrcState, c->Ka, c->device);
@@ -346,24 +361,30 @@ int force_launch(nbody_ctx *c, int mode, int src, int K, const nbk::RawSrc *raw,
                  nbk::NearSpec nr = nbk::NearSpec{nbk::kNearNone, 0.0f}) {
   const bool prof = c->profiling && s == c->stream;
   const bool use_pred = rec_kind >= 0;
+  const bool mixed_step = rec_kind == nbk::kPlanStep && nbk::mode_mixed(mode) &&
+                          !nbk::mode_acc_only(mode);
   // clusters of a mixed block step with few active particles run in FP64
-  const bool small = rec_kind == nbk::kPlanStep && nbk::mode_mixed(mode) &&
-                     !nbk::mode_acc_only(mode);
+  // (unless that routing is off)
+  const bool small = mixed_step && c->tune.small_log2 >= 0;
   // evaluations whose records are always built (mixed block steps beyond
   // the small ones, whole-state evaluations) use the record-only kernel
-  const bool rec_only = small || rec_kind == nbk::kPlanState;
+  const bool rec_only = mixed_step || rec_kind == nbk::kPlanState;
   const bool sb = nbk::mode_acc_only(mode) ? c->sba : c->sb;
-  if (use_pred) NB_HIP(nbk::launch_records(c->d, mode, rec_kind, raw, sb, rec_only, s));
+  const bool sb_only = mixed_step && c->step_sb_only;
+  if (use_pred)
+    NB_HIP(nbk::launch_records(c->d, mode, rec_kind, raw, sb, rec_only, sb_only, s));
   if (prof && c->ev_used == kEvPairs) {
     int rc = harvest_events(c);
     if (rc) return rc;
   }
   if (prof) NB_HIP(hipEventRecord(c->ev[2 * c->ev_used], s));
-  NB_HIP(nbk::launch_force(c->d, mode, rec_only ? nbk::kSrcRec : src, K, raw, list,
-                            use_pred ? nbk::kRoleMain : nbk::kRoleAlways, nr,
-                            rec_only ? (nbk::mode_acc_only(mode) ? c->grid_acc_rec : c->grid_rec)
-                                     : grid,
-                            s));
+  if (!sb_only)
+    NB_HIP(nbk::launch_force(c->d, mode, rec_only ? nbk::kSrcRec : src, K, raw, list,
+                              use_pred ? nbk::kRoleMain : nbk::kRoleAlways, nr,
+                              rec_only ? (nbk::mode_acc_only(mode) ? c->grid_acc_rec
+                                                                   : c->grid_rec)
+                                       : grid,
+                              s));
   if (use_pred && sb)
     NB_HIP(nbk::launch_force_sb(c->d, mode, K, raw, list, nr,
                                 nbk::mode_acc_only(mode) ? c->grid_acc_sb : c->grid_sb, s));
@@ -472,8 +493,14 @@ int enqueue_block_step(nbody_ctx *c, hipStream_t s) {
   int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->d.active,
                         c->grid_state, s, nbk::kPlanStep, nr);
   if (rc) return rc;
-  if ((rc = sum_and_refine(c, c->d.active, -1, nullptr, s, false, nr))) return rc;
-  NB_HIP(nbk::launch_correct(c->d, c->eta, c->dt_shared, c->lmin, c->lmax, s));
+  // with re-evaluation: sums and flags, the FP64 pass, then the corrector;
+  // without: the corrector sums the rows itself
+  int src = nbk::kCorrectGroups;
+  if (refine_ratio(c) > 0.0f) {
+    if ((rc = sum_and_refine(c, c->d.active, -1, nullptr, s, false, nr))) return rc;
+    src = nbk::kCorrectFsum;
+  }
+  NB_HIP(nbk::launch_correct(c->d, c->eta, c->dt_shared, c->lmin, c->lmax, src, s));
   return NBODY_OK;
 }
 
@@ -1026,6 +1053,11 @@ int nbody_set_tuning(nbody_ctx *c, const nbody_tuning *t) {
   if (t->near_jerk != 0.0f) {
     if (!std::isfinite(t->near_jerk)) return fail(NBODY_EINVAL, "near_jerk must be finite");
     n.near_jerk = t->near_jerk;
+  }
+  if (t->small_log2) {
+    if (t->small_log2 != -1 && (t->small_log2 < 1 || t->small_log2 > 62))
+      return fail(NBODY_EINVAL, "small_log2 must be -1 or in [1, 62]");
+    n.small_log2 = t->small_log2;
   }
   for (int b = 0; b < NBODY_TUNE_BUCKETS; ++b) {
     if (t->i_slots[b]) {

@@ -21,8 +21,8 @@ constexpr int kBuckets = 25;        // tuning buckets floor(log2(n_active))
 constexpr int kNoActive = 99;       // threshold level meaning "nothing due"
 constexpr int kSmallStep = 256;     // mixed block steps up to this many active
                                     // particles are evaluated by the FP64 kernel,
-constexpr int64_t kSmallWork = (int64_t)1 << 27;   // and so are those of up to
-                                    // this many interactions (n_active x N_c)
+                                    // and so are those of up to Tuning::small_work
+                                    // interactions (n_active x N_c)
 constexpr int kRowsPerJ = 32;       // partial rows a cluster may take per j-particle
 constexpr int kRowStride = 8;       // doubles per partial row: a(3), jerk(3),
                                     // bound on the largest acc term, far-field
@@ -67,9 +67,10 @@ struct ClusterPlan {
   int64_t jb, je;   // j range [jb, je)
   int64_t chunk;    // j per split (multiple of kTJ)
   int64_t t_pred;   // tick every particle of the cluster is predicted to
-  int32_t small;    // small mixed block step (kSmallStep, kSmallWork):
+  int32_t small;    // small mixed block step (kSmallStep, Tuning::small_work):
                     // evaluated by the FP64 kernel, never re-evaluated
-  int32_t pad_;
+  int32_t glog;     // log2 of the lanes that sum one entry's S rows
+                    // (the power of two >= S, at most 64)
 };
 
 struct Tuning {     // device copy of the launch policy (passed by value)
@@ -77,6 +78,8 @@ struct Tuning {     // device copy of the launch policy (passed by value)
   int32_t target_items[kBuckets];
   int32_t min_split_j;
   int32_t K;        // i-particles per thread slot (1 or 2)
+  int64_t small_work;   // small mixed block steps: at most this many
+                        // interactions, or kSmallStep active; < 0: none
 };
 
 // Plan kinds (k_plan): which time the particles are predicted to, where the
@@ -129,6 +132,7 @@ struct Dev {
   ClusterPlan *plan_c;    // C, by cluster id
   ClusterPlan *plan_lpt;  // C, largest item cost first
   int32_t *item_prefix;   // C + 1 (LPT order)
+  int32_t *sum_prefix;    // C + 1 (cluster order): waves of the row sums
   double *partial;        // rows_cap * kRowStride
   // per active entry k: summed acceleration and jerk, refinement flag
   double *fsum;           // cap_active * 6
@@ -209,8 +213,9 @@ bool plan_fused(const Dev &d);
 // of the due particles into the active list (plan: see plan_fused).
 hipError_t launch_compact(const Dev &d, const Tuning &t, bool allow_small, hipStream_t s);
 // allow_small: clusters of a small block step (at most kSmallStep active
-// particles, or at most kSmallWork interactions) are planned for the
-// small-step FP64 launch (mixed contexts).
+// particles, or at most Tuning::small_work interactions) are planned for the
+// small-step FP64 launch (mixed contexts).  A re-evaluation plan also
+// writes the per-cluster offsets of the re-evaluation list (ref_off).
 hipError_t launch_plan(const Dev &d, const Tuning &t, int kind,
                        int64_t api_nj, bool allow_small, hipStream_t s);
 // Sum each active entry's partial rows into fsum.  theta_out (first pass of
@@ -223,6 +228,7 @@ hipError_t launch_plan(const Dev &d, const Tuning &t, int kind,
 hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_host,
                                float refine_ratio, const NearSpec &nr, bool theta_out,
                                const Tuning &t1, int ref_kind, int64_t api_nj, hipStream_t s);
+// Overwrite fsum of the re-evaluated entries with their FP64 sums.
 hipError_t launch_refine_finalize(const Dev &d, hipStream_t s);
 // Which work a force launch takes.  The plan splits the items in two:
 // [0, work[2]) for the main launches, [work[2], total) for the small-step
@@ -241,8 +247,10 @@ hipError_t launch_force(const Dev &d, int mode, int src, int K,
 // broadcast kernel may take it: allow_sb and kWG i-slots in every cluster
 // with work for the main kernels).
 // kind: kPlanStep (predict to T_next), kPlanState (to T), kPlanApi (raw).
+// sb_only: the caller enqueues no workgroup-kernel launch for the main items,
+// so a record flag other than 2 is reported as kErrState.
 hipError_t launch_records(const Dev &d, int mode, int kind, const RawSrc *raw,
-                          bool allow_sb, bool always, hipStream_t s);
+                          bool allow_sb, bool always, bool sb_only, hipStream_t s);
 // The broadcast force kernel (j records in scalar registers); it does the
 // evaluation only when *d.pred_on == 2 and returns at once otherwise.
 hipError_t launch_force_sb(const Dev &d, int mode, int K, const RawSrc *raw,
@@ -255,8 +263,13 @@ hipError_t launch_sym_kick_drift(const Dev &d, double ck, double cd, bool check,
                                  const Tuning &t, hipStream_t s);
 hipError_t launch_sym_kick(const Dev &d, double ck, hipStream_t s);
 hipError_t launch_sym_advance(const Dev &d, int64_t dticks, hipStream_t s);
+// Where the corrector takes each active particle's new force from:
+// kCorrectFsum: fsum (launch_sum_and_flag ran, and launch_refine_finalize
+// after a re-evaluation); kCorrectGroups: the step plan's partial rows,
+// summed in the same launch (steps without a re-evaluation pass).
+enum CorrectSrc : int { kCorrectFsum = 0, kCorrectGroups = 1 };
 hipError_t launch_correct(const Dev &d, double eta, double dt_shared,
-                          int level_min, int level_max, hipStream_t s);
+                          int level_min, int level_max, int src, hipStream_t s);
 hipError_t launch_init_levels(const Dev &d, double eta_start,
                               double dt_shared, int level_min, int level_max,
                               hipStream_t s);

@@ -1100,7 +1100,7 @@ __device__ ClusterPlan plan_cluster(const Dev &d, const Tuning &tu, int kind, in
   p.row_off = 0;
   p.chunk = kTJ;
   p.small = 0;
-  p.pad_ = 0;
+  p.glog = 0;
   if (api && d.C == 1 && api_nj > 0) {
     p.jb = 0;
     p.je = api_nj;
@@ -1141,10 +1141,20 @@ __device__ ClusterPlan plan_cluster(const Dev &d, const Tuning &tu, int kind, in
     p.chunk = chunk;
     p.tiles = (int32_t)tiles;
     p.items = (int32_t)(tiles * S);
-    p.small = (allow_small && kind == kPlanStep &&
-               (p.na <= kSmallStep || (int64_t)p.na * nc <= kSmallWork)) ? 1 : 0;
+    int g = 0;
+    while (g < 6 && (1 << g) < S) ++g;
+    p.glog = g;
+    p.small = (allow_small && kind == kPlanStep && tu.small_work >= 0 &&
+               (p.na <= kSmallStep || (int64_t)p.na * nc <= tu.small_work)) ? 1 : 0;
   }
   return p;
+}
+
+// Waves that sum a cluster's partial rows: groups of 2^glog lanes per entry,
+// 64 >> glog entries per wave.
+__device__ __forceinline__ int32_t sum_waves(const ClusterPlan &p) {
+  const int32_t per = 64 >> p.glog;
+  return p.na > 0 ? (p.na + per - 1) / per : 0;
 }
 
 // The whole plan of a one-cluster context, by one thread: what k_plan
@@ -1157,6 +1167,8 @@ __device__ void plan_single(const Dev &d, const Tuning &tu, int kind, int64_t ap
   d.plan_lpt[0] = p;
   d.item_prefix[0] = 0;
   d.item_prefix[1] = p.items;
+  d.sum_prefix[0] = 0;
+  d.sum_prefix[1] = sum_waves(p);
   d.work[0] = 0;
   d.work[1] = 0;
   d.work[2] = p.small ? 0 : p.items;
@@ -1345,6 +1357,144 @@ __device__ __forceinline__ int64_t block_exscan64(int64_t v, int64_t *sh, int64_
   return before + incl - v;
 }
 
+// Neumaier accumulation, used for the fixed-order sums over split rows.
+__device__ __forceinline__ void neu_add(double &s, double &c, double x) {
+  const double u = s + x;
+  c += (fabs(s) >= fabs(x)) ? (s - u) + x : (x - u) + s;
+  s = u;
+}
+
+// Fixed-order sum of NC compensated pairs over aligned groups of 2 top lanes
+// (xor tree from offset top down to 1); every lane of a group ends with the
+// group's total.
+template <int NC>
+__device__ __forceinline__ void group_neu_reduce(double (&s)[NC], double (&c)[NC], int top) {
+  for (int off = top; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const double os = __shfl_xor(s[q], off), oc = __shfl_xor(c[q], off);
+      // order the pair by lane so both lanes of a butterfly compute the
+      // identical value
+      const bool low = (threadIdx.x & off) == 0;
+      const double a = low ? s[q] : os, b = low ? os : s[q];
+      const double ca = low ? c[q] : oc, cb = low ? oc : c[q];
+      double t = a, tc = ca + cb;
+      neu_add(t, tc, b);
+      s[q] = t;
+      c[q] = tc;
+    }
+  }
+}
+
+// Sum the S partial rows of one slot with a group of G = 2^glog lanes (an
+// aligned part of the wave; every lane of the wave calls this, lanes of an
+// idle group with valid = false): lane l of the group takes rows l, l + G,
+// ... in split order, then the group combines them.  Returns the 6 sums,
+// the max of column 6 and the sum of column 7, complete in the group's
+// first lane (the combining rounds skip lanes that hold no row).
+__device__ __forceinline__ void group_sum_rows(const Dev &d, const ClusterPlan &cp, int slot,
+                                               int glog, bool valid, double *out, double &tmax,
+                                               double &tf1) {
+  const int G = 1 << glog;
+  const int lig = threadIdx.x & (G - 1);
+  double s[6], c[6];
+  double tm = 0.0, f1 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) s[q] = c[q] = 0.0;
+  if (valid) {
+    const double *row = d.partial + (cp.row_off + (int64_t)lig * cp.na + slot) * kRowStride;
+    const int64_t step = (int64_t)G * cp.na * kRowStride;
+    int sp = lig;
+    // four rows in flight per lane, added in split order
+    for (; sp + 3 * G < cp.S; sp += 4 * G, row += 4 * step) {
+      double r[4][8];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) r[u][q] = row[u * step + q];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) neu_add(s[q], c[q], r[u][q]);
+        tm = fmax(tm, r[u][6]);
+        f1 += r[u][7];
+      }
+    }
+    for (; sp < cp.S; sp += G, row += step) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) neu_add(s[q], c[q], row[q]);
+      tm = fmax(tm, row[6]);
+      f1 += row[7];
+    }
+  }
+  // lanes >= S hold exact zeros, so the butterfly rounds that would only
+  // add them can be skipped without changing a bit of the result
+  int top = G >> 1;
+  while (top > 1 && top >= cp.S) top >>= 1;
+  if (!valid || cp.S <= 1) top = 0;
+  // the group's shuffles stay inside the group; every lane of the wave
+  // takes part in each round from the largest top in the wave down (groups
+  // with a smaller top leave those rounds out)
+  int start = 0;
+  for (int off = 32; off >= 1; off >>= 1)
+    if (__any(top >= off)) {
+      start = off;
+      break;
+    }
+  for (int off = start; off >= 1; off >>= 1) {
+    const bool on = off <= top;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const double os = __shfl_xor(s[q], off), oc = __shfl_xor(c[q], off);
+      if (on) {
+        const bool low = (threadIdx.x & off) == 0;
+        const double a = low ? s[q] : os, b = low ? os : s[q];
+        const double ca = low ? c[q] : oc, cb = low ? oc : c[q];
+        double t = a, tc = ca + cb;
+        neu_add(t, tc, b);
+        s[q] = t;
+        c[q] = tc;
+      }
+    }
+    const double otm = __shfl_xor(tm, off), of1 = __shfl_xor(f1, off);
+    if (on) {
+      tm = fmax(tm, otm);
+      // ordered by lane, so both lanes of a butterfly hold the same sum
+      f1 = ((threadIdx.x & off) == 0) ? f1 + of1 : of1 + f1;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) out[q] = s[q] + c[q];
+  tmax = tm;
+  tf1 = f1;
+}
+
+// Cluster of active entry k: from the particle (state lists) or from the
+// group offsets (caller's lists, where i indexes the caller's arrays).
+__device__ __forceinline__ int entry_cluster(const Dev &d, const int32_t *list,
+                                            int64_t k, bool api) {
+  if (d.C == 1) return 0;
+  if (!api) return d.cid[list[k]];
+  int lo = 0, hi = d.C;   // largest c with act_off[c] <= k
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (d.act_off[mid] <= k) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// First slot of the re-evaluation list whose entry belongs to cluster c or a
+// later one (the list of cnt slots is grouped by cluster in cluster order).
+__device__ __forceinline__ int ref_list_lower(const Dev &d, int cnt, int c, bool api) {
+  int lo = 0, hi = cnt;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const int cm = api ? entry_cluster(d, nullptr, d.ref_k[mid], true) : d.cid[d.ref_i[mid]];
+    if (cm < c) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
 // Launch plan for every cluster, in one 1024-thread workgroup; thread t owns
 // clusters t, t + 1024, ..., at most QN of them (C <= 1024 QN), kept in
 // registers.
@@ -1352,7 +1502,6 @@ template <int QN>
 __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
                                                 int64_t api_nj, int allow_small) {
   const bool refine = (kind == kPlanRefine || kind == kPlanApiRefine);
-  const int32_t *offs = refine ? d.ref_off : d.act_off;
   __shared__ uint64_t key[QN * 1024];           // LPT order key per cluster
   __shared__ int32_t items_by_rank[QN * 1024];
   __shared__ int64_t sh[16];
@@ -1373,7 +1522,23 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
       p.chunk = kTJ;
       continue;
     }
-    p = plan_cluster(d, tu, kind, api_nj, allow_small, c, offs[c], offs[c + 1] - offs[c]);
+    int32_t o0, o1;
+    if (refine) {
+      // re-evaluation: the cluster's range of the (cluster-grouped) flagged
+      // list, whose length the ordered compaction left in blk_off[nblk]
+      const int cnt = d.blk_off[d.nblk];
+      o0 = ref_list_lower(d, cnt, c, kind == kPlanApiRefine);
+      o1 = (c + 1 == C) ? cnt : ref_list_lower(d, cnt, c + 1, kind == kPlanApiRefine);
+      d.ref_off[c] = o0;
+      if (c + 1 == C) {
+        d.ref_off[C] = cnt;
+        d.ctr[kCtrRefined] += cnt;
+      }
+    } else {
+      o0 = d.act_off[c];
+      o1 = d.act_off[c + 1];
+    }
+    p = plan_cluster(d, tu, kind, api_nj, allow_small, c, o0, o1 - o0);
     if (p.items > 0) {
       my_inter += (int64_t)p.na * (p.je - p.jb);
       if (p.small) my_small += (int64_t)p.na * (p.je - p.jb);
@@ -1386,8 +1551,8 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
     key[c] = ((uint64_t)p.small << 63) | ((((uint64_t)1 << 40) - 1 - cost) << 12) |
              (uint64_t)c;
   }
-  // partial-row offsets in cluster order
-  int64_t carry = 0;
+  // partial-row offsets and row-sum waves in cluster order
+  int64_t carry = 0, wcarry = 0;
 #pragma unroll
   for (int q = 0; q < QN; ++q) {
     if (1024 * q >= C) break;                       // uniform
@@ -1395,7 +1560,13 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
     const int64_t r = (int64_t)cp[q].S * cp[q].na;
     cp[q].row_off = carry + block_exscan64(r, sh, &tot);
     carry += tot;
+    const int c = tid + 1024 * q;
+    const int64_t wv = (c < C) ? sum_waves(cp[q]) : 0;
+    const int64_t wpre = wcarry + block_exscan64(wv, sh, &tot);
+    if (c < C) d.sum_prefix[c] = (int32_t)wpre;
+    wcarry += tot;
   }
+  if (tid == 0) d.sum_prefix[C] = (int32_t)wcarry;
   __syncthreads();                                  // keys complete
   // rank of each owned cluster in LPT order
   int rank[QN];
@@ -1543,74 +1714,113 @@ __device__ double ext_pot(const Field &f, const double x[3]) {
   return p;
 }
 
-// Hermite-4 correction of every active particle, new level, bookkeeping.
+// Hermite-4 correction of active particle i (cluster c) with its new force
+// f (pair sums: a, jerk), new level, bookkeeping.
 template <bool FIELD>
-__global__ __launch_bounds__(kWG) void k_correct(Dev d, double eta,
-                                                 double dt_shared, int lmin,
-                                                 int lmax) {
+__device__ __forceinline__ void correct_one(const Dev &d, int64_t i, int c, double (&f)[6],
+                                            double eta, double dt_shared, int lmin, int lmax) {
   const int64_t n = d.n;
+  const int64_t tn = d.Tnext[c];
+  const double h = (double)(tn - d.tick[i]) * kTick;
+  const double h2 = h * h, h3 = h2 * h;
+  double x1[3], v1[3], a2e[3], a3v[3], a1[3], j1[3], xp[3], vp[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+    predict(d.x[q * n + i], d.v[q * n + i], d.a[q * n + i], d.j[q * n + i], h, xp[q], vp[q]);
+  if (FIELD) {
+    // the external field at the predicted position joins the pair sums
+    double fa[3], fj[3];
+    ext_field(d.fld, xp, vp, fa, fj);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      f[q] += fa[q];
+      f[3 + q] += fj[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double a0 = d.a[q * n + i], j0 = d.j[q * n + i];
+    a1[q] = f[q];
+    j1[q] = f[3 + q];
+    const double da = a0 - a1[q];
+    const double a2 = (-6.0 * da - h * (4.0 * j0 + 2.0 * j1[q])) / h2;
+    const double a3 = (12.0 * da + 6.0 * h * (j0 + j1[q])) / h3;
+    x1[q] = xp[q] + a2 * (h2 * h2 / 24.0) + a3 * (h2 * h3 / 120.0);
+    v1[q] = vp[q] + a2 * (h3 / 6.0) + a3 * (h2 * h2 / 24.0);
+    a2e[q] = a2 + h * a3;
+    a3v[q] = a3;
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    d.x[q * n + i] = x1[q];
+    d.v[q * n + i] = v1[q];
+    d.a[q * n + i] = a1[q];
+    d.j[q * n + i] = j1[q];
+  }
+  d.tick[i] = tn;
+  if (!(finite3(x1) && finite3(v1) && finite3(a1) && finite3(j1))) {
+    atomicOr(d.err, (int)kErrNonFinite);
+    return;
+  }
+  if (dt_shared <= 0.0) {
+    const int lv = d.level[i];
+    const double dtc = aarseth_dt(a1, j1, a2e, a3v, eta);
+    int fl = 0;
+    const int nl = next_level(lv, dtc, tn, lmin, lmax, fl);
+    if (fl) atomicAdd((unsigned long long *)&d.ctr[kCtrFloor], 1ull);
+    if (nl != lv) {
+      atomicSub(&d.hist[c * kLevels + lv], 1);
+      atomicAdd(&d.hist[c * kLevels + nl], 1);
+      d.level[i] = nl;
+    }
+  }
+}
+
+// Corrector over the active list, one thread per entry, with the new force
+// from fsum (launch_sum_and_flag, and the FP64 re-evaluation's
+// launch_refine_finalize, ran before).
+template <bool FIELD>
+__global__ __launch_bounds__(kWG) void k_correct(Dev d, double eta, double dt_shared,
+                                                 int lmin, int lmax) {
   const int total = d.act_off[d.C];
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < total;
        k += gridDim.x * blockDim.x) {
     const int64_t i = d.active[k];
-    const int c = d.cid[i];
     double f[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) f[q] = d.fsum[6 * (int64_t)k + q];
-    const int64_t tn = d.Tnext[c];
-    const double h = (double)(tn - d.tick[i]) * kTick;
-    const double h2 = h * h, h3 = h2 * h;
-    double x1[3], v1[3], a2e[3], a3v[3], a1[3], j1[3], xp[3], vp[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-      predict(d.x[q * n + i], d.v[q * n + i], d.a[q * n + i], d.j[q * n + i], h, xp[q], vp[q]);
-    if (FIELD) {
-      // the external field at the predicted position joins the pair sums
-      double fa[3], fj[3];
-      ext_field(d.fld, xp, vp, fa, fj);
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        f[q] += fa[q];
-        f[3 + q] += fj[q];
+    correct_one<FIELD>(d, i, d.cid[i], f, eta, dt_shared, lmin, lmax);
+  }
+}
+
+// Row sums and corrector in one pass, for block steps without a
+// re-evaluation: each entry's rows are summed by a group of lanes sized to
+// its split count (as in k_sum_flag), and the group's first lane corrects.
+template <bool FIELD>
+__global__ __launch_bounds__(kWG) void k_sum_correct(Dev d, double eta, double dt_shared,
+                                                     int lmin, int lmax) {
+  const int lane = threadIdx.x & 63;
+  const int nw = d.sum_prefix[d.C];
+  const int wave0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  for (int w = wave0; w < nw; w += nwaves) {
+    int c = 0;
+    if (d.C > 1) {   // largest c with sum_prefix[c] <= w
+      int lo = 0, hi = d.C;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (d.sum_prefix[mid] <= w) lo = mid; else hi = mid;
       }
+      c = lo;
     }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const double a0 = d.a[q * n + i], j0 = d.j[q * n + i];
-      a1[q] = f[q];
-      j1[q] = f[3 + q];
-      const double da = a0 - a1[q];
-      const double a2 = (-6.0 * da - h * (4.0 * j0 + 2.0 * j1[q])) / h2;
-      const double a3 = (12.0 * da + 6.0 * h * (j0 + j1[q])) / h3;
-      x1[q] = xp[q] + a2 * (h2 * h2 / 24.0) + a3 * (h2 * h3 / 120.0);
-      v1[q] = vp[q] + a2 * (h3 / 6.0) + a3 * (h2 * h2 / 24.0);
-      a2e[q] = a2 + h * a3;
-      a3v[q] = a3;
-    }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      d.x[q * n + i] = x1[q];
-      d.v[q * n + i] = v1[q];
-      d.a[q * n + i] = a1[q];
-      d.j[q * n + i] = j1[q];
-    }
-    d.tick[i] = tn;
-    if (!(finite3(x1) && finite3(v1) && finite3(a1) && finite3(j1))) {
-      atomicOr(d.err, (int)kErrNonFinite);
-      continue;
-    }
-    if (dt_shared <= 0.0) {
-      const int lv = d.level[i];
-      const double dtc = aarseth_dt(a1, j1, a2e, a3v, eta);
-      int fl = 0;
-      const int nl = next_level(lv, dtc, tn, lmin, lmax, fl);
-      if (fl) atomicAdd((unsigned long long *)&d.ctr[kCtrFloor], 1ull);
-      if (nl != lv) {
-        atomicSub(&d.hist[c * kLevels + lv], 1);
-        atomicAdd(&d.hist[c * kLevels + nl], 1);
-        d.level[i] = nl;
-      }
-    }
+    const ClusterPlan cp = d.plan_c[c];
+    const int slot = ((w - d.sum_prefix[c]) << (6 - cp.glog)) + (lane >> cp.glog);
+    const bool valid = slot < cp.na;
+    double f[6], tmax, tf1;
+    group_sum_rows(d, cp, slot, cp.glog, valid, f, tmax, tf1);
+    if (!valid || (lane & ((1 << cp.glog) - 1)) != 0) continue;
+    const int64_t k = cp.act_off + slot;
+    correct_one<FIELD>(d, d.active[k], c, f, eta, dt_shared, lmin, lmax);
   }
 }
 
@@ -1742,11 +1952,15 @@ __global__ void k_api_finalize(Dev d, int64_t na, double *acc, double *jerk) {
 // record-only kernel); particles of small-step clusters are skipped.
 template <int MODE>
 __global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, int allow_sb,
-                                                 int always) {
+                                                 int always, int sb_only) {
   using Rec = typename Traits<MODE>::Rec;
   const bool api = kind == kPlanApi;
   const int64_t nj = (api && raw.n_j > 0) ? raw.n_j : d.n;
   const int64_t total = api ? raw.n_active : (int64_t)d.act_off[d.C];
+  // the flag counts of this evaluation's k_sum_flag start at zero (the
+  // compaction that used blk_cnt ran before this kernel)
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < d.nblk; b += gridDim.x * blockDim.x)
+    d.blk_cnt[b] = 0;
   // the buffer holds d.n records
   const bool on = (always || total * 16 >= nj) && nj <= d.n;
   if (blockIdx.x == 0) {
@@ -1758,7 +1972,12 @@ __global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, in
       }
     }
     elig = __syncthreads_and(elig);
-    if (threadIdx.x == 0) *d.pred_on = on ? (elig ? 2 : 1) : 0;
+    if (threadIdx.x == 0) {
+      *d.pred_on = on ? (elig ? 2 : 1) : 0;
+      // the host left out the workgroup kernel's launch, which would have
+      // taken the main items here: report instead of leaving them undone
+      if (sb_only && !(on && elig)) atomicOr(d.err, (int)kErrState);
+    }
   }
   if (!on) return;
   Rec *pred = reinterpret_cast<Rec *>(d.pred);
@@ -2086,86 +2305,6 @@ __global__ void k_sym_advance(Dev d, int64_t dticks) {
   }
 }
 
-// Neumaier accumulation and the exact combination of two (sum, correction)
-// pairs; used for the fixed-order reductions over split rows.
-__device__ __forceinline__ void neu_add(double &s, double &c, double x) {
-  const double u = s + x;
-  c += (fabs(s) >= fabs(x)) ? (s - u) + x : (x - u) + s;
-  s = u;
-}
-
-// Wave-wide sum of NC compensated pairs over the 64 lanes (xor tree, same
-// order on every run); every lane ends with the total.
-template <int NC>
-__device__ __forceinline__ void wave_neu_reduce(double (&s)[NC], double (&c)[NC],
-                                                int top = 32) {
-  for (int off = top; off >= 1; off >>= 1) {
-#pragma unroll
-    for (int q = 0; q < NC; ++q) {
-      const double os = __shfl_xor(s[q], off), oc = __shfl_xor(c[q], off);
-      // order the pair by lane so both lanes of a butterfly compute the
-      // identical value
-      const bool low = (threadIdx.x & off) == 0;
-      const double a = low ? s[q] : os, b = low ? os : s[q];
-      const double ca = low ? c[q] : oc, cb = low ? oc : c[q];
-      double t = a, tc = ca + cb;
-      neu_add(t, tc, b);
-      s[q] = t;
-      c[q] = tc;
-    }
-  }
-}
-
-// Sum the S partial rows of one slot with the 64 lanes of a wave: lane l
-// takes rows l, l + 64, ...; returns the 6 sums, the max of column 6 and the
-// sum of column 7.
-__device__ __forceinline__ void wave_sum_rows(const Dev &d, const ClusterPlan &cp, int slot,
-                                              double *out, double &tmax, double &tf1) {
-  const int lane = threadIdx.x & 63;
-  double s[6], c[6];
-  double tm = 0.0, f1 = 0.0;
-#pragma unroll
-  for (int q = 0; q < 6; ++q) s[q] = c[q] = 0.0;
-  for (int sp = lane; sp < cp.S; sp += 64) {
-    const double *row = d.partial + (cp.row_off + (int64_t)sp * cp.na + slot) * kRowStride;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) neu_add(s[q], c[q], row[q]);
-    tm = fmax(tm, row[6]);
-    f1 += row[7];
-  }
-  if (cp.S > 1) {
-    // lanes >= S hold exact zeros, so the butterfly rounds that would only
-    // add them can be skipped without changing a bit of the result
-    int top = 32;
-    while (top > 1 && top >= cp.S) top >>= 1;
-    wave_neu_reduce<6>(s, c, top);
-    for (int off = top; off >= 1; off >>= 1) {
-      tm = fmax(tm, __shfl_xor(tm, off));
-      // ordered by lane, so both lanes of a butterfly hold the same sum
-      const double o = __shfl_xor(f1, off);
-      f1 = ((threadIdx.x & off) == 0) ? f1 + o : o + f1;
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 6; ++q) out[q] = s[q] + c[q];
-  tmax = tm;
-  tf1 = f1;
-}
-
-// Cluster of active entry k: from the particle (state lists) or from the
-// group offsets (caller's lists, where i indexes the caller's arrays).
-__device__ __forceinline__ int entry_cluster(const Dev &d, const int32_t *list,
-                                            int64_t k, bool api) {
-  if (d.C == 1) return 0;
-  if (!api) return d.cid[list[k]];
-  int lo = 0, hi = d.C;   // largest c with act_off[c] <= k
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (d.act_off[mid] <= k) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
 // Sum the partial rows of every active entry (split order, compensated) into
 // fsum.
 //  * theta_out (first pass of a mixed evaluation with jerk): store the
@@ -2181,63 +2320,69 @@ __device__ __forceinline__ int entry_cluster(const Dev &d, const int32_t *list,
 //    double-single form, the entries whose far-field scale (column 7)
 //    exceeds kFarRatio times the jerk (a jerk that is a small remainder of a
 //    far field many times larger).
+// Each entry's rows are summed by a group of lanes sized to its split count
+// (the plan's glog and sum_prefix); the flag counts per kScanBlock entries
+// go to blk_cnt for the ordered compaction of the flagged entries
+// (k_rscatter).
 __global__ __launch_bounds__(kWG) void k_sum_flag(Dev d, const int32_t *list,
                                                   int64_t na_host, float ratio, float near_c,
                                                   int near_src, int theta_out) {
   const bool api = na_host >= 0;
-  const int64_t total = api ? na_host : d.act_off[d.C];
-  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t k = wave; k < total; k += nwaves) {
-    const ClusterPlan cp = d.plan_c[entry_cluster(d, list, k, api)];
-    const int slot = (int)(k - cp.act_off);
-    double f[6] = {0, 0, 0, 0, 0, 0};
-    double tmax = 0.0, tf1 = 0.0;
-    if (slot >= 0 && slot < cp.na) wave_sum_rows(d, cp, slot, f, tmax, tf1);
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) d.fsum[6 * k + c] = f[c];
-      const double jn = sqrt(f[3] * f[3] + f[4] * f[4] + f[5] * f[5]);
-      int flag = 0;
-      if (theta_out) {
-        d.theta[k] = near_c * (float)jn;
-      } else if (ratio > 0.0f && !cp.small) {     // small-step clusters ran in FP64
-        const double an = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
-        flag = !(tmax <= (double)ratio * an);
-        double jest = -1.0;
-        if (near_src == kNearState) {
-          const int i = list[k];
-          const double jx = d.j[i], jy = d.j[d.n + i], jz = d.j[2 * d.n + i];
-          jest = sqrt(jx * jx + jy * jy + jz * jz);
-        } else if (near_src == kNearList) {
-          jest = (double)d.theta[k] / (double)near_c;
-        }
-        if (jest >= 0.0) flag |= !(jest <= kNearStale * jn);
-        // double-single form: the far-field scale against the jerk
-        if (near_src != kNearNone && tf1 > 0.0) flag |= !(tf1 <= kFarRatio * jn);
+  const int lane = threadIdx.x & 63;
+  const int nw = d.sum_prefix[d.C];
+  const int wave0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  for (int w = wave0; w < nw; w += nwaves) {
+    int c = 0;
+    if (d.C > 1) {   // largest c with sum_prefix[c] <= w
+      int lo = 0, hi = d.C;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (d.sum_prefix[mid] <= w) lo = mid; else hi = mid;
       }
-      d.rflag[k] = flag;
+      c = lo;
     }
-  }
-}
-
-// Ordered compaction of the flagged entries (blocks of kScanBlock entries).
-__global__ __launch_bounds__(kWG) void k_rcount(Dev d, int64_t na_host) {
-  __shared__ int sh[4];
-  const int64_t total = na_host >= 0 ? na_host : d.act_off[d.C];
-  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
-  int cnt = 0;
+    const ClusterPlan cp = d.plan_c[c];
+    const int slot = ((w - d.sum_prefix[c]) << (6 - cp.glog)) + (lane >> cp.glog);
+    const bool valid = slot < cp.na;
+    double f[6], tmax, tf1;
+    group_sum_rows(d, cp, slot, cp.glog, valid, f, tmax, tf1);
+    if (!valid || (lane & ((1 << cp.glog) - 1)) != 0) continue;
+    // the group's first lane finishes the entry
+    const int64_t k = cp.act_off + slot;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int64_t k = base + e;
-    if (k < total && d.rflag[k]) ++cnt;
+    for (int q = 0; q < 6; ++q) d.fsum[6 * k + q] = f[q];
+    const double jn = sqrt(f[3] * f[3] + f[4] * f[4] + f[5] * f[5]);
+    int flag = 0;
+    if (theta_out) {
+      d.theta[k] = near_c * (float)jn;
+    } else if (ratio > 0.0f && !cp.small) {     // small-step clusters ran in FP64
+      const double an = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+      flag = !(tmax <= (double)ratio * an);
+      double jest = -1.0;
+      if (near_src == kNearState) {
+        const int i = list[k];
+        const double jx = d.j[i], jy = d.j[d.n + i], jz = d.j[2 * d.n + i];
+        jest = sqrt(jx * jx + jy * jy + jz * jz);
+      } else if (near_src == kNearList) {
+        jest = (double)d.theta[k] / (double)near_c;
+      }
+      if (jest >= 0.0) flag |= !(jest <= kNearStale * jn);
+      // double-single form: the far-field scale against the jerk
+      if (near_src != kNearNone && tf1 > 0.0) flag |= !(tf1 <= kFarRatio * jn);
+    }
+    d.rflag[k] = flag;
+    // per-block counts for the ordered compaction (zeroed by the record
+    // kernel before this evaluation's force launches)
+    if (flag) atomicAdd(&d.blk_cnt[k / kScanBlock], 1);
   }
-  cnt = block_sum_i(cnt, sh);
-  if (threadIdx.x == 0) d.blk_cnt[blockIdx.x] = cnt;
 }
 
-// FUSED: the block sums the counts before it itself, and the last block
-// publishes the total (and, for one cluster, the re-evaluation offsets).
+// Ordered compaction of the flagged entries (blocks of kScanBlock entries,
+// counted by k_sum_flag): the re-evaluation list ref_i / ref_k, grouped by
+// cluster because the active list is.  FUSED: the block sums the counts before it itself, and the
+// last block publishes the total (and, for one cluster, the re-evaluation
+// offsets and plan).
 template <bool FUSED>
 __global__ __launch_bounds__(kWG) void k_rscatter(Dev d, const int32_t *list,
                                                   int64_t na_host, Tuning tu, int plan_kind,
@@ -2278,41 +2423,17 @@ __global__ __launch_bounds__(kWG) void k_rscatter(Dev d, const int32_t *list,
   }
   if (FUSED && blockIdx.x == gridDim.x - 1 && threadIdx.x == kWG - 1) {
     d.blk_off[d.nblk] = pos;          // the total, as k_scan leaves it
-    if (d.C == 1) {                   // k_ref_offsets is not launched
+    if (d.C == 1) {                   // no k_plan: offsets and plan here
       d.ref_off[0] = 0;
       d.ref_off[1] = pos;
       d.ctr[kCtrRefined] += pos;
-      // nor the re-evaluation's k_plan
       if (plan_kind >= 0) plan_single(d, tu, plan_kind, api_nj, 0, pos);
     }
   }
 }
 
-// Per-cluster offsets of the (cluster-grouped) re-evaluation list.
-__global__ void k_ref_offsets(Dev d, int api) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c > d.C) return;
-  const int cnt = d.blk_off[d.nblk];
-  if (c == d.C) {
-    d.ref_off[c] = cnt;
-    d.ctr[kCtrRefined] += cnt;
-    return;
-  }
-  if (d.C == 1) {
-    d.ref_off[0] = 0;
-    return;
-  }
-  // entry r belongs to the cluster of active entry ref_k[r]
-  int lo = 0, hi = cnt;   // first r whose cluster >= c
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    const int cm = api ? entry_cluster(d, nullptr, d.ref_k[mid], true) : d.cid[d.ref_i[mid]];
-    if (cm < c) lo = mid + 1; else hi = mid;
-  }
-  d.ref_off[c] = lo;
-}
-
-// Write the FP64 re-evaluations over the mixed sums of their entries.
+// Write the FP64 re-evaluations over the mixed sums of their entries (one
+// wave per re-evaluated entry).
 __global__ __launch_bounds__(kWG) void k_ref_final(Dev d) {
   const int total = d.ref_off[d.C];
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -2329,7 +2450,7 @@ __global__ __launch_bounds__(kWG) void k_ref_final(Dev d) {
     }
     const ClusterPlan cp = d.plan_c[c];
     double f[6], tmax, tf1;
-    wave_sum_rows(d, cp, r - cp.act_off, f, tmax, tf1);
+    group_sum_rows(d, cp, r - cp.act_off, 6, true, f, tmax, tf1);
     if ((threadIdx.x & 63) == 0) {
       const int64_t k = d.ref_k[r];
 #pragma unroll
@@ -2675,18 +2796,18 @@ hipError_t launch_sym_advance(const Dev &d, int64_t dticks, hipStream_t s) {
 }
 
 hipError_t launch_records(const Dev &d, int mode, int kind, const RawSrc *raw,
-                          bool allow_sb, bool always, hipStream_t s) {
+                          bool allow_sb, bool always, bool sb_only, hipStream_t s) {
   RawSrc r{};
   if (raw) r = *raw;
   const int64_t nj = (kind == kPlanApi && r.n_j > 0) ? r.n_j : d.n;
   const dim3 g(grid_for(nj, kWG, 1024)), b(kWG);
-  const int sb = allow_sb ? 1 : 0, al = always ? 1 : 0;
+  const int sb = allow_sb ? 1 : 0, al = always ? 1 : 0, so = sb_only ? 1 : 0;
   if (mode == kModeMixed || mode == kModeMixedAcc)     // double-single records
-    hipLaunchKernelGGL(k_records<kModeMixed>, g, b, 0, s, d, kind, r, sb, al);
+    hipLaunchKernelGGL(k_records<kModeMixed>, g, b, 0, s, d, kind, r, sb, al, so);
   else if (mode == kModeMixed64 || mode == kModeMixed64Acc)   // FP64 records, m / m_ref
-    hipLaunchKernelGGL(k_records<kModeMixed64>, g, b, 0, s, d, kind, r, sb, al);
+    hipLaunchKernelGGL(k_records<kModeMixed64>, g, b, 0, s, d, kind, r, sb, al, so);
   else
-    hipLaunchKernelGGL(k_records<kModeFP64>, g, b, 0, s, d, kind, r, sb, al);
+    hipLaunchKernelGGL(k_records<kModeFP64>, g, b, 0, s, d, kind, r, sb, al, so);
   return hipGetLastError();
 }
 
@@ -2751,13 +2872,11 @@ hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_hos
                                float refine_ratio, const NearSpec &nr, bool theta_out,
                                const Tuning &t1, int ref_kind, int64_t api_nj, hipStream_t s) {
   const int64_t cap = na_host >= 0 ? na_host : d.cap_active;
-  // one wave (64 lanes) per entry, grid-stride
+  // at most one wave per entry, grid-stride
   hipLaunchKernelGGL(k_sum_flag, dim3(grid_for(cap * 64, kWG, 4096)), dim3(kWG), 0, s, d,
                      list, na_host, refine_ratio, nr.c, nr.src, theta_out ? 1 : 0);
   if (refine_ratio > 0.0f && !theta_out) {
-    hipLaunchKernelGGL(k_rcount, dim3(d.nblk), dim3(kWG), 0, s, d, na_host);
-    const bool fused = d.nblk <= kFusedScan;
-    if (fused) {
+    if (d.nblk <= kFusedScan) {
       hipLaunchKernelGGL(k_rscatter<true>, dim3(d.nblk), dim3(kWG), 0, s, d, list, na_host, t1,
                          plan_fused(d) ? ref_kind : -1, api_nj);
     } else {
@@ -2765,9 +2884,6 @@ hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_hos
       hipLaunchKernelGGL(k_rscatter<false>, dim3(d.nblk), dim3(kWG), 0, s, d, list, na_host,
                          t1, -1, api_nj);
     }
-    if (!fused || d.C > 1)
-      hipLaunchKernelGGL(k_ref_offsets, dim3((d.C + 1 + kWG - 1) / kWG), dim3(kWG), 0, s,
-                         d, na_host >= 0 ? 1 : 0);
   }
   return hipGetLastError();
 }
@@ -2779,13 +2895,22 @@ hipError_t launch_refine_finalize(const Dev &d, hipStream_t s) {
 }
 
 hipError_t launch_correct(const Dev &d, double eta, double dt_shared,
-                          int level_min, int level_max, hipStream_t s) {
-  if (d.fld.on)
+                          int level_min, int level_max, int src, hipStream_t s) {
+  if (src == kCorrectGroups) {
+    const dim3 g(grid_for((int64_t)d.cap_active * 64, kWG, 4096)), b(kWG);
+    if (d.fld.on)
+      hipLaunchKernelGGL(k_sum_correct<true>, g, b, 0, s, d, eta, dt_shared, level_min,
+                         level_max);
+    else
+      hipLaunchKernelGGL(k_sum_correct<false>, g, b, 0, s, d, eta, dt_shared, level_min,
+                         level_max);
+  } else if (d.fld.on) {
     hipLaunchKernelGGL(k_correct<true>, dim3(grid_for(d.n, kWG, 2048)), dim3(kWG), 0, s,
                        d, eta, dt_shared, level_min, level_max);
-  else
+  } else {
     hipLaunchKernelGGL(k_correct<false>, dim3(grid_for(d.n, kWG, 2048)), dim3(kWG), 0, s,
                        d, eta, dt_shared, level_min, level_max);
+  }
   return hipGetLastError();
 }
 

@@ -173,7 +173,7 @@ def test_null_context_calls():
 def test_tuning_struct_roundtrip():
     t = binding.Tuning.from_dict({"variant": 2, "i_slots": [1] * 25, "target_items": [64] * 25})
     assert t.as_dict()["i_slots"][3] == 1
-    assert C.sizeof(binding.Tuning) == 4 * (7 + 2 * binding.TUNE_BUCKETS)
+    assert C.sizeof(binding.Tuning) == 4 * (8 + 2 * binding.TUNE_BUCKETS)
 
 
 def test_noalloc_limits_checked_on_host():

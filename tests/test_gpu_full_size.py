@@ -32,7 +32,7 @@ def test_full_size_sampled(king, prec):
                       tuning="auto")
     g.set_tuning({"steps_per_launch": 1})
     rng = np.random.default_rng(44)
-    idx = np.sort(rng.choice(N, 2048, replace=False)).astype(np.int64)
+    idx = np.sort(rng.choice(N, 4096, replace=False)).astype(np.int64)
     # the initial full evaluation (state source, all active)
     s0 = {k: to_np(t) for k, t in g.get_state().items()}
     a_ref, j_ref = oracle.forces(x, v, m, EPS, idx=idx)

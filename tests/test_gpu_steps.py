@@ -96,20 +96,32 @@ def test_graph_replay_equals_eager_bitwise(prec):
         assert np.array_equal(sa[k], sb[k]), k
 
 
-@pytest.mark.parametrize("prec", [binding.FP64, binding.MIXED, binding.MIXED_DS])
-def test_ensemble_equals_solo_bitwise(prec):
+@pytest.mark.parametrize("prec,small_log2", [(binding.FP64, 0), (binding.MIXED, 0),
+                                              (binding.MIXED_DS, 0), (binding.MIXED, -1),
+                                              (binding.MIXED_DS, -1)])
+def test_ensemble_equals_solo_bitwise(prec, small_log2):
+    # small_log2 = -1: no block step is routed to the FP64 kernel, so every
+    # step of every cluster runs the mixed kernels (records, near pairs,
+    # FP64 re-evaluation) inside the batched launches
     require_gpu()
     sizes = [300, 1024, 64, 777]
     m, x, v, off = ics.ensemble(4, sizes=sizes, seed=5000)
     eps = [1e-3, 2e-3, 1e-3, 4e-3]
     kw = dict(precision=prec, eta=0.02, level_min=3, level_max=20)
-    e = binding.NBody(m, x, v, eps=eps, cluster_offsets=off, **kw)
+    tune = {"small_log2": small_log2}
+    e = binding.NBody(m, x, v, eps=eps, cluster_offsets=off, tuning=tune, **kw)
     e.step(0.125)
+    st = e.stats()
+    if small_log2 < 0:
+        assert st["small_step_interactions"] == 0, st
+    elif prec != binding.FP64:
+        # clusters this small take every block step in FP64 by default
+        assert st["small_step_interactions"] == st["interactions"], st
     se = _state_np(e)
     energies = e.energy()
     for c in range(4):
         sl = slice(off[c], off[c + 1])
-        s = binding.NBody(m[sl], x[sl], v[sl], eps=eps[c], **kw)
+        s = binding.NBody(m[sl], x[sl], v[sl], eps=eps[c], tuning=tune, **kw)
         s.step(0.125)
         ss = _state_np(s)
         for k in ("x", "v", "a", "j", "tick", "level"):

@@ -353,3 +353,22 @@ def test_shared_step_momentum_exact():
     p0 = s.energy()["P"]
     s.run(2.0 ** -4)
     assert np.linalg.norm(s.energy()["P"] - p0) < 1e-15
+
+
+def test_block_step_energy_drift_shrinks_with_eta():
+    # the Hermite scheme is fourth order, so halving the accuracy parameter
+    # eta (step ~ eta) should cut the energy error by about 2^4; close
+    # encounters make single runs noisy, so the sum over four Plummer
+    # spheres is compared, with a factor 4 of margin
+    drift = {}
+    for eta in (0.02, 0.01):
+        tot = 0.0
+        for seed in (21, 22, 23, 24):
+            m, x, v = ics.plummer(2048, seed)
+            s = oracle.System(m, x, v, 1e-3, eta=eta, eta_start=eta, level_min=4,
+                              level_max=20)
+            e0 = s.energy()["E"]
+            s.run(1 / 16)
+            tot += abs(s.energy()["E"] - e0) / abs(e0)
+        drift[eta] = tot
+    assert drift[0.01] * 4 < drift[0.02], drift
