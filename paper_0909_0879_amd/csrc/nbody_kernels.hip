@@ -741,6 +741,34 @@ template <int MODE, int SRC, int K> struct ForceOcc {
   static constexpr int waves = 1;
 };
 
+// Per-cluster prefix arrays (work items, row-sum waves) in LDS: with several
+// clusters every work item or wave finds its cluster by a binary search,
+// which in LDS costs a few LDS reads instead of a chain of dependent global
+// loads.  The launch sizes the dynamic LDS to (C + 1) ints for 1 < C <= 1024
+// (4 KB at most beside the kernels' own LDS); more clusters search in
+// global memory.
+__host__ __device__ __forceinline__ bool prefix_in_lds(int C) { return C > 1 && C <= 1024; }
+
+__device__ __forceinline__ void prefix_to_lds(const int32_t *src, int C, int32_t *dst) {
+  for (int c = threadIdx.x; c <= C; c += blockDim.x) dst[c] = src[c];
+  __syncthreads();
+}
+
+// Largest c with pre[c] <= g (pre non-decreasing, pre[0] = 0 <= g).
+__device__ __forceinline__ int prefix_find(const int32_t *pre, int C, int g) {
+  int lo = 0, hi = C;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Dynamic LDS bytes of the kernels that use prefix_to_lds.
+inline size_t prefix_lds_bytes(int C) {
+  return prefix_in_lds(C) ? sizeof(int32_t) * (size_t)(C + 1) : 0;
+}
+
 template <int MODE, int SRC, int K>
 __global__ __launch_bounds__(kWG)
 __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force(ForceArgs A) {
@@ -780,6 +808,10 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
   // a launch with no items leaves before touching the shared counter (the
   // whole grid queueing on one atomic costs more than the launch itself)
   if (n_items <= item_base) return;
+  extern __shared__ int32_t s_ipre[];   // item_prefix when prefix_in_lds(C)
+  const bool lds_pre = prefix_in_lds(d.C);
+  if (lds_pre) prefix_to_lds(d.item_prefix, d.C, s_ipre);
+  const int32_t *ipre = lds_pre ? s_ipre : d.item_prefix;
   const bool use_pred = REC || pred_flag == 1;
   const Rec *pred = reinterpret_cast<const Rec *>(d.pred);
   for (;;) {
@@ -788,15 +820,12 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
     const int g = s_g;
     __syncthreads();
     if (g >= n_items) break;
-    int lo = 0, hi = d.C;   // item_prefix[lo] <= g < item_prefix[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (d.item_prefix[mid] <= g) lo = mid; else hi = mid;
-    }
+    // item_prefix[lo] <= g < item_prefix[lo + 1]
+    const int lo = (d.C > 1) ? prefix_find(ipre, d.C, g) : 0;
     const ClusterPlan cp = d.plan_lpt[lo];
     // split-major: the workgroups that run at the same time work on the
     // same j chunk, so each XCD's L2 serves the chunk to all of them
-    const int t_item = g - d.item_prefix[lo];
+    const int t_item = g - ((d.C > 1) ? ipre[lo] : 0);
     const int split = t_item / cp.tiles;
     const int tile_i = t_item - split * cp.tiles;
     const int64_t js = cp.jb + (int64_t)split * cp.chunk;
@@ -1803,18 +1832,18 @@ __global__ __launch_bounds__(kWG) void k_sum_correct(Dev d, double eta, double d
   const int nw = d.sum_prefix[d.C];
   const int wave0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  extern __shared__ int32_t s_spre[];   // sum_prefix when prefix_in_lds(C)
+  const bool lds_pre = prefix_in_lds(d.C);
+  if (lds_pre) {
+    if (wave0 - (int)(threadIdx.x >> 6) >= nw) return;   // no wave of this block has work
+    prefix_to_lds(d.sum_prefix, d.C, s_spre);
+  }
+  const int32_t *spre = lds_pre ? s_spre : d.sum_prefix;
   for (int w = wave0; w < nw; w += nwaves) {
-    int c = 0;
-    if (d.C > 1) {   // largest c with sum_prefix[c] <= w
-      int lo = 0, hi = d.C;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (d.sum_prefix[mid] <= w) lo = mid; else hi = mid;
-      }
-      c = lo;
-    }
+    // largest c with sum_prefix[c] <= w
+    const int c = (d.C > 1) ? prefix_find(spre, d.C, w) : 0;
     const ClusterPlan cp = d.plan_c[c];
-    const int slot = ((w - d.sum_prefix[c]) << (6 - cp.glog)) + (lane >> cp.glog);
+    const int slot = ((w - ((d.C > 1) ? spre[c] : 0)) << (6 - cp.glog)) + (lane >> cp.glog);
     const bool valid = slot < cp.na;
     double f[6], tmax, tf1;
     group_sum_rows(d, cp, slot, cp.glog, valid, f, tmax, tf1);
@@ -2128,20 +2157,21 @@ __attribute__((amdgpu_waves_per_eu(SbOcc<MODE, K>::waves))) void k_force_sb(Forc
   const Rec *pred = reinterpret_cast<const Rec *>(d.pred);
   const ScalarPtr<Rec> spred = (ScalarPtr<Rec>)d.pred;
   const bool raw = A.rx != nullptr;
+  extern __shared__ int32_t s_ipre[];   // item_prefix when prefix_in_lds(C)
+  const bool lds_pre = prefix_in_lds(d.C);
+  if (lds_pre) prefix_to_lds(d.item_prefix, d.C, s_ipre);
+  const int32_t *ipre = lds_pre ? s_ipre : d.item_prefix;
   for (;;) {
     if (tid == 0) s_g = atomicAdd(d.work, 1);
     __syncthreads();
     const int g = __builtin_amdgcn_readfirstlane(s_g);
     __syncthreads();
     if (g >= n_items) break;
-    int lo = 0, hi = d.C;   // item_prefix[lo] <= g < item_prefix[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (d.item_prefix[mid] <= g) lo = mid; else hi = mid;
-    }
+    // item_prefix[lo] <= g < item_prefix[lo + 1] (uniform: scalar from here)
+    const int lo = (d.C > 1) ? __builtin_amdgcn_readfirstlane(prefix_find(ipre, d.C, g)) : 0;
     const ClusterPlan cp = d.plan_lpt[lo];
     // split-major, as in k_force
-    const int t_item = g - d.item_prefix[lo];
+    const int t_item = g - ((d.C > 1) ? __builtin_amdgcn_readfirstlane(ipre[lo]) : 0);
     const int split = t_item / cp.tiles;
     const int tile_i = t_item - split * cp.tiles;
     const int64_t js = cp.jb + (int64_t)split * cp.chunk;
@@ -2332,18 +2362,18 @@ __global__ __launch_bounds__(kWG) void k_sum_flag(Dev d, const int32_t *list,
   const int nw = d.sum_prefix[d.C];
   const int wave0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  extern __shared__ int32_t s_spre[];   // sum_prefix when prefix_in_lds(C)
+  const bool lds_pre = prefix_in_lds(d.C);
+  if (lds_pre) {
+    if (wave0 - (int)(threadIdx.x >> 6) >= nw) return;   // no wave of this block has work
+    prefix_to_lds(d.sum_prefix, d.C, s_spre);
+  }
+  const int32_t *spre = lds_pre ? s_spre : d.sum_prefix;
   for (int w = wave0; w < nw; w += nwaves) {
-    int c = 0;
-    if (d.C > 1) {   // largest c with sum_prefix[c] <= w
-      int lo = 0, hi = d.C;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (d.sum_prefix[mid] <= w) lo = mid; else hi = mid;
-      }
-      c = lo;
-    }
+    // largest c with sum_prefix[c] <= w
+    const int c = (d.C > 1) ? prefix_find(spre, d.C, w) : 0;
     const ClusterPlan cp = d.plan_c[c];
-    const int slot = ((w - d.sum_prefix[c]) << (6 - cp.glog)) + (lane >> cp.glog);
+    const int slot = ((w - ((d.C > 1) ? spre[c] : 0)) << (6 - cp.glog)) + (lane >> cp.glog);
     const bool valid = slot < cp.na;
     double f[6], tmax, tf1;
     group_sum_rows(d, cp, slot, cp.glog, valid, f, tmax, tf1);
@@ -2597,7 +2627,8 @@ inline int grid_for(int64_t n, int block = kWG, int cap = 4096) {
 
 template <int MODE, int SRC, int K>
 hipError_t launch_force_t(const ForceArgs &A, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_force<MODE, SRC, K>), dim3(grid), dim3(kWG), 0, s, A);
+  hipLaunchKernelGGL((k_force<MODE, SRC, K>), dim3(grid), dim3(kWG), prefix_lds_bytes(A.d.C),
+                     s, A);
   return hipGetLastError();
 }
 
@@ -2825,7 +2856,7 @@ hipError_t launch_force_sb(const Dev &d, int mode, int K, const RawSrc *raw,
   A.near_c = nr.c;
   const dim3 g(grid), b(kWG);
 #define NB_CASE(M, KK) \
-  if (mode == M && K == KK) { hipLaunchKernelGGL((k_force_sb<M, KK>), g, b, 0, s, A); return hipGetLastError(); }
+  if (mode == M && K == KK) { hipLaunchKernelGGL((k_force_sb<M, KK>), g, b, prefix_lds_bytes(d.C), s, A); return hipGetLastError(); }
   NB_CASE(kModeFP64, 1)
   NB_CASE(kModeFP64, 2)
   NB_CASE(kModeMixed, 1)
@@ -2873,8 +2904,9 @@ hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_hos
                                const Tuning &t1, int ref_kind, int64_t api_nj, hipStream_t s) {
   const int64_t cap = na_host >= 0 ? na_host : d.cap_active;
   // at most one wave per entry, grid-stride
-  hipLaunchKernelGGL(k_sum_flag, dim3(grid_for(cap * 64, kWG, 4096)), dim3(kWG), 0, s, d,
-                     list, na_host, refine_ratio, nr.c, nr.src, theta_out ? 1 : 0);
+  hipLaunchKernelGGL(k_sum_flag, dim3(grid_for(cap * 64, kWG, 4096)), dim3(kWG),
+                     prefix_lds_bytes(d.C), s, d, list, na_host, refine_ratio, nr.c, nr.src,
+                     theta_out ? 1 : 0);
   if (refine_ratio > 0.0f && !theta_out) {
     if (d.nblk <= kFusedScan) {
       hipLaunchKernelGGL(k_rscatter<true>, dim3(d.nblk), dim3(kWG), 0, s, d, list, na_host, t1,
@@ -2898,11 +2930,12 @@ hipError_t launch_correct(const Dev &d, double eta, double dt_shared,
                           int level_min, int level_max, int src, hipStream_t s) {
   if (src == kCorrectGroups) {
     const dim3 g(grid_for((int64_t)d.cap_active * 64, kWG, 4096)), b(kWG);
+    const size_t lds = prefix_lds_bytes(d.C);
     if (d.fld.on)
-      hipLaunchKernelGGL(k_sum_correct<true>, g, b, 0, s, d, eta, dt_shared, level_min,
+      hipLaunchKernelGGL(k_sum_correct<true>, g, b, lds, s, d, eta, dt_shared, level_min,
                          level_max);
     else
-      hipLaunchKernelGGL(k_sum_correct<false>, g, b, 0, s, d, eta, dt_shared, level_min,
+      hipLaunchKernelGGL(k_sum_correct<false>, g, b, lds, s, d, eta, dt_shared, level_min,
                          level_max);
   } else if (d.fld.on) {
     hipLaunchKernelGGL(k_correct<true>, dim3(grid_for(d.n, kWG, 2048)), dim3(kWG), 0, s,
