@@ -572,6 +572,11 @@ def main():
                        "kernel_ms": fp64["kernel_ms"], "achieved_tflops": f_ach,
                        "frac_fp64_peak": f_ach / FP64_VECTOR_PEAK_TFLOPS}
         out["mixed_over_fp64"] = mixed["rate"] / fp64["rate"]
+    # the targets of the mixed path and where the measurement stands
+    out["targets"] = {
+        "frac_fp32_peak": {"target": 0.60, "achieved": achieved / FP32_VECTOR_PEAK_TFLOPS},
+        "mixed_over_fp64": {"target": 2.0,
+                            "achieved": (mixed["rate"] / fp64["rate"]) if fp64 else None}}
     if mixed_ds:
         # the other mixed form: x_j - x_i from double-single pairs and FP32
         # velocity differences (the paper's software double precision)

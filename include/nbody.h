@@ -336,13 +336,16 @@ typedef struct nbody_tuning {
                                estimate of i's jerk is evaluated in FP64 and
                                left out of the FP32 sums (the few close
                                neighbours whose terms set the FP32 error of
-                               the jerk; about two pairs per particle at
-                               the default 0.0625).  The estimate is i's
-                               stored jerk in block steps, and a first FP64-
-                               free pass over the same evaluation otherwise
+                               the jerk; 3-6 pairs per particle at the
+                               default 0.0625).  The estimate is a first
+                               FP64-free pass over the same evaluation
                                (nbody_init, nbody_forces, the closing
-                               evaluation of nbody_step_symplectic).  < 0
-                               turns near pairs off. */
+                               evaluation of nbody_step_symplectic), and a
+                               particle whose estimate exceeds twice its
+                               jerk is re-evaluated in FP64; in block steps
+                               it is the particle's stored jerk, with the
+                               threshold halved and four times its jerk as
+                               the bound.  < 0 turns near pairs off. */
   int32_t small_log2;       /* mixed paths, block steps: a cluster whose step
                                has at most 256 active particles or at most
                                2^small_log2 interactions (n_active x N_c) is

@@ -432,6 +432,12 @@ nbk::NearSpec near_spec(const nbody_ctx *c, int mode, int src) {
                   mode != nbk::kModePot && mode != nbk::kModeFP64;
   nr.src = on ? src : nbk::kNearNone;
   if (!on) nr.c = 0.0f;
+  // block steps take the estimate from the stored jerk of the particle's
+  // previous step: half the threshold, and a stale bound of kNearStaleState
+  // instead of kNearStale, give the same effective threshold (at most
+  // 2 near_jerk times the jerk found) while tolerating a jerk that fell
+  // by up to 4x over the step
+  if (nr.src == nbk::kNearState) nr.c *= 0.5f;
   return nr;
 }
 

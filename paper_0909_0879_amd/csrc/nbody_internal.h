@@ -33,6 +33,8 @@ constexpr double kFarRatio = 8.0;   // double-single: a far-field jerk scale
 constexpr double kNearStale = 2.0;  // a near-pair threshold taken from a jerk
                                     // estimate more than this many times the
                                     // jerk found sends the particle to FP64
+constexpr double kNearStaleState = 4.0;   // the same for block steps, whose
+                                    // thresholds are halved (stored jerk)
 
 // kErrState: a state given to nbody_set_state, or found by a driver, that
 // breaks the block-step invariants

@@ -2345,7 +2345,8 @@ __global__ void k_sym_advance(Dev d, int64_t dticks) {
 //    max_j m_j / s_ij, exceeds ratio times the net acceleration (there the
 //    FP32 error of that term is not small against the result), and the
 //    entries whose near-pair threshold was taken from a jerk estimate (the
-//    stored jerk, or the first pass) more than kNearStale times the jerk
+//    stored jerk, or the first pass) more than kNearStaleState (stored
+//    jerk, whose thresholds are halved) or kNearStale times the jerk
 //    found (the near pairs were then chosen too coarsely), and, in the
 //    double-single form, the entries whose far-field scale (column 7)
 //    exceeds kFarRatio times the jerk (a jerk that is a small remainder of a
@@ -2397,7 +2398,8 @@ __global__ __launch_bounds__(kWG) void k_sum_flag(Dev d, const int32_t *list,
       } else if (near_src == kNearList) {
         jest = (double)d.theta[k] / (double)near_c;
       }
-      if (jest >= 0.0) flag |= !(jest <= kNearStale * jn);
+      if (jest >= 0.0)
+        flag |= !(jest <= (near_src == kNearState ? kNearStaleState : kNearStale) * jn);
       // double-single form: the far-field scale against the jerk
       if (near_src != kNearNone && tf1 > 0.0) flag |= !(tf1 <= kFarRatio * jn);
     }
