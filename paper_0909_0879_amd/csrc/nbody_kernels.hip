@@ -1393,28 +1393,6 @@ __device__ __forceinline__ void neu_add(double &s, double &c, double x) {
   s = u;
 }
 
-// Fixed-order sum of NC compensated pairs over aligned groups of 2 top lanes
-// (xor tree from offset top down to 1); every lane of a group ends with the
-// group's total.
-template <int NC>
-__device__ __forceinline__ void group_neu_reduce(double (&s)[NC], double (&c)[NC], int top) {
-  for (int off = top; off >= 1; off >>= 1) {
-#pragma unroll
-    for (int q = 0; q < NC; ++q) {
-      const double os = __shfl_xor(s[q], off), oc = __shfl_xor(c[q], off);
-      // order the pair by lane so both lanes of a butterfly compute the
-      // identical value
-      const bool low = (threadIdx.x & off) == 0;
-      const double a = low ? s[q] : os, b = low ? os : s[q];
-      const double ca = low ? c[q] : oc, cb = low ? oc : c[q];
-      double t = a, tc = ca + cb;
-      neu_add(t, tc, b);
-      s[q] = t;
-      c[q] = tc;
-    }
-  }
-}
-
 // Sum the S partial rows of one slot with a group of G = 2^glog lanes (an
 // aligned part of the wave; every lane of the wave calls this, lanes of an
 // idle group with valid = false): lane l of the group takes rows l, l + G,
@@ -2355,10 +2333,8 @@ __global__ void k_sym_advance(Dev d, int64_t dticks) {
 // (the plan's glog and sum_prefix); the flag counts per kScanBlock entries
 // go to blk_cnt for the ordered compaction of the flagged entries
 // (k_rscatter).
-__global__ __launch_bounds__(kWG) void k_sum_flag(Dev d, const int32_t *list,
-                                                  int64_t na_host, float ratio, float near_c,
-                                                  int near_src, int theta_out) {
-  const bool api = na_host >= 0;
+__global__ __launch_bounds__(kWG) void k_sum_flag(Dev d, const int32_t *list, float ratio,
+                                                  float near_c, int near_src, int theta_out) {
   const int lane = threadIdx.x & 63;
   const int nw = d.sum_prefix[d.C];
   const int wave0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -2907,7 +2883,7 @@ hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_hos
   const int64_t cap = na_host >= 0 ? na_host : d.cap_active;
   // at most one wave per entry, grid-stride
   hipLaunchKernelGGL(k_sum_flag, dim3(grid_for(cap * 64, kWG, 4096)), dim3(kWG),
-                     prefix_lds_bytes(d.C), s, d, list, na_host, refine_ratio, nr.c, nr.src,
+                     prefix_lds_bytes(d.C), s, d, list, refine_ratio, nr.c, nr.src,
                      theta_out ? 1 : 0);
   if (refine_ratio > 0.0f && !theta_out) {
     if (d.nblk <= kFusedScan) {
