@@ -215,3 +215,33 @@ def test_mixed_block_steps_conserve_energy():
         check_parity(a, j, a_ref, j_ref, prec == binding.MIXED, "final state")
     assert res[binding.FP64] < 1e-4
     assert res[binding.MIXED] < 10 * res[binding.FP64] + 1e-7
+
+
+def test_small_step_routing_tuning():
+    # small_log2: 0 keeps the value, -1 turns the FP64 routing of small mixed
+    # steps off, 1..62 set it; anything else is rejected on the host
+    require_gpu()
+    m, x, v = ics.plummer(512, 4)
+    g = binding.NBody(m, x, v, eps=1e-3, precision=binding.MIXED, level_min=5, level_max=20)
+    assert g.get_tuning()["small_log2"] == 27
+    g.set_tuning({"small_log2": 0})
+    assert g.get_tuning()["small_log2"] == 27
+    g.set_tuning({"small_log2": -1})
+    assert g.get_tuning()["small_log2"] == -1
+    st0 = g.stats()
+    g.step(1 / 32)
+    st1 = g.stats()
+    assert st1["small_step_interactions"] == st0["small_step_interactions"]
+    assert st1["interactions"] > st0["interactions"]
+    g.set_tuning({"small_log2": 62})
+    st2 = g.stats()
+    g.step(1 / 16)
+    st3 = g.stats()
+    # every step of 512 particles is small: all of it on the FP64 kernel
+    assert (st3["small_step_interactions"] - st2["small_step_interactions"]
+            == st3["interactions"] - st2["interactions"] > 0)
+    for bad in (63, -2, 200):
+        with pytest.raises(binding.NBodyError) as e:
+            g.set_tuning({"small_log2": bad})
+        assert e.value.code == binding.EINVAL
+    assert g.get_tuning()["small_log2"] == 62
