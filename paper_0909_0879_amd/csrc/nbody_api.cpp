@@ -78,6 +78,7 @@ size_t carve(int64_t n, int32_t C, char *base, Dev *d, int rows_per_j = nbk::kRo
   t.active = (int32_t *)take(sizeof(int32_t) * t.cap_active);
   t.act_off = (int32_t *)take(sizeof(int32_t) * (C + 1));
   t.blk_cnt = (int32_t *)take(sizeof(int32_t) * t.nblk);
+  t.flag_cnt = (int32_t *)take(sizeof(int32_t) * t.nblk);
   t.blk_off = (int32_t *)take(sizeof(int32_t) * (t.nblk + 1));
   t.plan_c = (nbk::ClusterPlan *)take(sizeof(nbk::ClusterPlan) * C);
   t.plan_lpt = (nbk::ClusterPlan *)take(sizeof(nbk::ClusterPlan) * C);
@@ -353,6 +354,12 @@ int refresh_grids(nbody_ctx *c) {
 
 int harvest_events(nbody_ctx *c);
 
+// Block steps of one small cluster build their j records in the compaction
+// (one launch fewer per step).
+bool rec_in_compact(const nbody_ctx *c) {
+  return c->C == 1 && nbk::plan_fused(c->d) && c->n <= nbk::kRecInCompactMax;
+}
+
 // Launch the force kernel, bracketed by timing events when profiling.
 // rec_kind >= 0 (a PlanKind): build the evaluation's j records first when its
 // active set is large, and let the broadcast kernel take it when enabled.
@@ -371,7 +378,7 @@ int force_launch(nbody_ctx *c, int mode, int src, int K, const nbk::RawSrc *raw,
   const bool rec_only = mixed_step || rec_kind == nbk::kPlanState;
   const bool sb = nbk::mode_acc_only(mode) ? c->sba : c->sb;
   const bool sb_only = mixed_step && c->step_sb_only;
-  if (use_pred)
+  if (use_pred && !(rec_kind == nbk::kPlanStep && rec_in_compact(c)))
     NB_HIP(nbk::launch_records(c->d, mode, rec_kind, raw, sb, rec_only, sb_only, s));
   if (prof && c->ev_used == kEvPairs) {
     int rc = harvest_events(c);
@@ -492,7 +499,9 @@ int two_pass(nbody_ctx *c, const int32_t *list, int64_t na_host, const nbk::RawS
 int enqueue_block_step(nbody_ctx *c, hipStream_t s) {
   const nbk::Tuning t = device_tuning(c, c->K);
   const bool allow_small = is_mixed(c->prec);
-  NB_HIP(nbk::launch_compact(c->d, t, allow_small, s));
+  const bool rc_records = rec_in_compact(c);
+  NB_HIP(nbk::launch_compact(c->d, t, allow_small, rc_records ? mode_of(c) : -1, c->sb,
+                             rc_records && is_mixed(c->prec) && c->step_sb_only, s));
   if (!nbk::plan_fused(c->d))
     NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanStep, 0, allow_small, s));
   const nbk::NearSpec nr = near_spec(c, mode_of(c), nbk::kNearState);

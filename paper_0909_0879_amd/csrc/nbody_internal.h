@@ -23,6 +23,9 @@ constexpr int kSmallStep = 256;     // mixed block steps up to this many active
                                     // particles are evaluated by the FP64 kernel,
                                     // and so are those of up to Tuning::small_work
                                     // interactions (n_active x N_c)
+constexpr int64_t kRecInCompactMax = (int64_t)1 << 17;   // one-cluster block
+                                    // steps up to this many particles build
+                                    // their j records in the compaction
 constexpr int kRowsPerJ = 32;       // partial rows a cluster may take per j-particle
 constexpr int kRowStride = 8;       // doubles per partial row: a(3), jerk(3),
                                     // bound on the largest acc term, far-field
@@ -128,7 +131,8 @@ struct Dev {
   // active list and compaction
   int32_t *active;     // cap_active
   int32_t *act_off;    // C + 1
-  int32_t *blk_cnt;    // nblk
+  int32_t *blk_cnt;    // nblk: due particles per compaction block
+  int32_t *flag_cnt;   // nblk: flagged entries per block of the active list
   int32_t *blk_off;    // nblk + 1
   // plan
   ClusterPlan *plan_c;    // C, by cluster id
@@ -213,7 +217,13 @@ hipError_t launch_all_active(const Dev &d, const Tuning &t, hipStream_t s);
 bool plan_fused(const Dev &d);
 // Scheduler (per-cluster T_next and threshold level) and ordered compaction
 // of the due particles into the active list (plan: see plan_fused).
-hipError_t launch_compact(const Dev &d, const Tuning &t, bool allow_small, hipStream_t s);
+// rec_mode >= 0 (a force mode; one cluster with plan_fused and at most
+// kRecInCompactMax particles): the compaction also writes every particle's
+// j record predicted to T_next and the record flag (allow_sb, sb_only as in
+// launch_records), so no launch_records follows; -1: records are left to
+// launch_records.
+hipError_t launch_compact(const Dev &d, const Tuning &t, bool allow_small, int rec_mode,
+                          bool allow_sb, bool sb_only, hipStream_t s);
 // allow_small: clusters of a small block step (at most kSmallStep active
 // particles, or at most Tuning::small_work interactions) are planned for the
 // small-step FP64 launch (mixed contexts).  A re-evaluation plan also

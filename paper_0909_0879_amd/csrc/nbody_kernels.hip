@@ -1277,24 +1277,28 @@ __global__ __launch_bounds__(kWG) void k_count(Dev d) {
     if (i < d.n && d.level[i] >= thr[d.cid[i] - c0]) ++cnt;
   }
   cnt = block_sum_i(cnt, sh);
-  if (threadIdx.x == 0) d.blk_cnt[blockIdx.x] = cnt;
+  if (threadIdx.x == 0) {
+    d.blk_cnt[blockIdx.x] = cnt;
+    d.flag_cnt[blockIdx.x] = 0;     // this step's flagging pass counts from zero
+  }
 }
 
-// Sum of blk_cnt[0, b) by the whole block (grids of at most kFusedScan
-// blocks, where every block reading the counts beats a separate scan launch).
-__device__ __forceinline__ int block_prefix(const Dev &d, int b, int *sh4) {
+// Sum of cnt[0, b) by the whole block (grids of at most kFusedScan blocks,
+// where every block reading the counts beats a separate scan launch).
+__device__ __forceinline__ int block_prefix(const int32_t *cnt, int b, int *sh4) {
   int v = 0;
-  for (int u = threadIdx.x; u < b; u += kWG) v += d.blk_cnt[u];
+  for (int u = threadIdx.x; u < b; u += kWG) v += cnt[u];
   return block_sum_i(v, sh4);
 }
 
-// Exclusive scan of nblk block counts by one 1024-thread workgroup.
-__global__ __launch_bounds__(1024) void k_scan(Dev d) {
+// Exclusive scan of nblk block counts (cnt: blk_cnt or flag_cnt) into blk_off
+// by one 1024-thread workgroup.
+__global__ __launch_bounds__(1024) void k_scan(Dev d, const int32_t *cnt) {
   __shared__ int sh[1024];
   int carry = 0;
   for (int base = 0; base < d.nblk; base += 1024) {
     const int i = base + threadIdx.x;
-    const int v = (i < d.nblk) ? d.blk_cnt[i] : 0;
+    const int v = (i < d.nblk) ? cnt[i] : 0;
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -1312,13 +1316,19 @@ __global__ __launch_bounds__(1024) void k_scan(Dev d) {
 
 // Ordered compaction: active list ascending in particle index, and each
 // cluster's offset in it.  FUSED: the block sums the counts before it
-// itself (no k_scan).
-template <bool FUSED>
+// itself (no k_scan).  RMODE >= 0 (one small cluster, FUSED, block steps):
+// each block also writes the j records of its particles, predicted to
+// T_next, in place of the record kernel (there one more launch costs more
+// than the prediction), and the plan's thread sets the record flag as the
+// record kernel would (0: not built; 1: built; 2: built and the broadcast
+// kernel takes them, when allow_sb and the cluster's main items have kWG
+// i-slots; with sb_only a flag other than 2 is reported as kErrState).
+template <bool FUSED, int RMODE>
 __global__ __launch_bounds__(kWG) void k_scatter(Dev d, Tuning tu, int plan_kind,
-                                                 int allow_small) {
+                                                 int allow_small, int allow_sb, int sb_only) {
   __shared__ int wsum[4];
   __shared__ int sh4[4];
-  const int bpre = FUSED ? block_prefix(d, blockIdx.x, sh4) : d.blk_off[blockIdx.x];
+  const int bpre = FUSED ? block_prefix(d.blk_cnt, blockIdx.x, sh4) : d.blk_off[blockIdx.x];
   const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
   int flag[4];
   int cnt = 0;
@@ -1350,11 +1360,48 @@ __global__ __launch_bounds__(kWG) void k_scatter(Dev d, Tuning tu, int plan_kind
       if (flag[e]) d.active[pos++] = (int32_t)i;
     }
   }
+  bool rec_on = false;
+  if constexpr (RMODE >= 0) {
+    // the due count of the whole cluster, for the plan's small-step test
+    // (a step the FP64 small-step launch takes reads no records)
+    __shared__ int sh4t[4];
+    int v = 0;
+    for (int u = threadIdx.x; u < d.nblk; u += kWG) v += d.blk_cnt[u];
+    const int na = block_sum_i(v, sh4t);
+    const bool small = allow_small && tu.small_work >= 0 &&
+                       (na <= kSmallStep || (int64_t)na * d.n <= tu.small_work);
+    // as the record kernel decides: mixed steps always read records, FP64
+    // steps only when at least one particle in 16 is due
+    rec_on = mode_mixed(RMODE) || (int64_t)na * 16 >= d.n;
+    if (d.Lthr[0] != kNoActive && rec_on && !small) {
+      using Rec = typename Traits<RMODE>::Rec;
+      Rec *pred = reinterpret_cast<Rec *>(d.pred);
+      const double mref = mode_mixed(RMODE) ? mass_ref(d.m[0]) : 1.0;
+      const int64_t t1 = d.Tnext[0];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = (int64_t)blockIdx.x * kScanBlock + e * kWG + threadIdx.x;
+        if (i < d.n) {
+          double xp[3], vp[3];
+          predict_state(d, i, t1, xp, vp);
+          Rec r;
+          make_rec(xp, vp, d.m[i], (int32_t)i, r, mref);
+          pred[i] = r;
+        }
+      }
+    }
+  }
   if (FUSED) {
     if (blockIdx.x == d.nblk - 1 && threadIdx.x == kWG - 1) {
       d.act_off[d.C] = pos;
       // one cluster: the active count is known here, so plan here
       if (plan_kind >= 0) plan_single(d, tu, plan_kind, 0, allow_small, pos);
+      if constexpr (RMODE >= 0) {
+        const ClusterPlan &p = d.plan_c[0];
+        const bool elig = allow_sb && !(p.na > 0 && !p.small && p.P != kWG);
+        *d.pred_on = rec_on ? (elig ? 2 : 1) : 0;
+        if (sb_only && !(rec_on && elig)) atomicOr(d.err, (int)kErrState);
+      }
     }
   } else if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.act_off[d.C] = d.blk_off[d.nblk];
@@ -1964,10 +2011,9 @@ __global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, in
   const bool api = kind == kPlanApi;
   const int64_t nj = (api && raw.n_j > 0) ? raw.n_j : d.n;
   const int64_t total = api ? raw.n_active : (int64_t)d.act_off[d.C];
-  // the flag counts of this evaluation's k_sum_flag start at zero (the
-  // compaction that used blk_cnt ran before this kernel)
+  // the flag counts of this evaluation's k_sum_flag start at zero
   for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < d.nblk; b += gridDim.x * blockDim.x)
-    d.blk_cnt[b] = 0;
+    d.flag_cnt[b] = 0;
   // the buffer holds d.n records
   const bool on = (always || total * 16 >= nj) && nj <= d.n;
   if (blockIdx.x == 0) {
@@ -2331,7 +2377,7 @@ __global__ void k_sym_advance(Dev d, int64_t dticks) {
 //    far field many times larger).
 // Each entry's rows are summed by a group of lanes sized to its split count
 // (the plan's glog and sum_prefix); the flag counts per kScanBlock entries
-// go to blk_cnt for the ordered compaction of the flagged entries
+// go to flag_cnt for the ordered compaction of the flagged entries
 // (k_rscatter).
 __global__ __launch_bounds__(kWG) void k_sum_flag(Dev d, const int32_t *list, float ratio,
                                                   float near_c, int near_src, int theta_out) {
@@ -2380,9 +2426,10 @@ __global__ __launch_bounds__(kWG) void k_sum_flag(Dev d, const int32_t *list, fl
       if (near_src != kNearNone && tf1 > 0.0) flag |= !(tf1 <= kFarRatio * jn);
     }
     d.rflag[k] = flag;
-    // per-block counts for the ordered compaction (zeroed by the record
-    // kernel before this evaluation's force launches)
-    if (flag) atomicAdd(&d.blk_cnt[k / kScanBlock], 1);
+    // per-block counts for the ordered compaction (zeroed before this
+    // evaluation's force launches, by the record kernel or, for a block step,
+    // by the step's k_count)
+    if (flag) atomicAdd(&d.flag_cnt[k / kScanBlock], 1);
   }
 }
 
@@ -2397,7 +2444,7 @@ __global__ __launch_bounds__(kWG) void k_rscatter(Dev d, const int32_t *list,
                                                   int64_t api_nj) {
   __shared__ int wsum[4];
   __shared__ int sh4[4];
-  const int bpre = FUSED ? block_prefix(d, blockIdx.x, sh4) : d.blk_off[blockIdx.x];
+  const int bpre = FUSED ? block_prefix(d.flag_cnt, blockIdx.x, sh4) : d.blk_off[blockIdx.x];
   const int64_t total = na_host >= 0 ? na_host : d.act_off[d.C];
   const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
   int flag[4];
@@ -2648,15 +2695,31 @@ hipError_t launch_all_active(const Dev &d, const Tuning &t, hipStream_t s) {
 
 bool plan_fused(const Dev &d) { return d.C == 1 && d.nblk <= kFusedScan; }
 
-hipError_t launch_compact(const Dev &d, const Tuning &t, bool allow_small, hipStream_t s) {
+hipError_t launch_compact(const Dev &d, const Tuning &t, bool allow_small, int rec_mode,
+                          bool allow_sb, bool sb_only, hipStream_t s) {
   hipLaunchKernelGGL(k_count, dim3(d.nblk), dim3(kWG), 0, s, d);
-  const int al = allow_small ? 1 : 0;
+  const int al = allow_small ? 1 : 0, sb = allow_sb ? 1 : 0, so = sb_only ? 1 : 0;
   if (d.nblk <= kFusedScan) {
-    hipLaunchKernelGGL(k_scatter<true>, dim3(d.nblk), dim3(kWG), 0, s, d, t,
-                       plan_fused(d) ? (int)kPlanStep : -1, al);
+    const int pk = plan_fused(d) ? (int)kPlanStep : -1;
+    if (rec_mode >= 0 && !(plan_fused(d) && d.n <= kRecInCompactMax))
+      return hipErrorInvalidValue;
+    if (rec_mode == kModeFP64)
+      hipLaunchKernelGGL((k_scatter<true, kModeFP64>), dim3(d.nblk), dim3(kWG), 0, s, d, t, pk,
+                         al, sb, so);
+    else if (rec_mode == kModeMixed64)
+      hipLaunchKernelGGL((k_scatter<true, kModeMixed64>), dim3(d.nblk), dim3(kWG), 0, s, d, t,
+                         pk, al, sb, so);
+    else if (rec_mode == kModeMixed)
+      hipLaunchKernelGGL((k_scatter<true, kModeMixed>), dim3(d.nblk), dim3(kWG), 0, s, d, t, pk,
+                         al, sb, so);
+    else
+      hipLaunchKernelGGL((k_scatter<true, -1>), dim3(d.nblk), dim3(kWG), 0, s, d, t, pk, al, sb,
+                         so);
   } else {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d);
-    hipLaunchKernelGGL(k_scatter<false>, dim3(d.nblk), dim3(kWG), 0, s, d, t, -1, al);
+    if (rec_mode >= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d, (const int32_t *)d.blk_cnt);
+    hipLaunchKernelGGL((k_scatter<false, -1>), dim3(d.nblk), dim3(kWG), 0, s, d, t, -1, al, sb,
+                       so);
   }
   return hipGetLastError();
 }
@@ -2890,7 +2953,7 @@ hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_hos
       hipLaunchKernelGGL(k_rscatter<true>, dim3(d.nblk), dim3(kWG), 0, s, d, list, na_host, t1,
                          plan_fused(d) ? ref_kind : -1, api_nj);
     } else {
-      hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d);
+      hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, d, (const int32_t *)d.flag_cnt);
       hipLaunchKernelGGL(k_rscatter<false>, dim3(d.nblk), dim3(kWG), 0, s, d, list, na_host,
                          t1, -1, api_nj);
     }
