@@ -95,6 +95,7 @@ size_t carve(int64_t n, int32_t C, char *base, Dev *d, int rows_per_j = nbk::kRo
   t.pred_on = (int32_t *)take(sizeof(int32_t) * 4);
   t.work = (int32_t *)take(sizeof(int32_t) * 4);
   t.err = (int32_t *)take(sizeof(int32_t) * 4);
+  t.sync = (int32_t *)take(sizeof(int32_t) * 4);
   t.ctr = (int64_t *)take(sizeof(int64_t) * nbk::kCtrCount);
   t.eout = (double *)take(sizeof(double) * 9 * C);
   if (d) *d = t;
@@ -354,11 +355,9 @@ int refresh_grids(nbody_ctx *c) {
 
 int harvest_events(nbody_ctx *c);
 
-// Block steps of one small cluster build their j records in the compaction
-// (one launch fewer per step).
-bool rec_in_compact(const nbody_ctx *c) {
-  return c->C == 1 && nbk::plan_fused(c->d) && c->n <= nbk::kRecInCompactMax;
-}
+// Block steps of one cluster whose compaction also plans build their j
+// records in the compaction too (one launch fewer per step).
+bool rec_in_compact(const nbody_ctx *c) { return nbk::plan_fused(c->d); }
 
 // Launch the force kernel, bracketed by timing events when profiling.
 // rec_kind >= 0 (a PlanKind): build the evaluation's j records first when its
@@ -451,16 +450,19 @@ nbk::NearSpec near_spec(const nbody_ctx *c, int mode, int src) {
 // Sum the partial rows into fsum and, on the mixed path, re-evaluate the
 // flagged entries with the FP64 kernel (a second plan over the flagged list).
 // nr: where the evaluation's near-pair thresholds came from (the flags test
-// them against the jerk found).
+// them against the jerk found).  corr (block steps): the flagged entries are
+// appended (one cluster), and the re-evaluation's final launch applies the
+// corrector to every active particle.
 int sum_and_refine(nbody_ctx *c, const int32_t *list, int64_t na_host, const nbk::RawSrc *raw,
-                   hipStream_t s, bool acc_only, nbk::NearSpec nr) {
+                   hipStream_t s, bool acc_only, nbk::NearSpec nr,
+                   const nbk::CorrectSpec *corr = nullptr) {
   const float ratio = refine_ratio(c);
   const nbk::Tuning t1 = device_tuning(c, 1);
   const bool api = raw != nullptr;
   const int ref_kind = api ? nbk::kPlanApiRefine : nbk::kPlanRefine;
   const int64_t api_nj = api ? raw->n_j : 0;
   NB_HIP(nbk::launch_sum_and_flag(c->d, list, na_host, ratio, nr, false, t1, ref_kind, api_nj,
-                                  s));
+                                  corr != nullptr, s));
   if (ratio <= 0.0f) return NBODY_OK;
   if (!nbk::plan_fused(c->d))
     NB_HIP(nbk::launch_plan(c->d, t1, ref_kind, api_nj, false, s));
@@ -469,7 +471,7 @@ int sum_and_refine(nbody_ctx *c, const int32_t *list, int64_t na_host, const nbk
   int rc = force_launch(c, acc_only ? nbk::kModeFP64Acc : nbk::kModeFP64,
                         api ? nbk::kSrcRaw : nbk::kSrcState, 1, raw, c->d.ref_i, grid, s);
   if (rc) return rc;
-  NB_HIP(nbk::launch_refine_finalize(c->d, s));
+  NB_HIP(nbk::launch_refine_finalize(c->d, corr, s));
   return NBODY_OK;
 }
 
@@ -487,7 +489,8 @@ int two_pass(nbody_ctx *c, const int32_t *list, int64_t na_host, const nbk::RawS
   if (rc) return rc;
   if (second.src == nbk::kNearList) {
     const nbk::Tuning t1 = device_tuning(c, 1);
-    NB_HIP(nbk::launch_sum_and_flag(c->d, list, na_host, 0.0f, second, true, t1, 0, 0, s));
+    NB_HIP(nbk::launch_sum_and_flag(c->d, list, na_host, 0.0f, second, true, t1, 0, 0, false,
+                                    s));
     NB_HIP(nbk::launch_fill32(c->d.work, 0, 2, s));
     if ((rc = launch(second))) return rc;
   }
@@ -508,14 +511,14 @@ int enqueue_block_step(nbody_ctx *c, hipStream_t s) {
   int rc = force_launch(c, mode_of(c), nbk::kSrcState, c->K, nullptr, c->d.active,
                         c->grid_state, s, nbk::kPlanStep, nr);
   if (rc) return rc;
-  // with re-evaluation: sums and flags, the FP64 pass, then the corrector;
-  // without: the corrector sums the rows itself
-  int src = nbk::kCorrectGroups;
+  // with re-evaluation: sums and flags, the FP64 pass, then its final
+  // launch corrects every active particle; without: the corrector sums the
+  // rows itself
   if (refine_ratio(c) > 0.0f) {
-    if ((rc = sum_and_refine(c, c->d.active, -1, nullptr, s, false, nr))) return rc;
-    src = nbk::kCorrectFsum;
+    const nbk::CorrectSpec cs{c->eta, c->dt_shared, c->lmin, c->lmax};
+    return sum_and_refine(c, c->d.active, -1, nullptr, s, false, nr, &cs);
   }
-  NB_HIP(nbk::launch_correct(c->d, c->eta, c->dt_shared, c->lmin, c->lmax, src, s));
+  NB_HIP(nbk::launch_correct(c->d, c->eta, c->dt_shared, c->lmin, c->lmax, s));
   return NBODY_OK;
 }
 

@@ -23,9 +23,6 @@ constexpr int kSmallStep = 256;     // mixed block steps up to this many active
                                     // particles are evaluated by the FP64 kernel,
                                     // and so are those of up to Tuning::small_work
                                     // interactions (n_active x N_c)
-constexpr int64_t kRecInCompactMax = (int64_t)1 << 17;   // one-cluster block
-                                    // steps up to this many particles build
-                                    // their j records in the compaction
 constexpr int kRowsPerJ = 32;       // partial rows a cluster may take per j-particle
 constexpr int kRowStride = 8;       // doubles per partial row: a(3), jerk(3),
                                     // bound on the largest acc term, far-field
@@ -154,6 +151,8 @@ struct Dev {
   // words
   int32_t *work;       // [0] main item counter, [1] small-step item counter,
                        // [2] number of main items (written by k_plan)
+  int32_t *sync;       // [0] flagged-entry count, [1] finished blocks of an
+                       // appending k_sum_flag (both zero between launches)
   int32_t *err;        // sticky error bits
   int64_t *ctr;        // kCtrCount counters
   double *eout;        // C * 9 energy output
@@ -217,8 +216,8 @@ hipError_t launch_all_active(const Dev &d, const Tuning &t, hipStream_t s);
 bool plan_fused(const Dev &d);
 // Scheduler (per-cluster T_next and threshold level) and ordered compaction
 // of the due particles into the active list (plan: see plan_fused).
-// rec_mode >= 0 (a force mode; one cluster with plan_fused and at most
-// kRecInCompactMax particles): the compaction also writes every particle's
+// rec_mode >= 0 (a force mode; one cluster with plan_fused): the
+// compaction also writes every particle's
 // j record predicted to T_next and the record flag (allow_sb, sb_only as in
 // launch_records), so no launch_records follows; -1: records are left to
 // launch_records.
@@ -237,11 +236,22 @@ hipError_t launch_plan(const Dev &d, const Tuning &t, int kind,
 // acceleration or whose near-pair threshold came from a jerk estimate above
 // kNearStale times their jerk (nr.src), and build the grouped re-evaluation
 // list.
+// Hermite corrector parameters of a block step.
+struct CorrectSpec {
+  double eta, dt_shared;
+  int lmin, lmax;
+};
+// append (block steps): with one cluster and a fused plan, the flagged
+// entries are appended to the list in any order and the sum launch writes
+// the re-evaluation plan (no k_rscatter).
 hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_host,
                                float refine_ratio, const NearSpec &nr, bool theta_out,
-                               const Tuning &t1, int ref_kind, int64_t api_nj, hipStream_t s);
-// Overwrite fsum of the re-evaluated entries with their FP64 sums.
-hipError_t launch_refine_finalize(const Dev &d, hipStream_t s);
+                               const Tuning &t1, int ref_kind, int64_t api_nj, bool append,
+                               hipStream_t s);
+// Overwrite fsum of the re-evaluated entries with their FP64 sums; corr
+// (block steps): and apply the corrector to every active particle, so no
+// launch_correct follows.
+hipError_t launch_refine_finalize(const Dev &d, const CorrectSpec *corr, hipStream_t s);
 // Which work a force launch takes.  The plan splits the items in two:
 // [0, work[2]) for the main launches, [work[2], total) for the small-step
 // launch.  kRoleAlways: the main items, whatever the record flag
@@ -275,13 +285,11 @@ hipError_t launch_sym_kick_drift(const Dev &d, double ck, double cd, bool check,
                                  const Tuning &t, hipStream_t s);
 hipError_t launch_sym_kick(const Dev &d, double ck, hipStream_t s);
 hipError_t launch_sym_advance(const Dev &d, int64_t dticks, hipStream_t s);
-// Where the corrector takes each active particle's new force from:
-// kCorrectFsum: fsum (launch_sum_and_flag ran, and launch_refine_finalize
-// after a re-evaluation); kCorrectGroups: the step plan's partial rows,
-// summed in the same launch (steps without a re-evaluation pass).
-enum CorrectSrc : int { kCorrectFsum = 0, kCorrectGroups = 1 };
+// Row sums of the step plan's partial rows and the corrector in one launch
+// (block steps without a re-evaluation pass; with one, the re-evaluation's
+// launch_refine_finalize corrects).
 hipError_t launch_correct(const Dev &d, double eta, double dt_shared,
-                          int level_min, int level_max, int src, hipStream_t s);
+                          int level_min, int level_max, hipStream_t s);
 hipError_t launch_init_levels(const Dev &d, double eta_start,
                               double dt_shared, int level_min, int level_max,
                               hipStream_t s);

@@ -1098,6 +1098,7 @@ __global__ void k_init_state(Dev d, const double *m, const double *x,
     d.cid[i] = find_cluster(d.coff, d.C, i);
   }
   const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gt < 2) d.sync[gt] = 0;
   if (gt < d.C) {
     d.T[gt] = 0;
     d.Tnext[gt] = 0;
@@ -1316,7 +1317,7 @@ __global__ __launch_bounds__(1024) void k_scan(Dev d, const int32_t *cnt) {
 
 // Ordered compaction: active list ascending in particle index, and each
 // cluster's offset in it.  FUSED: the block sums the counts before it
-// itself (no k_scan).  RMODE >= 0 (one small cluster, FUSED, block steps):
+// itself (no k_scan).  RMODE >= 0 (one cluster, FUSED, block steps):
 // each block also writes the j records of its particles, predicted to
 // T_next, in place of the record kernel (there one more launch costs more
 // than the prediction), and the plan's thread sets the record flag as the
@@ -1827,23 +1828,6 @@ __device__ __forceinline__ void correct_one(const Dev &d, int64_t i, int c, doub
       atomicAdd(&d.hist[c * kLevels + nl], 1);
       d.level[i] = nl;
     }
-  }
-}
-
-// Corrector over the active list, one thread per entry, with the new force
-// from fsum (launch_sum_and_flag, and the FP64 re-evaluation's
-// launch_refine_finalize, ran before).
-template <bool FIELD>
-__global__ __launch_bounds__(kWG) void k_correct(Dev d, double eta, double dt_shared,
-                                                 int lmin, int lmax) {
-  const int total = d.act_off[d.C];
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < total;
-       k += gridDim.x * blockDim.x) {
-    const int64_t i = d.active[k];
-    double f[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) f[q] = d.fsum[6 * (int64_t)k + q];
-    correct_one<FIELD>(d, i, d.cid[i], f, eta, dt_shared, lmin, lmax);
   }
 }
 
@@ -2378,9 +2362,15 @@ __global__ void k_sym_advance(Dev d, int64_t dticks) {
 // Each entry's rows are summed by a group of lanes sized to its split count
 // (the plan's glog and sum_prefix); the flag counts per kScanBlock entries
 // go to flag_cnt for the ordered compaction of the flagged entries
-// (k_rscatter).
+// (k_rscatter).  APPEND (one cluster): the flagged entries go to the
+// re-evaluation list through one atomic counter, in whatever order they
+// come (each entry's FP64 sums do not depend on its place in the list), and
+// the last block to finish publishes the count and writes the re-evaluation
+// plan (plan_kind), in place of k_rscatter.
+template <bool APPEND>
 __global__ __launch_bounds__(kWG) void k_sum_flag(Dev d, const int32_t *list, float ratio,
-                                                  float near_c, int near_src, int theta_out) {
+                                                  float near_c, int near_src, int theta_out,
+                                                  Tuning tu, int plan_kind) {
   const int lane = threadIdx.x & 63;
   const int nw = d.sum_prefix[d.C];
   const int wave0 = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -2429,7 +2419,40 @@ __global__ __launch_bounds__(kWG) void k_sum_flag(Dev d, const int32_t *list, fl
     // per-block counts for the ordered compaction (zeroed before this
     // evaluation's force launches, by the record kernel or, for a block step,
     // by the step's k_count)
-    if (flag) atomicAdd(&d.flag_cnt[k / kScanBlock], 1);
+    if (flag) {
+      if constexpr (APPEND) {
+        const int r = atomicAdd(&d.sync[0], 1);
+        d.ref_i[r] = list[k];
+        d.ref_k[r] = (int32_t)k;
+      } else {
+        atomicAdd(&d.flag_cnt[k / kScanBlock], 1);
+      }
+    }
+  }
+  if constexpr (APPEND) {
+    // the blocks that own work waves (block 0 always) take a ticket once
+    // done; every count increment of a block returned before its ticket is
+    // taken (the list position is used), so the last ticket's holder reads
+    // the whole count
+    constexpr int kWavesPerBlock = kWG / 64;
+    int owners = (nw + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (owners > (int)gridDim.x) owners = (int)gridDim.x;
+    if (owners < 1) owners = 1;
+    if ((int)blockIdx.x >= owners) return;
+    __shared__ int s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(&d.sync[1], 1) == owners - 1;
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+      const int total = atomicAdd(&d.sync[0], 0);
+      atomicExch(&d.sync[0], 0);     // both words start at zero for the next pass
+      atomicExch(&d.sync[1], 0);
+      d.blk_off[d.nblk] = total;
+      d.ref_off[0] = 0;
+      d.ref_off[1] = total;
+      d.ctr[kCtrRefined] += total;
+      plan_single(d, tu, plan_kind, 0, 0, total);
+    }
   }
 }
 
@@ -2487,12 +2510,32 @@ __global__ __launch_bounds__(kWG) void k_rscatter(Dev d, const int32_t *list,
   }
 }
 
-// Write the FP64 re-evaluations over the mixed sums of their entries (one
-// wave per re-evaluated entry).
-__global__ __launch_bounds__(kWG) void k_ref_final(Dev d) {
+// Write the FP64 re-evaluations over the mixed sums of their entries: one
+// wave per re-evaluated entry, in blocks [0, ref_blocks).  CORR (block
+// steps): that wave also corrects its particle, and blocks [ref_blocks,
+// gridDim.x) correct every other active entry from fsum, one thread each —
+// the whole corrector in this launch, after the FP64 pass (which predicts
+// from the state) has finished.
+template <bool CORR, bool FIELD>
+__global__ __launch_bounds__(kWG) void k_ref_final(Dev d, int ref_blocks, CorrectSpec cs) {
+  if constexpr (CORR) {
+    if ((int)blockIdx.x >= ref_blocks) {
+      const int na = d.act_off[d.C];
+      const int stride = ((int)gridDim.x - ref_blocks) * kWG;
+      for (int k = ((int)blockIdx.x - ref_blocks) * kWG + threadIdx.x; k < na; k += stride) {
+        if (d.rflag[k]) continue;           // corrected by its wave below
+        const int64_t i = d.active[k];
+        double f[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) f[q] = d.fsum[6 * (int64_t)k + q];
+        correct_one<FIELD>(d, i, d.cid[i], f, cs.eta, cs.dt_shared, cs.lmin, cs.lmax);
+      }
+      return;
+    }
+  }
   const int total = d.ref_off[d.C];
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  const int nwaves = (ref_blocks * kWG) >> 6;
   for (int r = wave; r < total; r += nwaves) {
     int c = 0;
     if (d.C > 1) {   // largest c with ref_off[c] <= r
@@ -2510,6 +2553,8 @@ __global__ __launch_bounds__(kWG) void k_ref_final(Dev d) {
       const int64_t k = d.ref_k[r];
 #pragma unroll
       for (int q = 0; q < 6; ++q) d.fsum[6 * k + q] = f[q];
+      if constexpr (CORR)
+        correct_one<FIELD>(d, d.ref_i[r], c, f, cs.eta, cs.dt_shared, cs.lmin, cs.lmax);
     }
   }
 }
@@ -2701,7 +2746,7 @@ hipError_t launch_compact(const Dev &d, const Tuning &t, bool allow_small, int r
   const int al = allow_small ? 1 : 0, sb = allow_sb ? 1 : 0, so = sb_only ? 1 : 0;
   if (d.nblk <= kFusedScan) {
     const int pk = plan_fused(d) ? (int)kPlanStep : -1;
-    if (rec_mode >= 0 && !(plan_fused(d) && d.n <= kRecInCompactMax))
+    if (rec_mode >= 0 && !plan_fused(d))
       return hipErrorInvalidValue;
     if (rec_mode == kModeFP64)
       hipLaunchKernelGGL((k_scatter<true, kModeFP64>), dim3(d.nblk), dim3(kWG), 0, s, d, t, pk,
@@ -2942,13 +2987,23 @@ int force_sb_grid_size(int mode, int K, int device) {
 
 hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_host,
                                float refine_ratio, const NearSpec &nr, bool theta_out,
-                               const Tuning &t1, int ref_kind, int64_t api_nj, hipStream_t s) {
+                               const Tuning &t1, int ref_kind, int64_t api_nj, bool append,
+                               hipStream_t s) {
   const int64_t cap = na_host >= 0 ? na_host : d.cap_active;
   // at most one wave per entry, grid-stride
-  hipLaunchKernelGGL(k_sum_flag, dim3(grid_for(cap * 64, kWG, 4096)), dim3(kWG),
-                     prefix_lds_bytes(d.C), s, d, list, refine_ratio, nr.c, nr.src,
-                     theta_out ? 1 : 0);
-  if (refine_ratio > 0.0f && !theta_out) {
+  const dim3 g(grid_for(cap * 64, kWG, 4096)), b(kWG);
+  const size_t lds = prefix_lds_bytes(d.C);
+  const int th = theta_out ? 1 : 0;
+  // one cluster with a fused plan (block steps): the flagged entries are
+  // appended and planned by the sum launch itself
+  const bool app = append && plan_fused(d) && refine_ratio > 0.0f && !theta_out;
+  if (app)
+    hipLaunchKernelGGL(k_sum_flag<true>, g, b, lds, s, d, list, refine_ratio, nr.c, nr.src, th,
+                       t1, ref_kind);
+  else
+    hipLaunchKernelGGL(k_sum_flag<false>, g, b, lds, s, d, list, refine_ratio, nr.c, nr.src, th,
+                       t1, ref_kind);
+  if (refine_ratio > 0.0f && !theta_out && !app) {
     if (d.nblk <= kFusedScan) {
       hipLaunchKernelGGL(k_rscatter<true>, dim3(d.nblk), dim3(kWG), 0, s, d, list, na_host, t1,
                          plan_fused(d) ? ref_kind : -1, api_nj);
@@ -2961,30 +3016,31 @@ hipError_t launch_sum_and_flag(const Dev &d, const int32_t *list, int64_t na_hos
   return hipGetLastError();
 }
 
-hipError_t launch_refine_finalize(const Dev &d, hipStream_t s) {
-  hipLaunchKernelGGL(k_ref_final, dim3(grid_for(d.cap_active * 64, kWG, 512)), dim3(kWG),
-                     0, s, d);
+hipError_t launch_refine_finalize(const Dev &d, const CorrectSpec *corr, hipStream_t s) {
+  const int rb = grid_for(d.cap_active * 64, kWG, 512);
+  const dim3 b(kWG);
+  const CorrectSpec cs = corr ? *corr : CorrectSpec{};
+  // the corrector's blocks: one thread per active entry
+  const int cb = corr ? grid_for(d.cap_active, kWG, 2048) : 0;
+  if (!corr)
+    hipLaunchKernelGGL((k_ref_final<false, false>), dim3(rb), b, 0, s, d, rb, cs);
+  else if (d.fld.on)
+    hipLaunchKernelGGL((k_ref_final<true, true>), dim3(rb + cb), b, 0, s, d, rb, cs);
+  else
+    hipLaunchKernelGGL((k_ref_final<true, false>), dim3(rb + cb), b, 0, s, d, rb, cs);
   return hipGetLastError();
 }
 
 hipError_t launch_correct(const Dev &d, double eta, double dt_shared,
-                          int level_min, int level_max, int src, hipStream_t s) {
-  if (src == kCorrectGroups) {
-    const dim3 g(grid_for((int64_t)d.cap_active * 64, kWG, 4096)), b(kWG);
-    const size_t lds = prefix_lds_bytes(d.C);
-    if (d.fld.on)
-      hipLaunchKernelGGL(k_sum_correct<true>, g, b, lds, s, d, eta, dt_shared, level_min,
-                         level_max);
-    else
-      hipLaunchKernelGGL(k_sum_correct<false>, g, b, lds, s, d, eta, dt_shared, level_min,
-                         level_max);
-  } else if (d.fld.on) {
-    hipLaunchKernelGGL(k_correct<true>, dim3(grid_for(d.n, kWG, 2048)), dim3(kWG), 0, s,
-                       d, eta, dt_shared, level_min, level_max);
-  } else {
-    hipLaunchKernelGGL(k_correct<false>, dim3(grid_for(d.n, kWG, 2048)), dim3(kWG), 0, s,
-                       d, eta, dt_shared, level_min, level_max);
-  }
+                          int level_min, int level_max, hipStream_t s) {
+  const dim3 g(grid_for((int64_t)d.cap_active * 64, kWG, 4096)), b(kWG);
+  const size_t lds = prefix_lds_bytes(d.C);
+  if (d.fld.on)
+    hipLaunchKernelGGL(k_sum_correct<true>, g, b, lds, s, d, eta, dt_shared, level_min,
+                       level_max);
+  else
+    hipLaunchKernelGGL(k_sum_correct<false>, g, b, lds, s, d, eta, dt_shared, level_min,
+                       level_max);
   return hipGetLastError();
 }
 
