@@ -324,13 +324,28 @@ int refresh_grids(nbody_ctx *c) {
   c->sba = (va == NBODY_VARIANT_S1 || va == NBODY_VARIANT_S2);
   // A mixed block step's records are always built, and the record kernel
   // hands the main items to the broadcast kernel when every cluster with
-  // main work has kWG i-slots.  With small steps routed to FP64, a cluster
-  // with main work has more than kSmallStep active particles, so when the
-  // i-slots of those buckets are all kWG the workgroup kernel's launch would
-  // only return: it is not enqueued.
+  // main work has kWG i-slots.  With small steps routed to FP64, only the
+  // buckets of active counts that some cluster does not route there can
+  // hold main work (more than kSmallStep active particles, and more than
+  // small_work interactions in the largest cluster); when the i-slots of
+  // those buckets are all kWG the workgroup kernel's launch would only
+  // return: it is not enqueued.
   c->step_sb_only = c->sb && is_mixed(c->prec) && c->tune.small_log2 >= 0;
-  for (int b = 31 - __builtin_clz((unsigned)nbk::kSmallStep + 1); b < nbk::kBuckets; ++b)
-    if (c->tune.i_slots[b] != nbk::kWG) c->step_sb_only = false;
+  if (c->step_sb_only) {
+    int64_t nmax = c->n;
+    if ((int64_t)c->coff.size() == (int64_t)c->C + 1) {
+      nmax = 0;
+      for (int k = 0; k < c->C; ++k) nmax = std::max(nmax, c->coff[k + 1] - c->coff[k]);
+    }
+    const int64_t sw = (int64_t)1 << c->tune.small_log2;
+    for (int b = 0; b < nbk::kBuckets; ++b) {
+      const int64_t lo = (int64_t)1 << b;
+      const int64_t hi = b + 1 < nbk::kBuckets ? 2 * lo - 1 : nmax;   // last bucket: the rest
+      if (lo > nmax) break;                          // no cluster that large
+      const bool all_small = hi <= nbk::kSmallStep || hi * nmax <= sw;
+      if (!all_small && c->tune.i_slots[b] != nbk::kWG) c->step_sb_only = false;
+    }
+  }
   c->grid_sb = c->sb ? nbk::force_sb_grid_size(mode_of(c), c->K, c->device) : 1;
   c->grid_acc_sb = c->sba ? nbk::force_sb_grid_size(acc_mode_of(c), c->Ka, c->device) : 1;
   c->grid_acc_state = nbk::force_grid_size(acc_mode_of(c), nbk::kSrcState, c->Ka, c->device);
