@@ -13,7 +13,12 @@ an ensemble spreads over every cluster, so its time is set by the longest
 work items, and narrower i-tiles than a single system of the same total N
 wants pay off.  The ensemble tuner starts from the single-system entry of
 the same size, caps the i-slots of the larger buckets, and times real block
-steps of a seeded ensemble of Plummer clusters for each cap.
+steps of a seeded ensemble of Plummer clusters for each cap; then it widens
+the i-tiles of the small buckets to their active counts (one work item per
+j-split then serves all of a cluster's active particles, so each j tile is
+predicted once for all of them, where the single-system entry spread a few
+active particles over many items of a far longer j range) and searches the
+smallest j-split.
 
 Every candidate computes the same sums in a different order, so tuning only
 changes rounding (the split-invariance GPU test bounds the difference).
@@ -234,8 +239,26 @@ def tune_ensemble(n_clusters: int, precision: int, n_min: int = 256, n_max: int 
     out = dict(base)
     out["i_slots"] = [min(s, best[1]) if b >= best[2] else s
                       for b, s in enumerate(base["i_slots"])]
+    # small buckets: i-slots 2^b for buckets 0 .. top (top = -1: as they
+    # are), and the smallest j-split
+    best_s = (best[0], -1, out["min_split_j"])
+    for top in (4, 7):
+        for msj in (256, 384, 512, 768):
+            tr = dict(out)
+            tr["i_slots"] = [min(1 << b, 256) if b <= top else s
+                             for b, s in enumerate(out["i_slots"])]
+            tr["min_split_j"] = msj
+            t = run(tr)
+            if verbose:
+                print(f"  small buckets 0..{top} covered, min split {msj}: {t:.3f} s", flush=True)
+            if t < best_s[0]:
+                best_s = (t, top, msj)
+    out["i_slots"] = [min(1 << b, 256) if b <= best_s[1] else s
+                      for b, s in enumerate(out["i_slots"])]
+    out["min_split_j"] = best_s[2]
     out["ensemble"] = {"clusters": n_clusters, "n_min": n_min, "n_max": n_max,
-                       "slot_cap": best[1], "from_bucket": best[2], "seconds": best[0]}
+                       "slot_cap": best[1], "from_bucket": best[2],
+                       "small_cover_to": best_s[1], "seconds": best_s[0]}
     out["measured"] = time.strftime("%Y-%m-%dT%H:%M:%S")
     if verbose:
         print(f"ensemble n={n}: i-slots <= {best[1]} from bucket {best[2]}, {best[0]:.3f} s",
