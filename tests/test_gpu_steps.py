@@ -119,15 +119,23 @@ def test_ensemble_equals_solo_bitwise(prec, small_log2):
         assert st["small_step_interactions"] == st["interactions"], st
     se = _state_np(e)
     energies = e.energy()
+    refined_solo = 0
     for c in range(4):
         sl = slice(off[c], off[c + 1])
         s = binding.NBody(m[sl], x[sl], v[sl], eps=eps[c], tuning=tune, **kw)
         s.step(0.125)
+        refined_solo += s.stats()["refined"]
         ss = _state_np(s)
         for k in ("x", "v", "a", "j", "tick", "level"):
             assert np.array_equal(se[k][sl], ss[k]), (c, k)
         es = s.energy()[0]
         assert np.allclose(energies[c], es, rtol=0, atol=1e-15)
+    if small_log2 < 0:
+        # the FP64 re-evaluation ran, and a cluster alone (whose flagged
+        # entries are appended in any order) re-evaluates exactly the
+        # particles it re-evaluates inside the ensemble (ordered list)
+        assert st["refined"] > 0, st
+        assert refined_solo == st["refined"], (refined_solo, st["refined"])
 
 
 def test_checkpoint_resume_bitwise():
