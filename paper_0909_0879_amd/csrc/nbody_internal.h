@@ -216,11 +216,10 @@ hipError_t launch_all_active(const Dev &d, const Tuning &t, hipStream_t s);
 bool plan_fused(const Dev &d);
 // Scheduler (per-cluster T_next and threshold level) and ordered compaction
 // of the due particles into the active list (plan: see plan_fused).
-// rec_mode >= 0 (a force mode; one cluster with plan_fused): the
-// compaction also writes every particle's
-// j record predicted to T_next and the record flag (allow_sb, sb_only as in
-// launch_records), so no launch_records follows; -1: records are left to
-// launch_records.
+// rec_mode >= 0 (a force mode; one cluster with plan_fused): the compaction
+// also writes every particle's j record predicted to T_next and the record
+// flag (allow_sb, sb_only as in launch_records), so no launch_records
+// follows; -1: records are left to launch_records.
 hipError_t launch_compact(const Dev &d, const Tuning &t, bool allow_small, int rec_mode,
                           bool allow_sb, bool sb_only, hipStream_t s);
 // allow_small: clusters of a small block step (at most kSmallStep active
@@ -229,6 +228,11 @@ hipError_t launch_compact(const Dev &d, const Tuning &t, bool allow_small, int r
 // writes the per-cluster offsets of the re-evaluation list (ref_off).
 hipError_t launch_plan(const Dev &d, const Tuning &t, int kind,
                        int64_t api_nj, bool allow_small, hipStream_t s);
+// Hermite corrector parameters of a block step.
+struct CorrectSpec {
+  double eta, dt_shared;
+  int lmin, lmax;
+};
 // Sum each active entry's partial rows into fsum.  theta_out (first pass of
 // a two-pass mixed evaluation): store each entry's near-pair threshold
 // nr.c |jerk| in d.theta.  Otherwise, with refine_ratio > 0, flag the entries
@@ -236,11 +240,6 @@ hipError_t launch_plan(const Dev &d, const Tuning &t, int kind,
 // acceleration or whose near-pair threshold came from a jerk estimate above
 // kNearStale times their jerk (nr.src), and build the grouped re-evaluation
 // list.
-// Hermite corrector parameters of a block step.
-struct CorrectSpec {
-  double eta, dt_shared;
-  int lmin, lmax;
-};
 // append (block steps): with one cluster and a fused plan, the flagged
 // entries are appended to the list in any order and the sum launch writes
 // the re-evaluation plan (no k_rscatter).
