@@ -2365,8 +2365,8 @@ __global__ void k_sym_advance(Dev d, int64_t dticks) {
 // (k_rscatter).  APPEND (one cluster): the flagged entries go to the
 // re-evaluation list through one atomic counter, in whatever order they
 // come (each entry's FP64 sums do not depend on its place in the list), and
-// the last block to finish publishes the count and writes the re-evaluation
-// plan (plan_kind), in place of k_rscatter.
+// the last of the blocks that own work waves to finish publishes the count
+// and writes the re-evaluation plan (plan_kind), in place of k_rscatter.
 template <bool APPEND>
 __global__ __launch_bounds__(kWG) void k_sum_flag(Dev d, const int32_t *list, float ratio,
                                                   float near_c, int near_src, int theta_out,
