@@ -136,8 +136,30 @@ struct JRecDS {          // one j-particle for the double-single mode, 64 bytes:
   float vlx, vly, vlz, pad1;
 };
 
+// One j-particle for the mixed mode with FP64 position differences, 64
+// bytes: the FP64 position, the velocity relative to the cluster's
+// reference velocity (that of the first particle of its j range) rounded to
+// FP32, the mass in units of the reference mass.  The FP32 velocity
+// difference (v_j - v_ref) - (v_i - v_ref), with the i side held as an exact
+// (hi, lo) pair, carries only the rounding of v_j - v_ref, which differs
+// from j to j (it does not add up coherently over the sum); the pairs whose
+// jerk term matters at that level are near pairs, taken in FP64.
+struct JRecV {
+  double x, y, z;
+  float vx, vy, vz;
+  float mf;
+  int32_t idx;
+  int32_t pad[5];
+};
+static_assert(sizeof(JRecV) == 64, "one 64-byte record");
+
 struct I64 {             // an i-particle in registers, FP64 modes
   double x[3], v[3];
+};
+
+struct IV {              // an i-particle in registers for JRecV: FP64 position,
+  double x[3];           // velocity relative to the cluster's reference as a
+  float vh[3], vl[3];    // (hi, lo) FP32 pair
 };
 
 struct IDS {             // an i-particle in registers, mixed mode: position
@@ -149,6 +171,25 @@ __device__ __forceinline__ void make_i(const double *xp, const double *vp, I64 &
   for (int c = 0; c < 3; ++c) {
     s.x[c] = xp[c];
     s.v[c] = vp[c];
+  }
+}
+
+// vref: the cluster's reference velocity (JRecV form only; the other forms
+// take the velocity as it is)
+__device__ __forceinline__ void make_i(const double *xp, const double *vp, I64 &s,
+                                       const double *vref) {
+  (void)vref;
+  make_i(xp, vp, s);
+}
+
+__device__ __forceinline__ void make_i(const double *xp, const double *vp, IV &s,
+                                       const double *vref) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    s.x[c] = xp[c];
+    const double w = vp[c] - vref[c];
+    s.vh[c] = (float)w;
+    s.vl[c] = (float)(w - (double)s.vh[c]);
   }
 }
 
@@ -164,6 +205,12 @@ __device__ __forceinline__ void make_i(const double *xp, const double *vp, IDS &
   }
 }
 
+__device__ __forceinline__ void make_i(const double *xp, const double *vp, IDS &s,
+                                       const double *vref) {
+  (void)vref;
+  make_i(xp, vp, s);
+}
+
 // Reference mass of a cluster's FP32 sums: the mass of the first particle of
 // its j range (1 if that is zero).  The FP32 pair terms take m_j / m_ref, so
 // equal masses enter them as exactly 1 and the rounding of a mass such as
@@ -172,8 +219,11 @@ __device__ __forceinline__ void make_i(const double *xp, const double *vp, IDS &
 __device__ __forceinline__ double mass_ref(double m0) { return m0 != 0.0 ? m0 : 1.0; }
 
 // FP64 records keep m exact (FP64 and potential modes) and m / m_ref in FP32.
+// vref: the cluster's reference velocity, used by the JRecV form only.
 __device__ __forceinline__ void make_rec(const double *xp, const double *vp, double m,
-                                         int32_t idx, JRec64 &r, double mref) {
+                                         int32_t idx, JRec64 &r, double mref,
+                                         const double *vref) {
+  (void)vref;
   r.x = xp[0]; r.y = xp[1]; r.z = xp[2]; r.m = m;
   r.vx = vp[0]; r.vy = vp[1]; r.vz = vp[2];
   r.mf = (float)(m / mref);
@@ -181,7 +231,9 @@ __device__ __forceinline__ void make_rec(const double *xp, const double *vp, dou
 }
 
 __device__ __forceinline__ void make_rec(const double *xp, const double *vp, double m,
-                                         int32_t idx, JRecDS &r, double mref) {
+                                         int32_t idx, JRecDS &r, double mref,
+                                         const double *vref) {
+  (void)vref;
   IDS s;
   make_i(xp, vp, s);
   r.xh = s.xh[0]; r.yh = s.xh[1]; r.zh = s.xh[2];
@@ -191,6 +243,19 @@ __device__ __forceinline__ void make_rec(const double *xp, const double *vp, dou
   r.m = (float)(m / mref);
   r.pad0 = r.pad1 = 0.0f;
   r.idx = idx;
+}
+
+__device__ __forceinline__ void make_rec(const double *xp, const double *vp, double m,
+                                         int32_t idx, JRecV &r, double mref,
+                                         const double *vref) {
+  r.x = xp[0]; r.y = xp[1]; r.z = xp[2];
+  r.vx = (float)(vp[0] - vref[0]);
+  r.vy = (float)(vp[1] - vref[1]);
+  r.vz = (float)(vp[2] - vref[2]);
+  r.mf = (float)(m / mref);
+  r.idx = idx;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) r.pad[q] = 0;
 }
 
 // ------------------------------------------------------------ pair terms
@@ -362,17 +427,19 @@ __device__ __forceinline__ uint64_t pair_mixed_acc(const IDS &I, int iidx, const
   return 0;
 }
 
-// Mixed precision with FP64 differences: x_j - x_i and v_j - v_i are taken
-// in FP64 from the FP64 records and rounded to FP32; everything after them is
-// the FP32 arithmetic of pair_mixed.
+// Mixed precision with FP64 position differences: x_j - x_i is taken in
+// FP64 and rounded to FP32; v_j - v_i is (v_j - v_ref) - hi_i - lo_i in FP32
+// (JRecV); everything after them is the FP32 arithmetic of pair_mixed.
+// SELF: the i-particle's own slot has w = -lo_i rather than zero, so its
+// terms are dropped (exactly zero in FP64).
 template <bool MASK, bool SELF>
-__device__ __forceinline__ uint64_t pair_mixed64(const I64 &I, int iidx, const JRec64 &r,
+__device__ __forceinline__ uint64_t pair_mixed64(const IV &I, int iidx, const JRecV &r,
                                              float eps2, float th, float *t, int &dom,
                                              Bnd &ba) {
   const float dx = (float)(r.x - I.x[0]), dy = (float)(r.y - I.x[1]),
               dz = (float)(r.z - I.x[2]);
-  const float wx = (float)(r.vx - I.v[0]), wy = (float)(r.vy - I.v[1]),
-              wz = (float)(r.vz - I.v[2]);
+  const float wx = (r.vx - I.vh[0]) - I.vl[0], wy = (r.vy - I.vh[1]) - I.vl[1],
+              wz = (r.vz - I.vh[2]) - I.vl[2];
   const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
   const float rv = fmaf(dx, wx, fmaf(dy, wy, dz * wz));
   float r0 = __builtin_amdgcn_rsqf(s);
@@ -384,9 +451,10 @@ __device__ __forceinline__ uint64_t pair_mixed64(const I64 &I, int iidx, const J
   }
   const Fac32 f = fac32(s, r.mf, r0);
   const float al = (3.0f * rv) * f.rinv2;
-  ba.a = fmaxf(ba.a, (SELF && r.idx == iidx) ? 0.0f : f.mq);
+  const bool self = SELF && r.idx == iidx;
+  ba.a = fmaxf(ba.a, self ? 0.0f : f.mq);
   float mr3, wm;
-  const uint64_t nr = near_pair(f.mr3, wx, wy, wz, th, mr3, wm);
+  const uint64_t nr = near_pair(self ? 0.0f : f.mr3, wx, wy, wz, th, mr3, wm);
   t[0] = fmaf(mr3, dx, t[0]);
   t[1] = fmaf(mr3, dy, t[1]);
   t[2] = fmaf(mr3, dz, t[2]);
@@ -397,7 +465,7 @@ __device__ __forceinline__ uint64_t pair_mixed64(const I64 &I, int iidx, const J
 }
 
 template <bool MASK, bool SELF>
-__device__ __forceinline__ uint64_t pair_mixed64_acc(const I64 &I, int iidx, const JRec64 &r,
+__device__ __forceinline__ uint64_t pair_mixed64_acc(const IV &I, int iidx, const JRecV &r,
                                                  float eps2, float th, float *t, int &dom,
                                                  Bnd &ba) {
   const float dx = (float)(r.x - I.x[0]), dy = (float)(r.y - I.x[1]),
@@ -487,15 +555,15 @@ template <> struct Traits<kModeMixedAcc> {
 };
 template <> struct Traits<kModeMixed64> {
   using T = float;
-  using Rec = JRec64;
-  using Ist = I64;
+  using Rec = JRecV;
+  using Ist = IV;
   static constexpr int NC = 6;
   static constexpr int FOLD = 64;
 };
 template <> struct Traits<kModeMixed64Acc> {
   using T = float;
-  using Rec = JRec64;
-  using Ist = I64;
+  using Rec = JRecV;
+  using Ist = IV;
   static constexpr int NC = 3;
   static constexpr int FOLD = 64;
 };
@@ -523,6 +591,9 @@ __device__ __forceinline__ void fold(typename Traits<MODE>::T (&t)[K][Traits<MOD
 
 // Modes whose FP32 pairs may hand near pairs to FP64 (acceleration and jerk).
 constexpr bool mode_near(int m) { return m == kModeMixed || m == kModeMixed64; }
+// Modes whose records hold velocities relative to the cluster's reference
+// velocity (JRecV).
+constexpr bool mode_relv(int m) { return m == kModeMixed64 || m == kModeMixed64Acc; }
 
 // One j record against the K i-particles of a lane; nr[k] is the wave's lane
 // mask of near pairs with i-particle k (left out of the FP32 sums, see
@@ -712,7 +783,7 @@ __device__ __forceinline__ void near_drain(const ForceArgs &A, const ClusterPlan
         double xj[3], vj[3], mj;
         near_state(A, cp, j, raw, xj, vj, mj);
         JRec64 r;
-        make_rec(xj, vj, mj / mref, j, r, 1.0);   // in the FP32 sums' mass unit
+        make_rec(xj, vj, mj / mref, j, r, 1.0, nullptr);   // in the FP32 sums' mass unit
         near_fp64(ip, r, eps2, hi[k], lo[k]);
       }
     }
@@ -729,6 +800,40 @@ __device__ __forceinline__ void rec_to_i(const JRecDS &r, IDS &s) {
   s.xl[0] = r.xl; s.xl[1] = r.yl; s.xl[2] = r.zl;
   s.v[0] = r.vx; s.v[1] = r.vy; s.v[2] = r.vz;
   s.vl[0] = r.vlx; s.vl[1] = r.vly; s.vl[2] = r.vlz;
+}
+
+// The cluster's reference velocity of the JRecV form: that of the first
+// particle of the plan's j range, predicted to the plan's time (or the
+// caller's), as the record builders take it; zero where no velocity is read
+// (acceleration only) or the form has none.
+template <int MODE>
+__device__ __forceinline__ void ref_velocity(const ForceArgs &A, const ClusterPlan &cp, bool raw,
+                                             double vref[3]) {
+  vref[0] = vref[1] = vref[2] = 0.0;
+  if constexpr (mode_relv(MODE) && !mode_acc_only(MODE)) {
+    double x0[3], m0;
+    near_state(A, cp, (int)cp.jb, raw, x0, vref, m0);
+  }
+}
+
+// An i-particle from the evaluation's records.  The JRecV form takes the
+// position from the record and the velocity from the FP64 source (the
+// record holds it to FP32 only).
+template <int MODE>
+__device__ __forceinline__ void i_from_rec(const ForceArgs &A, const ClusterPlan &cp, bool raw,
+                                           const typename Traits<MODE>::Rec &r, int i,
+                                           const double *vref, typename Traits<MODE>::Ist &s) {
+  if constexpr (mode_relv(MODE)) {
+    const double xr[3] = {r.x, r.y, r.z};
+    double v[3] = {0.0, 0.0, 0.0};
+    if constexpr (!mode_acc_only(MODE)) {
+      double xs[3], ms;
+      near_state(A, cp, i, raw, xs, v, ms);
+    }
+    make_i(xr, v, s, vref);
+  } else {
+    rec_to_i(r, s);
+  }
 }
 
 // ------------------------------------------------------------ force kernel
@@ -838,6 +943,8 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
     // FP32 sums in units of the cluster's reference mass (mixed modes)
     const double mref = !mode_mixed(MODE) ? 1.0
                         : mass_ref(SRC == kSrcRaw ? A.rm[cp.jb] : d.m[cp.jb]);
+    double vref[3];
+    ref_velocity<MODE>(A, cp, SRC == kSrcRaw, vref);
 
     typename Tr::Ist I[K];
     int iidx[K], dom[K];
@@ -861,7 +968,7 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
       if (!ok[k]) {
         iidx[k] = -1;
       } else if (use_pred) {
-        rec_to_i(pred[iidx[k]], I[k]);
+        i_from_rec<MODE>(A, cp, SRC == kSrcRaw, pred[iidx[k]], iidx[k], vref, I[k]);
         continue;
       } else if constexpr (SRC == kSrcState) {
         predict_state(d, iidx[k], cp.t_pred, xp, vp);
@@ -872,7 +979,7 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
           vp[c] = mode_acc_only(MODE) ? 0.0 : A.rv[3 * (int64_t)iidx[k] + c];
         }
       }
-      make_i(xp, vp, I[k]);
+      make_i(xp, vp, I[k], vref);
     }
     T t[K][NC], shi[K][NC], slo[K][NC];
     Bnd ba[K];
@@ -905,7 +1012,7 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
           m = A.rm[j];
         }
         Rec r;
-        make_rec(xp, vp, m, (int32_t)j, r, mref);
+        make_rec(xp, vp, m, (int32_t)j, r, mref, vref);
         tile[tid] = r;
       }
       // the tile barrier also tells whether any i of this workgroup lies in
@@ -1379,6 +1486,11 @@ __global__ __launch_bounds__(kWG) void k_scatter(Dev d, Tuning tu, int plan_kind
       Rec *pred = reinterpret_cast<Rec *>(d.pred);
       const double mref = mode_mixed(RMODE) ? mass_ref(d.m[0]) : 1.0;
       const int64_t t1 = d.Tnext[0];
+      double vref[3] = {0.0, 0.0, 0.0};     // the cluster's first particle's
+      if constexpr (mode_relv(RMODE)) {      // velocity (JRecV form)
+        double x0[3];
+        predict_state(d, 0, t1, x0, vref);
+      }
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t i = (int64_t)blockIdx.x * kScanBlock + e * kWG + threadIdx.x;
@@ -1386,7 +1498,7 @@ __global__ __launch_bounds__(kWG) void k_scatter(Dev d, Tuning tu, int plan_kind
           double xp[3], vp[3];
           predict_state(d, i, t1, xp, vp);
           Rec r;
-          make_rec(xp, vp, d.m[i], (int32_t)i, r, mref);
+          make_rec(xp, vp, d.m[i], (int32_t)i, r, mref, vref);
           pred[i] = r;
         }
       }
@@ -2020,7 +2132,9 @@ __global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, in
   Rec *pred = reinterpret_cast<Rec *>(d.pred);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nj;
        i += (int64_t)gridDim.x * blockDim.x) {
-    double xp[3], vp[3], m, m0;
+    // vref: the velocity of the first particle of the cluster's j range
+    // (JRecV form), taken as the force kernels take it
+    double xp[3], vp[3], m, m0, vref[3] = {0.0, 0.0, 0.0};
     if (api) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -2028,17 +2142,27 @@ __global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, in
         vp[c] = raw.v ? raw.v[3 * i + c] : 0.0;
       }
       m = raw.m[i];
-      m0 = raw.m[d.C == 1 ? 0 : d.coff[d.cid[i]]];
+      const int64_t j0 = d.C == 1 ? 0 : d.coff[d.cid[i]];
+      m0 = raw.m[j0];
+      if constexpr (mode_relv(MODE)) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vref[c] = raw.v ? raw.v[3 * j0 + c] : 0.0;
+      }
     } else {
       const int c = d.cid[i];
       if (kind == kPlanStep && (d.Lthr[c] == kNoActive || d.plan_c[c].small))
         continue;                   // not stepping, or evaluated by the FP64 launch
-      predict_state(d, i, kind == kPlanStep ? d.Tnext[c] : d.T[c], xp, vp);
+      const int64_t t = kind == kPlanStep ? d.Tnext[c] : d.T[c];
+      predict_state(d, i, t, xp, vp);
       m = d.m[i];
       m0 = d.m[d.coff[c]];
+      if constexpr (mode_relv(MODE)) {
+        double x0[3];
+        predict_state(d, d.coff[c], t, x0, vref);
+      }
     }
     Rec r;
-    make_rec(xp, vp, m, (int32_t)i, r, mode_mixed(MODE) ? mass_ref(m0) : 1.0);
+    make_rec(xp, vp, m, (int32_t)i, r, mode_mixed(MODE) ? mass_ref(m0) : 1.0, vref);
     pred[i] = r;
   }
 }
@@ -2072,6 +2196,16 @@ __device__ __forceinline__ JRec64 load_rec(ScalarPtr<JRec64> p) {
   r.x = p->x; r.y = p->y; r.z = p->z; r.m = p->m;
   r.vx = p->vx; r.vy = p->vy; r.vz = p->vz;
   r.mf = p->mf; r.idx = p->idx;
+  return r;
+}
+
+__device__ __forceinline__ JRecV load_rec(ScalarPtr<JRecV> p) {
+  JRecV r;
+  r.x = p->x; r.y = p->y; r.z = p->z;
+  r.vx = p->vx; r.vy = p->vy; r.vz = p->vz;
+  r.mf = p->mf; r.idx = p->idx;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) r.pad[q] = 0;
   return r;
 }
 
@@ -2120,17 +2254,40 @@ __device__ __forceinline__ void sb_run(
     int (&dom)[K], Bnd (&ba)[K], int (&ncnt)[K], NearQueue<MODE, K> &nq) {
   using Rec = typename Traits<MODE>::Rec;
   int jj = 0;
-  for (; jj + 4 <= cnt; jj += 4) {
-    Rec r[4];
-    uint64_t nr[4][K];
-    int ji[4];
-    load4(rec + jj, r);
+  if constexpr (mode_relv(MODE)) {
+    // JRecV (11 of its 16 dwords live): each group's first record is loaded
+    // one group early, so the group starts without waiting on the scalar
+    // cache; the prefetch address stays inside the chunk
+    Rec first = load_rec(rec + 0);
+    for (; jj + 4 <= cnt; jj += 4) {
+      Rec r[4];
+      uint64_t nr[4][K];
+      int ji[4];
+      r[0] = first;
+      r[1] = load_rec(rec + jj + 1);
+      r[2] = load_rec(rec + jj + 2);
+      r[3] = load_rec(rec + jj + 3);
+      first = load_rec(rec + ((jj + 4 < cnt) ? jj + 4 : cnt - 1));
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      pair_k<MODE, K, MASK, SELF>(r[u], I, iidx, eps2, th, t, dom, ba, nr[u]);
-      ji[u] = r[u].idx;
+      for (int u = 0; u < 4; ++u) {
+        pair_k<MODE, K, MASK, SELF>(r[u], I, iidx, eps2, th, t, dom, ba, nr[u]);
+        ji[u] = r[u].idx;
+      }
+      near_push<MODE, K, 4>(nr, ji, ncnt, nq);
     }
-    near_push<MODE, K, 4>(nr, ji, ncnt, nq);
+  } else {
+    for (; jj + 4 <= cnt; jj += 4) {
+      Rec r[4];
+      uint64_t nr[4][K];
+      int ji[4];
+      load4(rec + jj, r);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        pair_k<MODE, K, MASK, SELF>(r[u], I, iidx, eps2, th, t, dom, ba, nr[u]);
+        ji[u] = r[u].idx;
+      }
+      near_push<MODE, K, 4>(nr, ji, ncnt, nq);
+    }
   }
   for (; jj < cnt; ++jj) {
     const Rec r = load_rec(rec + jj);
@@ -2186,6 +2343,8 @@ __attribute__((amdgpu_waves_per_eu(SbOcc<MODE, K>::waves))) void k_force_sb(Forc
     const int64_t je = (js + cp.chunk < cp.je) ? js + cp.chunk : cp.je;
     const double eps2 = d.eps2[cp.c];
     const double mref = !mode_mixed(MODE) ? 1.0 : mass_ref(raw ? A.rm[cp.jb] : d.m[cp.jb]);
+    double vref[3];
+    ref_velocity<MODE>(A, cp, raw, vref);
 
     typename Tr::Ist I[K];
     int iidx[K], dom[K];
@@ -2206,11 +2365,11 @@ __attribute__((amdgpu_waves_per_eu(SbOcc<MODE, K>::waves))) void k_force_sb(Forc
                   ? (float)(near_threshold(A, cp.act_off + slot, iidx[k]) / mref)
                   : INFINITY;
       if (ok[k]) {
-        rec_to_i(pred[iidx[k]], I[k]);
+        i_from_rec<MODE>(A, cp, raw, pred[iidx[k]], iidx[k], vref, I[k]);
       } else {
         iidx[k] = -1;
         const double z[3] = {0.0, 0.0, 0.0};
-        make_i(z, z, I[k]);
+        make_i(z, z, I[k], vref);
       }
     }
     T t[K][NC], shi[K][NC], slo[K][NC];
