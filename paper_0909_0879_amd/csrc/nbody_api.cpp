@@ -96,6 +96,7 @@ size_t carve(int64_t n, int32_t C, char *base, Dev *d, int rows_per_j = nbk::kRo
   t.work = (int32_t *)take(sizeof(int32_t) * 4);
   t.err = (int32_t *)take(sizeof(int32_t) * 4);
   t.sync = (int32_t *)take(sizeof(int32_t) * 4);
+  t.vref = (double *)take(sizeof(double) * 3 * C);
   t.ctr = (int64_t *)take(sizeof(int64_t) * nbk::kCtrCount);
   t.eout = (double *)take(sizeof(double) * 9 * C);
   if (d) *d = t;
@@ -579,6 +580,7 @@ int take_error(nbody_ctx *c) {
 int full_evaluation_into_state(nbody_ctx *c) {
   // initial forces: every particle active, predicted to its own time
   const nbk::Tuning t = device_tuning(c, c->K);
+  if (c->prec == NBODY_MIXED) NB_HIP(nbk::launch_vref(c->d, nullptr, c->stream));
   NB_HIP(nbk::launch_all_active(c->d, t, c->stream));
   if (c->C > 1) NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanState, 0, false, c->stream));
   // all particles start at T = T_next = 0, so the re-evaluation plan
@@ -638,6 +640,7 @@ int api_forces(nbody_ctx *c, bool acc_only, const int32_t *i_active, int64_t n_a
     r.acc = acc + 3 * k0;
     r.jerk = jerk ? jerk + 3 * k0 : nullptr;
     NB_HIP(nbk::launch_api_group(c->d, r, t, c->stream));
+    if (c->prec == NBODY_MIXED && !acc_only) NB_HIP(nbk::launch_vref(c->d, &r, c->stream));
     if (c->C > 1) NB_HIP(nbk::launch_plan(c->d, t, nbk::kPlanApi, r.n_j, false, c->stream));
     int rc = two_pass(c, r.i_active, r.n_active, &r, c->stream, mode, [&](nbk::NearSpec nr) {
       return force_launch(c, mode, nbk::kSrcRaw, K, &r, r.i_active, grid, c->stream,
@@ -866,6 +869,8 @@ int nbody_step(nbody_ctx *c, double t_end, int64_t *n_block_steps, int64_t *n_in
   int64_t launches = 0;
   const int64_t max_launches = remaining / (c->tune.steps_per_launch > 0 ? c->tune.steps_per_launch : 1) + 2;
   while (remaining > 0) {
+    // the records' reference velocities follow the clusters' bulk motion
+    if (c->prec == NBODY_MIXED) NB_HIP(nbk::launch_vref(c->d, nullptr, c->stream));
     if (c->tune.use_graph == NBODY_GRAPH_ON && !c->profiling) {
       if ((rc = ensure_graph(c))) return rc;
       NB_HIP(hipGraphLaunch(c->gexec, c->stream));
@@ -897,6 +902,7 @@ int nbody_step_blocks(nbody_ctx *c, double t_end, int64_t max_block_steps,
   const int64_t steps0 = c->pinned[nbk::kCtrSteps], inter0 = c->pinned[nbk::kCtrInter];
   NB_HIP(nbk::launch_set_word64(c->d.ctr + nbk::kCtrTend, tend, c->stream));
   for (int64_t k = 0; k < max_block_steps; ++k) {
+    if ((k & 63) == 0 && c->prec == NBODY_MIXED) NB_HIP(nbk::launch_vref(c->d, nullptr, c->stream));
     if ((rc = enqueue_block_step(c, c->stream))) return rc;
     if ((k & 63) == 63 || k + 1 == max_block_steps) {
       if ((rc = readback(c))) return rc;

@@ -151,6 +151,8 @@ struct Dev {
   // words
   int32_t *work;       // [0] main item counter, [1] small-step item counter,
                        // [2] number of main items (written by k_plan)
+  double *vref;        // 3 * C: each cluster's reference velocity of the
+                       // FP64-difference mixed records (k_vref)
   int32_t *sync;       // [0] flagged-entry count, [1] finished blocks of an
                        // appending k_sum_flag (both zero between launches)
   int32_t *err;        // sticky error bits
@@ -284,6 +286,10 @@ hipError_t launch_sym_kick_drift(const Dev &d, double ck, double cd, bool check,
                                  const Tuning &t, hipStream_t s);
 hipError_t launch_sym_kick(const Dev &d, double ck, hipStream_t s);
 hipError_t launch_sym_advance(const Dev &d, int64_t dticks, hipStream_t s);
+// Each cluster's reference velocity for the FP64-difference mixed records
+// (the mass-weighted mean velocity of a strided sample of the cluster), from
+// the state, or from a caller's arrays (raw, which must carry velocities).
+hipError_t launch_vref(const Dev &d, const RawSrc *raw, hipStream_t s);
 // Row sums of the step plan's partial rows and the corrector in one launch
 // (block steps without a re-evaluation pass; with one, the re-evaluation's
 // launch_refine_finalize corrects).

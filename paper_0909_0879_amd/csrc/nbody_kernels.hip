@@ -138,8 +138,10 @@ struct JRecDS {          // one j-particle for the double-single mode, 64 bytes:
 
 // One j-particle for the mixed mode with FP64 position differences, 64
 // bytes: the FP64 position, the velocity relative to the cluster's
-// reference velocity (that of the first particle of its j range) rounded to
-// FP32, the mass in units of the reference mass.  The FP32 velocity
+// reference velocity rounded to FP32, the mass in units of the reference
+// mass.  The reference is the mass-weighted mean velocity of a strided
+// sample of the cluster (k_vref: refreshed between block-step launches for
+// the state, taken from a caller's arrays before an evaluation of them).  The FP32 velocity
 // difference (v_j - v_ref) - (v_i - v_ref), with the i side held as an exact
 // (hi, lo) pair, carries only the rounding of v_j - v_ref, which differs
 // from j to j (it does not add up coherently over the sum); the pairs whose
@@ -802,17 +804,17 @@ __device__ __forceinline__ void rec_to_i(const JRecDS &r, IDS &s) {
   s.vl[0] = r.vlx; s.vl[1] = r.vly; s.vl[2] = r.vlz;
 }
 
-// The cluster's reference velocity of the JRecV form: that of the first
-// particle of the plan's j range, predicted to the plan's time (or the
-// caller's), as the record builders take it; zero where no velocity is read
+// The cluster's reference velocity of the JRecV form, as the record
+// builders take it (d.vref, from k_vref); zero where no velocity is read
 // (acceleration only) or the form has none.
 template <int MODE>
 __device__ __forceinline__ void ref_velocity(const ForceArgs &A, const ClusterPlan &cp, bool raw,
                                              double vref[3]) {
+  (void)raw;
   vref[0] = vref[1] = vref[2] = 0.0;
   if constexpr (mode_relv(MODE) && !mode_acc_only(MODE)) {
-    double x0[3], m0;
-    near_state(A, cp, (int)cp.jb, raw, x0, vref, m0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vref[c] = A.d.vref[3 * cp.c + c];
   }
 }
 
@@ -1187,6 +1189,42 @@ __device__ int initial_level(const double *a, const double *j, double eta_s,
 
 // ------------------------------------------------------------ O(N) kernels
 
+// Each cluster's reference velocity for the JRecV records: the
+// mass-weighted mean velocity of a strided sample of up to kWG of its
+// particles (one block per cluster, a fixed-order tree sum, so a cluster
+// gets the same value alone and in an ensemble); zero for a massless
+// sample.  Any value serves as long as records and kernels of one
+// evaluation share it; one near the bulk velocity keeps |v - v_ref| of
+// order the dispersion.  raw.x set: from a caller's arrays (one cluster:
+// its n_j particles).
+__global__ __launch_bounds__(kWG) void k_vref(Dev d, RawSrc raw) {
+  __shared__ double sh[4][kWG];
+  const int c = blockIdx.x;
+  const bool api = raw.x != nullptr;
+  const int64_t b = (api && d.C == 1) ? 0 : d.coff[c];
+  const int64_t nc = (api && d.C == 1 && raw.n_j > 0) ? raw.n_j : d.coff[c + 1] - b;
+  const int k = threadIdx.x;
+  double w[4] = {0.0, 0.0, 0.0, 0.0};
+  if (k < nc) {
+    const int64_t i = b + (nc <= kWG ? k : (int64_t)k * nc / kWG);
+    const double m = api ? raw.m[i] : d.m[i];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) w[q] = m * (api ? raw.v[3 * i + q] : d.v[q * d.n + i]);
+    w[3] = m;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) sh[q][k] = w[q];
+  __syncthreads();
+  for (int off = kWG / 2; off > 0; off >>= 1) {
+    if (k < off) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sh[q][k] += sh[q][k + off];
+    }
+    __syncthreads();
+  }
+  if (k < 3) d.vref[3 * c + k] = sh[3][0] > 0.0 ? sh[k][0] / sh[3][0] : 0.0;
+}
+
 __global__ void k_init_state(Dev d, const double *m, const double *x,
                              const double *v) {
   const int64_t n = d.n;
@@ -1486,10 +1524,10 @@ __global__ __launch_bounds__(kWG) void k_scatter(Dev d, Tuning tu, int plan_kind
       Rec *pred = reinterpret_cast<Rec *>(d.pred);
       const double mref = mode_mixed(RMODE) ? mass_ref(d.m[0]) : 1.0;
       const int64_t t1 = d.Tnext[0];
-      double vref[3] = {0.0, 0.0, 0.0};     // the cluster's first particle's
+      double vref[3] = {0.0, 0.0, 0.0};     // the cluster's reference
       if constexpr (mode_relv(RMODE)) {      // velocity (JRecV form)
-        double x0[3];
-        predict_state(d, 0, t1, x0, vref);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vref[c] = d.vref[c];
       }
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -2132,8 +2170,8 @@ __global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, in
   Rec *pred = reinterpret_cast<Rec *>(d.pred);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nj;
        i += (int64_t)gridDim.x * blockDim.x) {
-    // vref: the velocity of the first particle of the cluster's j range
-    // (JRecV form), taken as the force kernels take it
+    // vref: the cluster's reference velocity (JRecV form), taken as the
+    // force kernels take it
     double xp[3], vp[3], m, m0, vref[3] = {0.0, 0.0, 0.0};
     if (api) {
 #pragma unroll
@@ -2142,11 +2180,11 @@ __global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, in
         vp[c] = raw.v ? raw.v[3 * i + c] : 0.0;
       }
       m = raw.m[i];
-      const int64_t j0 = d.C == 1 ? 0 : d.coff[d.cid[i]];
-      m0 = raw.m[j0];
+      const int cl = d.C == 1 ? 0 : d.cid[i];
+      m0 = raw.m[d.C == 1 ? 0 : d.coff[cl]];
       if constexpr (mode_relv(MODE)) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) vref[c] = raw.v ? raw.v[3 * j0 + c] : 0.0;
+        for (int c = 0; c < 3; ++c) vref[c] = d.vref[3 * cl + c];
       }
     } else {
       const int c = d.cid[i];
@@ -2157,8 +2195,8 @@ __global__ __launch_bounds__(kWG) void k_records(Dev d, int kind, RawSrc raw, in
       m = d.m[i];
       m0 = d.m[d.coff[c]];
       if constexpr (mode_relv(MODE)) {
-        double x0[3];
-        predict_state(d, d.coff[c], t, x0, vref);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) vref[q] = d.vref[3 * c + q];
       }
     }
     Rec r;
@@ -3187,6 +3225,14 @@ hipError_t launch_refine_finalize(const Dev &d, const CorrectSpec *corr, hipStre
     hipLaunchKernelGGL((k_ref_final<true, true>), dim3(rb + cb), b, 0, s, d, rb, cs);
   else
     hipLaunchKernelGGL((k_ref_final<true, false>), dim3(rb + cb), b, 0, s, d, rb, cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_vref(const Dev &d, const RawSrc *raw, hipStream_t s) {
+  RawSrc r{};
+  if (raw) r = *raw;
+  if (raw && !raw->v) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_vref, dim3(d.C), dim3(kWG), 0, s, d, r);
   return hipGetLastError();
 }
 
