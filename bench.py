@@ -114,7 +114,7 @@ COUNTER_FILE = os.path.join(ROOT, "profiles", "counters_k_force_king1M.json")
 
 def measured_counters():
     """Counter-based FLOP rates and the observed clock of the force kernels
-    (mixed with FP64 differences, double-single mixed, FP64) from the
+    (mixed with FP64 position differences, double-single mixed, FP64) from the
     committed rocprofv3 SQ counter runs (every executed FP operation: FMA 2,
     add / mul / transcendental 1, x 64 lanes); None if the kernel source
     changed since."""
@@ -549,8 +549,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"King W0=7 N={n} equal-mass Henon units eps=1e-4, Hermite-4 "
                                f"block step with all particles active (level {LEVEL}), "
-                               "mixed-precision force path (FP64 coordinate and velocity "
-                               "differences, FP32 rsqrt, r^-3 and jerk products)",
+                               "mixed-precision force path (FP64 coordinate differences, "
+                               "FP32 velocity differences against an exact i-side, FP32 "
+                               "rsqrt, r^-3 and jerk products)",
                    "n": n, "interactions_per_step": n * n},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
@@ -559,7 +560,7 @@ def main():
                                         + " (rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this "
                                         "kernel source; not measured by this invocation)")
                      if measured_traffic() is not None else None,
-                     "kernel": "k_force_sb<mixed,K=1> (FP64 j records through the scalar cache)",
+                     "kernel": "k_force_sb<mixed,K=1> (j records with FP64 positions through the scalar cache)",
                      "kernel_ms": mixed["kernel_ms"],
                      "flops_per_launch": per_launch_flops},
         "fp64_reevaluation": {"ms_per_step": mixed["refine_ms_per_step"],

@@ -65,9 +65,13 @@ typedef enum nbody_status {
 typedef enum nbody_precision {
   /* plain FP64 arithmetic throughout */
   NBODY_FP64 = 0,
-  /* FP64 state, predictor and corrector; x_j - x_i and v_j - v_i are FP64
-     subtractions of the FP64 predicted positions and velocities, rounded to
-     FP32 for the FP32 r^2, r.v, rsqrt, r^-3 and jerk products (the hardware
+  /* FP64 state, predictor and corrector; x_j - x_i is an FP64 subtraction
+     of the FP64 predicted positions rounded to FP32; v_j - v_i is
+     (v_j - v_ref) rounded to FP32 minus the i-particle's v_i - v_ref held
+     as an exact (hi, lo) FP32 pair, v_ref being each cluster's reference
+     velocity (the mass-weighted mean velocity of a strided sample of up to
+     256 of its particles), so it carries only the rounding of v_j - v_ref;
+     then FP32 r^2, r.v, rsqrt, r^-3 and jerk products (the hardware
      rsqrt corrected by its FMA residual); FP32 sums of every 64 j folded
      into a compensated (TwoSum) FP32 hi/lo pair.  Pairs that dominate a
      particle's jerk are evaluated in FP64 instead (near pairs, see
