@@ -136,22 +136,24 @@ struct JRecDS {          // one j-particle for the double-single mode, 64 bytes:
   float vlx, vly, vlz, pad1;
 };
 
-// One j-particle for the mixed mode with FP64 position differences, 64
+// One particle for the mixed mode with FP64 position differences, 64
 // bytes: the FP64 position, the velocity relative to the cluster's
-// reference velocity rounded to FP32, the mass in units of the reference
-// mass.  The reference is the mass-weighted mean velocity of a strided
-// sample of the cluster (k_vref: refreshed between block-step launches for
-// the state, taken from a caller's arrays before an evaluation of them).  The FP32 velocity
-// difference (v_j - v_ref) - (v_i - v_ref), with the i side held as an exact
-// (hi, lo) pair, carries only the rounding of v_j - v_ref, which differs
-// from j to j (it does not add up coherently over the sum); the pairs whose
-// jerk term matters at that level are near pairs, taken in FP64.
+// reference velocity as a (hi, lo) FP32 pair, the mass in units of the
+// reference mass.  The reference is the mass-weighted mean velocity of a
+// strided sample of the cluster (k_vref: refreshed between block-step
+// launches for the state, taken from a caller's arrays before an evaluation
+// of them).  A j-particle enters with hi alone and an i-particle with both,
+// so the FP32 velocity difference hi_j - hi_i - lo_i carries only the
+// rounding of v_j - v_ref, which differs from j to j (it does not add up
+// coherently over the sum); the pairs whose jerk term matters at that level
+// are near pairs, taken in FP64.
 struct JRecV {
   double x, y, z;
-  float vx, vy, vz;
+  float vx, vy, vz;        // v - v_ref rounded to FP32 (hi)
   float mf;
   int32_t idx;
-  int32_t pad[5];
+  float vlx, vly, vlz;     // (v - v_ref) - hi rounded to FP32 (lo): read only
+  int32_t pad[2];          // when the record is an i-particle
 };
 static_assert(sizeof(JRecV) == 64, "one 64-byte record");
 
@@ -251,13 +253,16 @@ __device__ __forceinline__ void make_rec(const double *xp, const double *vp, dou
                                          int32_t idx, JRecV &r, double mref,
                                          const double *vref) {
   r.x = xp[0]; r.y = xp[1]; r.z = xp[2];
-  r.vx = (float)(vp[0] - vref[0]);
-  r.vy = (float)(vp[1] - vref[1]);
-  r.vz = (float)(vp[2] - vref[2]);
+  const double w[3] = {vp[0] - vref[0], vp[1] - vref[1], vp[2] - vref[2]};
+  r.vx = (float)w[0];
+  r.vy = (float)w[1];
+  r.vz = (float)w[2];
+  r.vlx = (float)(w[0] - (double)r.vx);
+  r.vly = (float)(w[1] - (double)r.vy);
+  r.vlz = (float)(w[2] - (double)r.vz);
   r.mf = (float)(m / mref);
   r.idx = idx;
-#pragma unroll
-  for (int q = 0; q < 5; ++q) r.pad[q] = 0;
+  r.pad[0] = r.pad[1] = 0;
 }
 
 // ------------------------------------------------------------ pair terms
@@ -818,24 +823,10 @@ __device__ __forceinline__ void ref_velocity(const ForceArgs &A, const ClusterPl
   }
 }
 
-// An i-particle from the evaluation's records.  The JRecV form takes the
-// position from the record and the velocity from the FP64 source (the
-// record holds it to FP32 only).
-template <int MODE>
-__device__ __forceinline__ void i_from_rec(const ForceArgs &A, const ClusterPlan &cp, bool raw,
-                                           const typename Traits<MODE>::Rec &r, int i,
-                                           const double *vref, typename Traits<MODE>::Ist &s) {
-  if constexpr (mode_relv(MODE)) {
-    const double xr[3] = {r.x, r.y, r.z};
-    double v[3] = {0.0, 0.0, 0.0};
-    if constexpr (!mode_acc_only(MODE)) {
-      double xs[3], ms;
-      near_state(A, cp, i, raw, xs, v, ms);
-    }
-    make_i(xr, v, s, vref);
-  } else {
-    rec_to_i(r, s);
-  }
+__device__ __forceinline__ void rec_to_i(const JRecV &r, IV &s) {
+  s.x[0] = r.x; s.x[1] = r.y; s.x[2] = r.z;
+  s.vh[0] = r.vx; s.vh[1] = r.vy; s.vh[2] = r.vz;
+  s.vl[0] = r.vlx; s.vl[1] = r.vly; s.vl[2] = r.vlz;
 }
 
 // ------------------------------------------------------------ force kernel
@@ -970,7 +961,7 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
       if (!ok[k]) {
         iidx[k] = -1;
       } else if (use_pred) {
-        i_from_rec<MODE>(A, cp, SRC == kSrcRaw, pred[iidx[k]], iidx[k], vref, I[k]);
+        rec_to_i(pred[iidx[k]], I[k]);
         continue;
       } else if constexpr (SRC == kSrcState) {
         predict_state(d, iidx[k], cp.t_pred, xp, vp);
@@ -2242,8 +2233,8 @@ __device__ __forceinline__ JRecV load_rec(ScalarPtr<JRecV> p) {
   r.x = p->x; r.y = p->y; r.z = p->z;
   r.vx = p->vx; r.vy = p->vy; r.vz = p->vz;
   r.mf = p->mf; r.idx = p->idx;
-#pragma unroll
-  for (int q = 0; q < 5; ++q) r.pad[q] = 0;
+  r.vlx = p->vlx; r.vly = p->vly; r.vlz = p->vlz;   // unread for j-particles
+  r.pad[0] = r.pad[1] = 0;
   return r;
 }
 
@@ -2293,7 +2284,7 @@ __device__ __forceinline__ void sb_run(
   using Rec = typename Traits<MODE>::Rec;
   int jj = 0;
   if constexpr (mode_relv(MODE)) {
-    // JRecV (11 of its 16 dwords live): each group's first record is loaded
+    // JRecV (11 of its 16 dwords read for a j-particle): each group's first record is loaded
     // one group early, so the group starts without waiting on the scalar
     // cache; the prefetch address stays inside the chunk
     Rec first = load_rec(rec + 0);
@@ -2403,7 +2394,7 @@ __attribute__((amdgpu_waves_per_eu(SbOcc<MODE, K>::waves))) void k_force_sb(Forc
                   ? (float)(near_threshold(A, cp.act_off + slot, iidx[k]) / mref)
                   : INFINITY;
       if (ok[k]) {
-        i_from_rec<MODE>(A, cp, raw, pred[iidx[k]], iidx[k], vref, I[k]);
+        rec_to_i(pred[iidx[k]], I[k]);
       } else {
         iidx[k] = -1;
         const double z[3] = {0.0, 0.0, 0.0};
