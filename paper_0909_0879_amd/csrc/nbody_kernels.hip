@@ -2273,6 +2273,22 @@ __device__ __forceinline__ void load4(ScalarPtr<JRec64> p, JRec64 (&r)[4]) {
   }
 }
 
+__device__ __forceinline__ void load4(ScalarPtr<JRecV> p, JRecV (&r)[4]) {
+  const ScalarPtr<f32x16> b = (ScalarPtr<f32x16>)p;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const f32x16 a = b[u];
+    r[u].x = __builtin_bit_cast(double, __builtin_shufflevector(a, a, 0, 1));
+    r[u].y = __builtin_bit_cast(double, __builtin_shufflevector(a, a, 2, 3));
+    r[u].z = __builtin_bit_cast(double, __builtin_shufflevector(a, a, 4, 5));
+    r[u].vx = a[6]; r[u].vy = a[7]; r[u].vz = a[8];
+    r[u].mf = a[9];
+    r[u].idx = __float_as_int(a[10]);
+    r[u].vlx = a[11]; r[u].vly = a[12]; r[u].vlz = a[13];
+    r[u].pad[0] = r[u].pad[1] = 0;
+  }
+}
+
 // A chunk of records against the lane's K i-particles, four records per
 // scalar load group; near pairs go to the lane's queue.
 template <int MODE, int K, bool MASK, bool SELF>
@@ -2283,7 +2299,7 @@ __device__ __forceinline__ void sb_run(
     int (&dom)[K], Bnd (&ba)[K], int (&ncnt)[K], NearQueue<MODE, K> &nq) {
   using Rec = typename Traits<MODE>::Rec;
   int jj = 0;
-  if constexpr (mode_relv(MODE)) {
+  if constexpr (mode_relv(MODE) && !mode_acc_only(MODE)) {
     // JRecV (11 of its 16 dwords read for a j-particle): each group's first record is loaded
     // one group early, so the group starts without waiting on the scalar
     // cache; the prefetch address stays inside the chunk
