@@ -1550,9 +1550,10 @@ __global__ __launch_bounds__(kWG) void k_scatter(Dev d, Tuning tu, int plan_kind
   }
 }
 
-// Exclusive scan of one int64 per thread over a 1024-thread workgroup
-// (wave shuffles, then the 16 wave totals); returns the prefix and sets
-// *total.  sh: 16 int64 of LDS.
+// Exclusive scan of one int64 per thread over a workgroup of NW waves
+// (wave shuffles, then the NW wave totals); returns the prefix and sets
+// *total.  sh: NW int64 of LDS.
+template <int NW>
 __device__ __forceinline__ int64_t block_exscan64(int64_t v, int64_t *sh, int64_t *total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int64_t incl = v;
@@ -1565,7 +1566,7 @@ __device__ __forceinline__ int64_t block_exscan64(int64_t v, int64_t *sh, int64_
   __syncthreads();
   int64_t before = 0, all = 0;
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
+  for (int u = 0; u < NW; ++u) {
     const int64_t t = sh[u];
     before += (u < w) ? t : 0;
     all += t;
@@ -1691,15 +1692,15 @@ __device__ __forceinline__ int ref_list_lower(const Dev &d, int cnt, int c, bool
   return lo;
 }
 
-// Launch plan for every cluster, in one 1024-thread workgroup; thread t owns
-// clusters t, t + 1024, ..., at most QN of them (C <= 1024 QN), kept in
+// Launch plan for every cluster, in one workgroup of BS threads; thread t
+// owns clusters t, t + BS, ..., at most QN of them (C <= BS QN), kept in
 // registers.
-template <int QN>
-__global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
+template <int QN, int BS>
+__global__ __launch_bounds__(BS) void k_plan(Dev d, Tuning tu, int kind,
                                                 int64_t api_nj, int allow_small) {
   const bool refine = (kind == kPlanRefine || kind == kPlanApiRefine);
-  __shared__ uint64_t key[QN * 1024];           // LPT order key per cluster
-  __shared__ int32_t items_by_rank[QN * 1024];
+  __shared__ uint64_t key[QN * BS];           // LPT order key per cluster
+  __shared__ int32_t items_by_rank[QN * BS];
   __shared__ int64_t sh[16];
   const int C = d.C;
   const int K = tu.K;
@@ -1709,7 +1710,7 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
   ClusterPlan cp[QN];
 #pragma unroll
   for (int q = 0; q < QN; ++q) {
-    const int c = tid + 1024 * q;
+    const int c = tid + BS * q;
     ClusterPlan &p = cp[q];
     if (c >= C) {
       p = ClusterPlan{};
@@ -1751,14 +1752,14 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
   int64_t carry = 0, wcarry = 0;
 #pragma unroll
   for (int q = 0; q < QN; ++q) {
-    if (1024 * q >= C) break;                       // uniform
+    if (BS * q >= C) break;                       // uniform
     int64_t tot;
     const int64_t r = (int64_t)cp[q].S * cp[q].na;
-    cp[q].row_off = carry + block_exscan64(r, sh, &tot);
+    cp[q].row_off = carry + block_exscan64<BS / 64>(r, sh, &tot);
     carry += tot;
-    const int c = tid + 1024 * q;
+    const int c = tid + BS * q;
     const int64_t wv = (c < C) ? sum_waves(cp[q]) : 0;
-    const int64_t wpre = wcarry + block_exscan64(wv, sh, &tot);
+    const int64_t wpre = wcarry + block_exscan64<BS / 64>(wv, sh, &tot);
     if (c < C) d.sum_prefix[c] = (int32_t)wpre;
     wcarry += tot;
   }
@@ -1770,7 +1771,7 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
   for (int q = 0; q < QN; ++q) rank[q] = 0;
   uint64_t mine[QN];
 #pragma unroll
-  for (int q = 0; q < QN; ++q) mine[q] = (tid + 1024 * q < C) ? key[tid + 1024 * q] : ~0ull;
+  for (int q = 0; q < QN; ++q) mine[q] = (tid + BS * q < C) ? key[tid + BS * q] : ~0ull;
   int u = 0;
   for (; u + 4 <= C; u += 4) {
     const uint64_t k0 = key[u], k1 = key[u + 1], k2 = key[u + 2], k3 = key[u + 3];
@@ -1785,7 +1786,7 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
   }
 #pragma unroll
   for (int q = 0; q < QN; ++q) {
-    const int c = tid + 1024 * q;
+    const int c = tid + BS * q;
     if (c >= C) continue;
     d.plan_c[c] = cp[q];
     d.plan_lpt[rank[q]] = cp[q];
@@ -1797,17 +1798,17 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
   int64_t big = 0;
 #pragma unroll
   for (int q = 0; q < QN; ++q) {
-    if (1024 * q >= C) break;
-    const int r = tid + 1024 * q;
+    if (BS * q >= C) break;
+    const int r = tid + BS * q;
     const int64_t it = (r < C) ? items_by_rank[r] : 0;
     int64_t tot;
-    const int64_t pre = block_exscan64(it, sh, &tot);
+    const int64_t pre = block_exscan64<BS / 64>(it, sh, &tot);
     if (r < C) d.item_prefix[r] = (int32_t)(carry + pre);
     carry += tot;
   }
 #pragma unroll
   for (int q = 0; q < QN; ++q)
-    if (tid + 1024 * q < C && !cp[q].small) big += cp[q].items;
+    if (tid + BS * q < C && !cp[q].small) big += cp[q].items;
   __shared__ int64_t big_sh;
   if (tid == 0) big_sh = 0;
   __syncthreads();
@@ -1820,7 +1821,7 @@ __global__ __launch_bounds__(1024) void k_plan(Dev d, Tuning tu, int kind,
     d.work[2] = (int32_t)big_sh;   // items [0, big) are main, [big, total) small
   }
   if (kind == kPlanStep) {
-    for (int c = tid; c < C; c += 1024) d.T[c] = d.Tnext[c];
+    for (int c = tid; c < C; c += BS) d.T[c] = d.Tnext[c];
     // block totals (deterministic: integer atomics)
     if (my_inter) atomicAdd((unsigned long long *)&d.ctr[kCtrInter],
                             (unsigned long long)my_inter);
@@ -2975,12 +2976,17 @@ hipError_t launch_compact(const Dev &d, const Tuning &t, bool allow_small, int r
 
 hipError_t launch_plan(const Dev &d, const Tuning &t, int kind, int64_t api_nj,
                        bool allow_small, hipStream_t s) {
-  if (d.C <= 1024)
-    hipLaunchKernelGGL(k_plan<1>, dim3(1), dim3(1024), 0, s, d, t, kind, api_nj,
+  // the smallest workgroup that gives each cluster its own thread (fewer
+  // waves to synchronise in the plan's scans and barriers)
+  if (d.C <= kWG)
+    hipLaunchKernelGGL((k_plan<1, kWG>), dim3(1), dim3(kWG), 0, s, d, t, kind, api_nj,
+                       allow_small ? 1 : 0);
+  else if (d.C <= 1024)
+    hipLaunchKernelGGL((k_plan<1, 1024>), dim3(1), dim3(1024), 0, s, d, t, kind, api_nj,
                        allow_small ? 1 : 0);
   else
-    hipLaunchKernelGGL(k_plan<kMaxClusters / 1024>, dim3(1), dim3(1024), 0, s, d, t, kind,
-                       api_nj, allow_small ? 1 : 0);
+    hipLaunchKernelGGL((k_plan<kMaxClusters / 1024, 1024>), dim3(1), dim3(1024), 0, s, d, t,
+                       kind, api_nj, allow_small ? 1 : 0);
   return hipGetLastError();
 }
 
