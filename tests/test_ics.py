@@ -58,6 +58,26 @@ def test_king_profile_self_consistent():
     assert p["W"][0] == 7.0 and p["W"][-1] == 0.0
 
 
+def test_king_low_w0_limit_is_the_n_5_2_polytrope():
+    # For small W the King density behaves as 8 W^(5/2) / (15 sqrt(pi)) times
+    # (1 + 2W/7 + O(W^2)) (series of the lowered isothermal), so as W0 -> 0
+    # the profile becomes the Lane-Emden n = 5/2 polytrope: with
+    # r = xi sqrt(W0) / 3 the tidal radius is the polytrope's first zero
+    # xi_1 = 5.35528 and M_t / (9 a^3) is its mass factor
+    # -xi_1^2 theta'(xi_1) = 2.18720 (standard polytrope tables).
+    c = 8.0 / (15.0 * math.sqrt(math.pi))
+    for w in (1e-2, 1e-3):
+        ratio = ics._king_rho(w) / (c * w ** 2.5)
+        assert abs(ratio - (1.0 + 2.0 * w / 7.0)) < 2 * w * w
+    w0 = 1e-4
+    p = ics.king_profile(w0)
+    a = math.sqrt(w0) / 3.0
+    assert abs(p["r_t"] / a / 5.35528 - 1.0) < 1e-4
+    assert abs(p["M_t"] / (9.0 * a ** 3) / 2.18720 - 1.0) < 1e-4
+    # potential energy of an n-polytrope: -3/(5-n) G M^2 / R = -(6/5) M^2/R
+    assert abs(p["pot"] / (-1.2 * p["M_t"] ** 2 / p["r_t"]) - 1.0) < 1e-3
+
+
 def test_king_sample_henon_units():
     m, x, v = ics.king(20000, 7.0, 4)
     K = 0.5 * (m * (v * v).sum(1)).sum()
