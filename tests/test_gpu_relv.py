@@ -45,3 +45,33 @@ def test_reference_velocity_robust(name):
     st = g.get_state()
     check_parity(to_np(st["a"]), to_np(st["j"]), a_ref, j_ref, True, f"{name} initial state")
     g.close()
+
+
+def test_reference_velocity_per_cluster():
+    # Clusters of one ensemble moving at different bulk velocities, each
+    # hundreds of times its dispersion: every cluster's differences are taken
+    # against its own reference, so all stay within the gates.  No block step
+    # is routed to the FP64 kernel, so the mixed kernels evaluate every
+    # cluster.
+    require_gpu()
+    sizes = [700, 2048, 1500]
+    bulk = np.array([[300.0, -200.0, 100.0], [-250.0, 150.0, 0.0], [0.0, 0.0, 400.0]])
+    eps = [1e-3, 2e-3, 1e-3]
+    m, x, v, off = ics.ensemble(3, sizes=sizes, seed=7100)
+    v = v.copy()
+    for c in range(3):
+        v[off[c]:off[c + 1]] += bulk[c]
+    print("relv per-cluster ensemble", sizes, flush=True)
+    g = binding.NBody(m, x, v, eps=eps, cluster_offsets=off, precision=binding.MIXED,
+                      tuning={"small_log2": -1})
+    acc, jerk = g.forces(x, v, m)
+    g.sync()
+    acc, jerk = to_np(acc), to_np(jerk)
+    st = g.get_state()
+    sa, sj = to_np(st["a"]), to_np(st["j"])
+    for c in range(3):
+        sl = slice(off[c], off[c + 1])
+        a_ref, j_ref = oracle.forces(x[sl], v[sl], m[sl], eps[c])
+        check_parity(acc[sl], jerk[sl], a_ref, j_ref, True, f"cluster {c} forces")
+        check_parity(sa[sl], sj[sl], a_ref, j_ref, True, f"cluster {c} initial state")
+    g.close()
