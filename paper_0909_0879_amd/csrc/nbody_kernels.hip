@@ -11,9 +11,10 @@
 // criterion.
 //
 // Kernel layout on CDNA4:
-//  * the force kernels are persistent: each 256-thread workgroup pulls work
-//    items (cluster, i-tile, j-split) from an atomic counter; items are
-//    ordered largest cost first (k_plan), so uneven clusters balance;
+//  * the force kernels are persistent: each 256-thread workgroup takes the
+//    work item (cluster, i-tile, j-split) of its own index, then pulls further
+//    ones from an atomic counter; items are ordered largest cost first
+//    (k_plan), so uneven clusters balance;
 //  * i-particles sit in registers, K per thread slot; j-particles reach the
 //    ALUs either through a 256-record LDS tile (k_force) — predicted while
 //    being copied from the SoA state for small active sets, or copied from
@@ -912,11 +913,18 @@ __attribute__((amdgpu_waves_per_eu(ForceOcc<MODE, SRC, K>::waves))) void k_force
   const int32_t *ipre = lds_pre ? s_ipre : d.item_prefix;
   const bool use_pred = REC || pred_flag == 1;
   const Rec *pred = reinterpret_cast<const Rec *>(d.pred);
-  for (;;) {
-    if (tid == 0) s_g = item_base + atomicAdd(counter, 1);
-    __syncthreads();
-    const int g = s_g;
-    __syncthreads();
+  // each workgroup's first item is item_base + its index; later ones come
+  // from the shared counter, past those first gridDim.x (a launch with fewer
+  // items than workgroups then touches the counter only once per busy
+  // workgroup, instead of queueing the whole grid on it)
+  for (int it = 0;; ++it) {
+    int g = item_base + (int)blockIdx.x;
+    if (it > 0) {
+      if (tid == 0) s_g = item_base + (int)gridDim.x + atomicAdd(counter, 1);
+      __syncthreads();
+      g = s_g;
+      __syncthreads();
+    }
     if (g >= n_items) break;
     // item_prefix[lo] <= g < item_prefix[lo + 1]
     const int lo = (d.C > 1) ? prefix_find(ipre, d.C, g) : 0;
@@ -2372,11 +2380,15 @@ __attribute__((amdgpu_waves_per_eu(SbOcc<MODE, K>::waves))) void k_force_sb(Forc
   const bool lds_pre = prefix_in_lds(d.C);
   if (lds_pre) prefix_to_lds(d.item_prefix, d.C, s_ipre);
   const int32_t *ipre = lds_pre ? s_ipre : d.item_prefix;
-  for (;;) {
-    if (tid == 0) s_g = atomicAdd(d.work, 1);
-    __syncthreads();
-    const int g = __builtin_amdgcn_readfirstlane(s_g);
-    __syncthreads();
+  // first item by workgroup index, later ones from the counter, as in k_force
+  for (int it = 0;; ++it) {
+    int g = (int)blockIdx.x;
+    if (it > 0) {
+      if (tid == 0) s_g = (int)gridDim.x + atomicAdd(d.work, 1);
+      __syncthreads();
+      g = __builtin_amdgcn_readfirstlane(s_g);
+      __syncthreads();
+    }
     if (g >= n_items) break;
     // item_prefix[lo] <= g < item_prefix[lo + 1] (uniform: scalar from here)
     const int lo = (d.C > 1) ? __builtin_amdgcn_readfirstlane(prefix_find(ipre, d.C, g)) : 0;
